@@ -1,0 +1,209 @@
+/*
+ * survscan -- Cox and Fine-Gray coordinate gradient / Hessian by fused
+ * single-pass scans, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Yang, Schuemie, Ji & Suchard, "Massive Parallelization of
+ * Massive Sample-size Survival Analysis" (arXiv 2204.08183).  With the
+ * subjects arranged by decreasing observed time the risk-set sums of the
+ * Cox log partial likelihood become prefix sums and the Fine-Gray ones a
+ * prefix plus a weighted suffix sum (Sec. 2.7, eqs. cox_g, cox_h, fg_g,
+ * fg_h); one coordinate's g' and g'' are a scan, an element-wise transform
+ * and a reduction, fused into one pass over the data (Sec. 2.7, Fig. 3),
+ * inside cyclic coordinate descent (Sec. 2.4, Fig. 4).
+ *
+ * Conventions for every entry point
+ *  - All array pointers are DEVICE pointers (hipMalloc'd or torch CUDA
+ *    tensors) unless the comment says [host].  The caller owns every buffer;
+ *    the library never allocates or frees device memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call is asynchronous on that stream, launches kernels only (no
+ *    host synchronisation, no memset nodes) and may be captured in a
+ *    hipGraph.  Outputs are valid once the stream has synchronised.
+ *  - Arguments are checked on the host before any launch; an invalid call
+ *    returns a negative status and launches nothing.  No C++ exception
+ *    crosses this interface.  NaN or Inf in the data propagate into the
+ *    outputs (they are not checked on the hot path).
+ *  - "Sorted order" is the order of decreasing observed time produced by
+ *    ss_prepare: position k holds subject perm[k]; equal times keep
+ *    increasing original index.
+ *  - Sizes: 1 <= n < 2^31, 1 <= p < 2^31; each column has at most n
+ *    non-zeros; the total number of non-zeros nnz may exceed 2^31.
+ *  - A workspace `ws` belongs to one stream at a time: two calls that use
+ *    the same workspace must not run concurrently.
+ */
+#ifndef SURVSCAN_H
+#define SURVSCAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status */
+#define SS_OK            0
+#define SS_EINVAL       (-1)   /* null pointer, bad size, index out of range */
+#define SS_EWORKSPACE   (-2)   /* workspace too small or misaligned          */
+#define SS_EUNSUPPORTED (-3)   /* unknown model / penalty                    */
+#define SS_EDEVICE      (-4)   /* a HIP runtime call failed                  */
+
+/* ------------------------------------------------------------ enums */
+#define SS_COX        0        /* Sec. 2.1: events are status != 0          */
+#define SS_FINE_GRAY  1        /* Sec. 2.2: events are status == 1,
+                                  competing events status == 2             */
+
+#define SS_PENALTY_NONE 0
+#define SS_PENALTY_L1   1      /* pi = -gamma |beta_j|        (Sec. 2.3)   */
+#define SS_PENALTY_L2   2      /* pi = -beta_j^2 / (2 tau)    (Sec. 2.3)   */
+
+/* Granularity (in sorted positions) of the per-column chunk index built by
+ * ss_prepare; tiles of the fused kernels are whole multiples of it. */
+#define SS_CHUNK 1024
+
+/* Human-readable text for a status code (static storage, never NULL).  For
+ * SS_EDEVICE it names the last HIP error seen by the library. */
+const char *ss_status_string(int32_t code);
+
+/* Number of chunks ceil(n / SS_CHUNK); the chunk index of ss_prepare holds
+ * p * (ss_chunk_count(n) + 1) int32 entries. */
+int64_t ss_chunk_count(int64_t n);
+
+/* ------------------------------------------------------------ a0: prepare
+ * One-time preparation of a data set (Sec. 2.7: arrangement by decreasing
+ * observed time; Sec. 2.2: Kaplan-Meier censoring weights).
+ *
+ * Inputs (device, original subject order):
+ *   y[n]        observed times Y_i = min(T_i, C_i); finite, not NaN.
+ *   status[n]   0 censored, 1 event (Fine-Gray: primary event), 2 competing
+ *               event (Fine-Gray only; the Cox model counts it as an event).
+ *   col_ptr[p+1] int64 CSC column pointers (col_ptr[0] = 0, non-decreasing,
+ *               col_ptr[p] = nnz), rows[nnz] int32 subject indices in [0, n)
+ *               with no duplicate inside a column (any order),
+ *   vals[nnz]   covariate values, or NULL for a 0/1 indicator design.
+ * Outputs (device, caller-allocated):
+ *   perm[n]      int32, perm[k] = subject at sorted position k.
+ *   inv_perm[n]  int32, inverse of perm.
+ *   d8[n]        uint8, at the last position of each tie run: number of
+ *                events in the run, saturated at 255; 0 elsewhere.
+ *   d32[n]       int32, the same counts unsaturated (read only where d8 is
+ *                255).
+ *   c[p]         c_j = sum over events of x_ij (Sec. 2.7, the constant term
+ *                delta' X_j of g'; Fine-Gray: over status == 1).
+ *   rows_sorted[nnz] int32, the design re-labelled to sorted positions and
+ *                ascending inside each column (same col_ptr).
+ *   vals_sorted[nnz] the values in that order (ignored when vals == NULL).
+ *   chunk_ptr[p*(ss_chunk_count(n)+1)] int32: entry j*(C+1)+t is the offset
+ *                inside column j of its first non-zero at sorted position
+ *                >= t*SS_CHUNK (C = ss_chunk_count(n)).
+ *   w_comp[n]    Fine-Gray only (else may be NULL): I(status=2)/G(y_k), the
+ *                censoring weight of a competing event at sorted position k.
+ *   g_end[n]     Fine-Gray only (else may be NULL): G(y_k), the Kaplan-Meier
+ *                estimate of Pr(C > y_k), right-continuous.
+ * ws/ws_bytes   device scratch of at least ss_prepare_workspace_bytes().
+ * The integer outputs are bit-exact and deterministic. */
+size_t ss_prepare_workspace_bytes(int64_t n, int64_t p, int64_t nnz);
+int32_t ss_prepare(int32_t model, int64_t n, int64_t p, int64_t nnz,
+                   const double *y, const int8_t *status,
+                   const int64_t *col_ptr, const int32_t *rows,
+                   const double *vals,
+                   int32_t *perm, int32_t *inv_perm, uint8_t *d8,
+                   int32_t *d32, double *c, int32_t *rows_sorted,
+                   double *vals_sorted, int32_t *chunk_ptr,
+                   double *w_comp, double *g_end,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ workspace
+ * Scratch of the fused kernels: tile look-back states, per-tile partial
+ * sums and the launch counters.  It must be cleared once with
+ * ss_workspace_init before its first use; afterwards every call leaves it
+ * ready for the next one (no per-call clearing). */
+size_t ss_workspace_bytes(int32_t model, int64_t n);
+int32_t ss_workspace_init(void *ws, size_t ws_bytes, void *stream);
+
+/* Device status word kept in the workspace: 0 while every bounded wait of
+ * the fused kernels has finished in time, non-zero once one gave up (the
+ * results of that call are then not valid).  Copies it to *flag [host]
+ * after synchronising `stream`. */
+int32_t ss_workspace_error(const void *ws, int32_t *flag, void *stream);
+
+/* ------------------------------------------------------------ a2 / a4
+ * Gradient and Hessian of the log partial likelihood (Cox, Sec. 2.7 eqs.
+ * cox_g/cox_h) or log pseudo-likelihood (Fine-Gray, eqs. fg_g/fg_h) along
+ * coordinate j, for the current e = exp(X beta):
+ *   g'  = c_j - sum_k d_k G_k,    g'' = -sum_k d_k (H_k - G_k^2),
+ *   G_k = S1_k / S0_k,  H_k = S2_k / S0_k  at the last position k of every
+ *   tie run (ties as the risk set y_r >= Y_i is written), where
+ *   Cox:        S_m,k = sum_{r <= k} e_r x_rj^m
+ *   Fine-Gray:  S_m,k = sum_{r <= k} e_r x_rj^m
+ *                       + g_end_k * sum_{r after k's run} e_r x_rj^m w_comp_r
+ * One fused pass: tuple scan with decoupled look-back, transform,
+ * reduction; the last tile finishes the reduction (Fig. 3).
+ * Inputs: e[n] in sorted order; the ss_prepare outputs; j in [0, p).
+ * Output out[3] (device): g', g'', and sum_k d_k log S0_k. */
+int32_t ss_grad_hess(int32_t model, int64_t n, int64_t p, int64_t j,
+                     const double *e, const uint8_t *d8, const int32_t *d32,
+                     const double *w_comp, const double *g_end,
+                     const int64_t *col_ptr, const int32_t *rows_sorted,
+                     const double *vals_sorted, const int32_t *chunk_ptr,
+                     const double *c, double *out,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* Log partial (pseudo-) likelihood l = beta' c - sum_k d_k log S0_k
+ * (Sec. 2.7, the prefix-sum form of eq. cox_l; eq. fg_l for Fine-Gray),
+ * with beta[p] on the device.  Output out[1] (device). */
+int32_t ss_loglik(int32_t model, int64_t n, int64_t p,
+                  const double *e, const uint8_t *d8, const int32_t *d32,
+                  const double *w_comp, const double *g_end,
+                  const double *beta, const double *c, double *out,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ a3 (+ a1)
+ * One coordinate update (Secs. 2.3-2.4): from g12[0..1] = (g', g'') of the
+ * unpenalised likelihood (device, e.g. the out of ss_grad_hess), take the
+ * penalised Newton step (l1 directional rule at beta_j = 0, an l1 step that
+ * would cross zero stops at zero), clip it to the trust region,
+ *   beta_j += sgn(s) min(|s|, delta_j),  delta_j <- max(2|s|, delta_j/2),
+ * store the applied step in *step, and if it is non-zero update
+ * eta_k += x_kj * step and e_k = exp(eta_k) at the non-zeros of column j
+ * (Sec. 2.7 step (1); Fig. 4's conditional kernel).  lambda is gamma (l1)
+ * or tau (l2), ignored for no penalty.  A penalised second derivative that
+ * is not strictly negative gives a zero step. */
+int32_t ss_ccd_update(int32_t penalty, double lambda, int64_t n, int64_t p,
+                      int64_t j, const double *g12, double *beta,
+                      double *delta, double *step, double *eta, double *e,
+                      const int64_t *col_ptr, const int32_t *rows_sorted,
+                      const double *vals_sorted, void *stream);
+
+/* ------------------------------------------------------------ fused sweep
+ * Cyclic coordinate descent over coordinates j_begin..j_end-1 (Fig. 4)
+ * without any host round trip: per coordinate one fused launch (Fine-Gray:
+ * two) that applies the previous coordinate's update to eta and e (step
+ * (1)), computes g', g'' (steps (2)-(4)) and, in its last tile, the update
+ * of beta_j, delta_j and steps[j] (a3).  The last coordinate's update of
+ * eta/e is applied before returning, so eta, e, beta and delta are
+ * consistent afterwards.  g12_out[3*p] (optional, may be NULL) receives
+ * (g', g'', sum d log S0) of every visited coordinate. */
+int32_t ss_ccd_sweep(int32_t model, int32_t penalty, double lambda,
+                     int64_t n, int64_t p, int64_t j_begin, int64_t j_end,
+                     double *eta, double *e, const uint8_t *d8,
+                     const int32_t *d32, const double *w_comp,
+                     const double *g_end, const int64_t *col_ptr,
+                     const int32_t *rows_sorted, const double *vals_sorted,
+                     const int32_t *chunk_ptr, const double *c,
+                     double *beta, double *delta, double *steps,
+                     double *g12_out, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* e_k = exp(eta_k) for k < n (sorted order; used to initialise e). */
+int32_t ss_exp(int64_t n, const double *eta, double *e, void *stream);
+
+/* dst[k] = src[perm[k]] for k < n: brings a per-subject vector into sorted
+ * order (dst and src must not overlap). */
+int32_t ss_gather(int64_t n, const int32_t *perm, const double *src,
+                  double *dst, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SURVSCAN_H */

@@ -51,12 +51,16 @@ static double cval(const csum *a) { return a->s + a->c; }
  * out[0] = g', out[1] = g'', out[2] = log partial likelihood l,
  * out[3] = sum_k d_k G_k, out[4] = sum_k d_k (H_k - G_k^2),
  * out[5] = sum_k d_k log S0_k.
+ * out[6..9] = sum_k d_k |G_k|, sum_k d_k (|H_k| + G_k^2),
+ * sum_k d_k |log S0_k| and sum over events of |x_kj|: the magnitudes that
+ * scale the parity tolerances (g' and l cancel near an optimum).
  */
 int oracle_cox_scan(int64_t n, const double *y, const int64_t *ev,
                     const double *eta, const double *x, double *out)
 {
     csum S0 = {0, 0}, S1 = {0, 0}, S2 = {0, 0};
     csum A = {0, 0}, B = {0, 0}, L = {0, 0}, C = {0, 0}, E = {0, 0};
+    csum SA = {0, 0}, SB = {0, 0}, SL = {0, 0}, SX = {0, 0};
     int64_t d = 0;
     for (int64_t k = 0; k < n; ++k) {
         double e = exp(eta[k]);              /* step (1) */
@@ -66,6 +70,7 @@ int oracle_cox_scan(int64_t n, const double *y, const int64_t *ev,
         if (ev[k]) {
             cadd(&C, x[k]);                  /* delta' X_j */
             cadd(&E, eta[k]);                /* delta' X beta */
+            cadd(&SX, fabs(x[k]));
             d += 1;
         }
         if (k == n - 1 || y[k] != y[k + 1]) {   /* last position of a run */
@@ -75,6 +80,9 @@ int oracle_cox_scan(int64_t n, const double *y, const int64_t *ev,
                 cadd(&A, (double)d * G);             /* step (4) */
                 cadd(&B, (double)d * (H - G * G));
                 cadd(&L, (double)d * log(s0));
+                cadd(&SA, (double)d * fabs(G));
+                cadd(&SB, (double)d * (fabs(H) + G * G));
+                cadd(&SL, (double)d * fabs(log(s0)));
             }
             d = 0;
         }
@@ -85,6 +93,10 @@ int oracle_cox_scan(int64_t n, const double *y, const int64_t *ev,
     out[3] = cval(&A);
     out[4] = cval(&B);
     out[5] = cval(&L);
+    out[6] = cval(&SA);
+    out[7] = cval(&SB);
+    out[8] = cval(&SL);
+    out[9] = cval(&SX);
     return 0;
 }
 
@@ -125,6 +137,7 @@ int oracle_fg_scan(int64_t n, const double *y, const int64_t *status,
     /* forward pass */
     csum S0 = {0, 0}, S1 = {0, 0}, S2 = {0, 0};
     csum A = {0, 0}, B = {0, 0}, L = {0, 0}, C = {0, 0}, E = {0, 0};
+    csum SA = {0, 0}, SB = {0, 0}, SL = {0, 0}, SX = {0, 0};
     int64_t d = 0;
     for (int64_t k = 0; k < n; ++k) {
         double e = exp(eta[k]);
@@ -134,6 +147,7 @@ int oracle_fg_scan(int64_t n, const double *y, const int64_t *status,
         if (status[k] == 1) {
             cadd(&C, x[k]);
             cadd(&E, eta[k]);
+            cadd(&SX, fabs(x[k]));
             d += 1;
         }
         if (k == n - 1 || y[k] != y[k + 1]) {
@@ -146,6 +160,9 @@ int oracle_fg_scan(int64_t n, const double *y, const int64_t *status,
                 cadd(&A, (double)d * G);
                 cadd(&B, (double)d * (H - G * G));
                 cadd(&L, (double)d * log(s0));
+                cadd(&SA, (double)d * fabs(G));
+                cadd(&SB, (double)d * (fabs(H) + G * G));
+                cadd(&SL, (double)d * fabs(log(s0)));
             }
             d = 0;
         }
@@ -156,6 +173,10 @@ int oracle_fg_scan(int64_t n, const double *y, const int64_t *status,
     out[3] = cval(&A);
     out[4] = cval(&B);
     out[5] = cval(&L);
+    out[6] = cval(&SA);
+    out[7] = cval(&SB);
+    out[8] = cval(&SL);
+    out[9] = cval(&SX);
     free(q0); free(q1); free(q2);
     return 0;
 }

@@ -80,7 +80,7 @@ class Prepared:
         lib = _load()
         eta_s = np.ascontiguousarray(eta_s, dtype=np.float64)
         x_s = np.ascontiguousarray(x_s, dtype=np.float64)
-        out = np.zeros(6, dtype=np.float64)
+        out = np.zeros(10, dtype=np.float64)
         if self.model == "cox":
             rc = lib.oracle_cox_scan(self.n, _dp(self.y), _ip(self.ev),
                                      _dp(eta_s), _dp(x_s), _dp(out))
@@ -91,7 +91,9 @@ class Prepared:
         if rc != 0:
             raise MemoryError("oracle scan failed")
         return {"g1": out[0], "g2": out[1], "loglik": out[2],
-                "A": out[3], "B": out[4], "L": out[5]}
+                "A": out[3], "B": out[4], "L": out[5],
+                "scale_g1": out[9] + out[6], "scale_g2": out[7],
+                "scale_L": out[8]}
 
     def coordinate(self, eta, xj):
         """g', g'', l from arrays in the original subject order."""

@@ -1,0 +1,265 @@
+// C ABI of libsurvscan (declared in include/survscan.h).  Every entry point
+// validates its arguments on the host before launching anything and returns
+// a status code; no exception crosses the interface.
+#include <stdio.h>
+
+#include "ss_internal.h"
+
+namespace ss {
+
+static thread_local char g_last_hip[256] = "no HIP error recorded";
+
+int32_t record_hip_error(hipError_t err)
+{
+    snprintf(g_last_hip, sizeof(g_last_hip), "HIP error %d: %s", (int)err,
+             hipGetErrorString(err));
+    return SS_EDEVICE;
+}
+
+static bool bad_size(int64_t n, int64_t p)
+{
+    return n < 1 || n > INT32_MAX || p < 1 || p > INT32_MAX;
+}
+
+static Column column(const int64_t *col_ptr, const int32_t *rows, const double *vals,
+                     const int32_t *chunk_ptr, int64_t n)
+{
+    Column c;
+    c.col_ptr = col_ptr;
+    c.rows = rows;
+    c.vals = vals;
+    c.chunk_ptr = chunk_ptr;
+    c.nchunk1 = ss_chunk_count(n) + 1;
+    return c;
+}
+
+static bool model_arrays_ok(int32_t model, const double *e, const uint8_t *d8,
+                            const int32_t *d32, const double *w_comp,
+                            const double *g_end)
+{
+    if (!e || !d8 || !d32) return false;
+    if (model == SS_FINE_GRAY && (!w_comp || !g_end)) return false;
+    return true;
+}
+
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" {
+
+const char *ss_status_string(int32_t code)
+{
+    switch (code) {
+    case SS_OK: return "ok";
+    case SS_EINVAL: return "invalid argument or data";
+    case SS_EWORKSPACE: return "workspace too small or not 256-byte aligned";
+    case SS_EUNSUPPORTED: return "unsupported model or penalty";
+    case SS_EDEVICE: return g_last_hip;
+    default: return "unknown status";
+    }
+}
+
+int64_t ss_chunk_count(int64_t n) { return n <= 0 ? 0 : ceil_div(n, SS_CHUNK); }
+
+size_t ss_prepare_workspace_bytes(int64_t n, int64_t p, int64_t nnz)
+{
+    if (n < 1 || p < 1 || nnz < 0) return 0;
+    return prepare_ws_bytes(n, p, nnz);
+}
+
+int32_t ss_prepare(int32_t model, int64_t n, int64_t p, int64_t nnz, const double *y,
+                   const int8_t *status, const int64_t *col_ptr, const int32_t *rows,
+                   const double *vals, int32_t *perm, int32_t *inv_perm, uint8_t *d8,
+                   int32_t *d32, double *c, int32_t *rows_sorted, double *vals_sorted,
+                   int32_t *chunk_ptr, double *w_comp, double *g_end, void *ws,
+                   size_t ws_bytes, void *stream)
+{
+    if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
+    if (bad_size(n, p) || nnz < 0 || nnz > INT32_MAX) return SS_EINVAL;
+    if (!y || !status || !col_ptr || !perm || !inv_perm || !d8 || !d32 || !c ||
+        !chunk_ptr)
+        return SS_EINVAL;
+    if (nnz > 0 && (!rows || !rows_sorted)) return SS_EINVAL;
+    if (vals && nnz > 0 && !vals_sorted) return SS_EINVAL;
+    if (model == SS_FINE_GRAY && (!w_comp || !g_end)) return SS_EINVAL;
+    if (!ws || ((uintptr_t)ws & 255u)) return SS_EWORKSPACE;
+    if (ws_bytes < prepare_ws_bytes(n, p, nnz)) return SS_EWORKSPACE;
+    return run_prepare(model, n, p, nnz, y, status, col_ptr, rows, vals, perm, inv_perm,
+                       d8, d32, c, rows_sorted, vals_sorted, chunk_ptr, w_comp, g_end, ws,
+                       ws_bytes, (hipStream_t)stream);
+}
+
+size_t ss_workspace_bytes(int32_t model, int64_t n)
+{
+    if ((model != SS_COX && model != SS_FINE_GRAY) || n < 1) return 0;
+    return fused_ws_bytes(n);
+}
+
+int32_t ss_workspace_init(void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < sizeof(WsHeader)) return SS_EWORKSPACE;
+    return launch_ws_init(ws, ws_bytes, (hipStream_t)stream);
+}
+
+int32_t ss_workspace_error(const void *ws, int32_t *flag, void *stream)
+{
+    if (!ws || !flag) return SS_EINVAL;
+    uint32_t v = 0;
+    const WsHeader *h = (const WsHeader *)ws;
+    SS_HIP_CHECK(hipMemcpyAsync(&v, &h->error, sizeof(v), hipMemcpyDeviceToHost,
+                                (hipStream_t)stream));
+    SS_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+    *flag = (int32_t)v;
+    return SS_OK;
+}
+
+int32_t ss_grad_hess(int32_t model, int64_t n, int64_t p, int64_t j, const double *e,
+                     const uint8_t *d8, const int32_t *d32, const double *w_comp,
+                     const double *g_end, const int64_t *col_ptr,
+                     const int32_t *rows_sorted, const double *vals_sorted,
+                     const int32_t *chunk_ptr, const double *c, double *out, void *ws,
+                     size_t ws_bytes, void *stream)
+{
+    if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
+    if (bad_size(n, p) || j < 0 || j >= p) return SS_EINVAL;
+    if (!model_arrays_ok(model, e, d8, d32, w_comp, g_end)) return SS_EINVAL;
+    if (!col_ptr || !rows_sorted || !chunk_ptr || !c || !out) return SS_EINVAL;
+    WsView v;
+    if (!fused_ws_view(ws, ws_bytes, n, &v)) return SS_EWORKSPACE;
+    FusedCall a = {};
+    a.model = model;
+    a.n = n;
+    a.p = p;
+    a.j = (int32_t)j;
+    a.jprev = -1;
+    a.e = const_cast<double *>(e);
+    a.d8 = d8;
+    a.d32 = d32;
+    a.w_comp = w_comp;
+    a.g_end = g_end;
+    a.col = column(col_ptr, rows_sorted, vals_sorted, chunk_ptr, n);
+    a.c = c;
+    a.out = out;
+    a.want_log = 1;
+    return launch_fused(a, v, (hipStream_t)stream);
+}
+
+int32_t ss_loglik(int32_t model, int64_t n, int64_t p, const double *e, const uint8_t *d8,
+                  const int32_t *d32, const double *w_comp, const double *g_end,
+                  const double *beta, const double *c, double *out, void *ws,
+                  size_t ws_bytes, void *stream)
+{
+    if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
+    if (bad_size(n, p)) return SS_EINVAL;
+    if (!model_arrays_ok(model, e, d8, d32, w_comp, g_end)) return SS_EINVAL;
+    if (!beta || !c || !out) return SS_EINVAL;
+    WsView v;
+    if (!fused_ws_view(ws, ws_bytes, n, &v)) return SS_EWORKSPACE;
+    FusedCall a = {};
+    a.model = model;
+    a.n = n;
+    a.p = p;
+    a.j = -1;
+    a.jprev = -1;
+    a.e = const_cast<double *>(e);
+    a.d8 = d8;
+    a.d32 = d32;
+    a.w_comp = w_comp;
+    a.g_end = g_end;
+    // no column: the chunk range is empty, the tuple is (e, 0, 0)
+    a.col.col_ptr = nullptr;
+    a.col.rows = nullptr;
+    a.col.vals = nullptr;
+    a.col.chunk_ptr = nullptr;
+    a.col.nchunk1 = ss_chunk_count(n) + 1;
+    a.c = c;
+    a.out = out;
+    a.beta_ll = beta;
+    a.want_log = 1;
+    return launch_fused(a, v, (hipStream_t)stream);
+}
+
+int32_t ss_ccd_update(int32_t penalty, double lambda, int64_t n, int64_t p, int64_t j,
+                      const double *g12, double *beta, double *delta, double *step,
+                      double *eta, double *e, const int64_t *col_ptr,
+                      const int32_t *rows_sorted, const double *vals_sorted, void *stream)
+{
+    if (penalty != SS_PENALTY_NONE && penalty != SS_PENALTY_L1 && penalty != SS_PENALTY_L2)
+        return SS_EUNSUPPORTED;
+    if (penalty != SS_PENALTY_NONE && !(lambda > 0.0)) return SS_EINVAL;
+    if (bad_size(n, p) || j < 0 || j >= p) return SS_EINVAL;
+    if (!g12 || !beta || !delta || !step || !eta || !e || !col_ptr || !rows_sorted)
+        return SS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t rc = launch_ccd_scalar(penalty, lambda, (int32_t)j, g12, beta, delta, step, s);
+    if (rc) return rc;
+    Column col = column(col_ptr, rows_sorted, vals_sorted, nullptr, n);
+    return launch_apply(n, (int32_t)j, step, eta, e, col, s);
+}
+
+int32_t ss_ccd_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, int64_t p,
+                     int64_t j_begin, int64_t j_end, double *eta, double *e,
+                     const uint8_t *d8, const int32_t *d32, const double *w_comp,
+                     const double *g_end, const int64_t *col_ptr,
+                     const int32_t *rows_sorted, const double *vals_sorted,
+                     const int32_t *chunk_ptr, const double *c, double *beta,
+                     double *delta, double *steps, double *g12_out, void *ws,
+                     size_t ws_bytes, void *stream)
+{
+    if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
+    if (penalty != SS_PENALTY_NONE && penalty != SS_PENALTY_L1 && penalty != SS_PENALTY_L2)
+        return SS_EUNSUPPORTED;
+    if (penalty != SS_PENALTY_NONE && !(lambda > 0.0)) return SS_EINVAL;
+    if (bad_size(n, p) || j_begin < 0 || j_end > p || j_begin > j_end) return SS_EINVAL;
+    if (!model_arrays_ok(model, e, d8, d32, w_comp, g_end) || !eta) return SS_EINVAL;
+    if (!col_ptr || !rows_sorted || !chunk_ptr || !c || !beta || !delta || !steps)
+        return SS_EINVAL;
+    WsView v;
+    if (!fused_ws_view(ws, ws_bytes, n, &v)) return SS_EWORKSPACE;
+    if (j_begin == j_end) return SS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    FusedCall a = {};
+    a.model = model;
+    a.n = n;
+    a.p = p;
+    a.eta = eta;
+    a.e = e;
+    a.d8 = d8;
+    a.d32 = d32;
+    a.w_comp = w_comp;
+    a.g_end = g_end;
+    a.col = column(col_ptr, rows_sorted, vals_sorted, chunk_ptr, n);
+    a.c = c;
+    a.ccd = 1;
+    a.penalty = penalty;
+    a.lambda = lambda;
+    a.beta = beta;
+    a.delta = delta;
+    a.steps = steps;
+    a.want_log = g12_out != nullptr;
+    for (int64_t j = j_begin; j < j_end; ++j) {
+        a.j = (int32_t)j;
+        a.jprev = j > j_begin ? (int32_t)(j - 1) : -1;
+        a.step_prev = j > j_begin ? steps + (j - 1) : nullptr;
+        a.out = g12_out ? g12_out + 3 * j : v.hdr->scratch_out;
+        int32_t rc = launch_fused(a, v, s);
+        if (rc) return rc;
+    }
+    return launch_apply(n, (int32_t)(j_end - 1), steps + (j_end - 1), eta, e, a.col, s);
+}
+
+int32_t ss_exp(int64_t n, const double *eta, double *e, void *stream)
+{
+    if (n < 1 || n > INT32_MAX || !eta || !e) return SS_EINVAL;
+    return launch_exp(n, eta, e, (hipStream_t)stream);
+}
+
+int32_t ss_gather(int64_t n, const int32_t *perm, const double *src, double *dst,
+                  void *stream)
+{
+    if (n < 1 || n > INT32_MAX || !perm || !src || !dst) return SS_EINVAL;
+    return launch_gather(n, perm, src, dst, (hipStream_t)stream);
+}
+
+}  // extern "C"

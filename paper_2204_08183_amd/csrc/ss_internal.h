@@ -1,0 +1,212 @@
+// Internal declarations shared by the survscan HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "survscan.h"
+
+namespace ss {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------ host helpers
+// Records the last HIP error for ss_status_string and maps it to a status.
+int32_t record_hip_error(hipError_t err);
+#define SS_HIP_CHECK(call)                                   \
+    do {                                                     \
+        hipError_t _e = (call);                              \
+        if (_e != hipSuccess) return ss::record_hip_error(_e); \
+    } while (0)
+#define SS_LAUNCH_CHECK() SS_HIP_CHECK(hipGetLastError())
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------ device helpers
+// Cross-workgroup communication goes through agent-scope atomics: the eight
+// XCDs of an MI355X each have their own L2, so ordinary stores are not
+// guaranteed to be seen by a workgroup on another XCD.
+__device__ __forceinline__ uint64_t ld_acquire(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_relaxed(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_relaxed_u32(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_relaxed_u64(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed_u32(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release_u64(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t fetch_add_acq_rel(uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// ------------------------------------------------------------ workspace
+// Layout of the fused-kernel workspace (all offsets 256-byte aligned):
+//   WsHeader | TileState[max_tiles] | partials[max_tiles][4] |
+//   fg_partials[max_tiles][4] | scratch scalars
+struct alignas(256) WsHeader {
+    uint32_t ticket;      // tile ticket of the running fused launch
+    uint32_t done;        // finished tiles of the running fused launch
+    uint64_t epoch;       // number of completed fused launches
+    uint32_t error;       // sticky: a bounded wait gave up
+    uint32_t fg_done;     // finished tiles of the Fine-Gray totals pass
+    double fg_tot[3];     // Fine-Gray totals sum_r e_r x_r^m w_r, m = 0..2
+    double scratch_out[4];
+};
+
+// Per-tile look-back state: the flag word is (epoch << 2) | state with
+// state 0 = nothing published, 1 = tile aggregate, 2 = inclusive prefix.
+constexpr int kMaxComp = 6;
+struct alignas(128) TileState {
+    uint64_t flag;
+    double agg[kMaxComp];
+    double inc[kMaxComp];
+};
+
+constexpr uint64_t kStateAgg = 1;
+constexpr uint64_t kStateInc = 2;
+
+// Upper bound on polls of one bounded wait before it gives up (each poll is
+// an uncached load plus a short sleep, so this is on the order of a second).
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+struct WsView {
+    WsHeader *hdr;
+    TileState *tiles;
+    double *partials;     // [max_tiles][4]
+    double *fg_partials;  // [max_tiles][4]
+    int64_t max_tiles;
+};
+
+size_t fused_ws_bytes(int64_t n);
+bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v);
+
+// ------------------------------------------------------------ launchers
+struct Column {
+    const int64_t *col_ptr;
+    const int32_t *rows;
+    const double *vals;      // nullptr: 0/1 indicator design
+    const int32_t *chunk_ptr;
+    int64_t nchunk1;         // ss_chunk_count(n) + 1
+};
+
+struct FusedCall {
+    int32_t model;
+    int64_t n;
+    int64_t p;
+    int32_t j;               // column of g', g''; -1 for the likelihood only
+    int32_t jprev;           // column whose pending step is applied; -1 none
+    const double *step_prev; // device scalar: pending step of jprev
+    double *eta;             // written only when jprev >= 0
+    double *e;
+    const uint8_t *d8;
+    const int32_t *d32;
+    const double *w_comp;
+    const double *g_end;
+    Column col;
+    const double *c;
+    double *out;             // [3]
+    // coordinate update in the last tile (a3)
+    int32_t ccd;             // 0 no update, 1 update beta/delta/steps
+    int32_t penalty;
+    double lambda;
+    double *beta;
+    double *delta;
+    double *steps;
+    // likelihood mode: out[0] = beta' c - sum d log S0
+    const double *beta_ll;
+    int32_t want_log;
+};
+
+int32_t launch_fused(const FusedCall &call, const WsView &ws,
+                     hipStream_t stream);
+int32_t launch_apply(int64_t n, int32_t j, const double *step, double *eta,
+                     double *e, const Column &col, hipStream_t stream);
+int32_t launch_ccd_scalar(int32_t penalty, double lambda, int32_t j,
+                          const double *g12, double *beta, double *delta,
+                          double *step, hipStream_t stream);
+int32_t launch_exp(int64_t n, const double *eta, double *e,
+                   hipStream_t stream);
+int32_t launch_gather(int64_t n, const int32_t *perm, const double *src,
+                      double *dst, hipStream_t stream);
+int32_t launch_ws_init(void *ws, size_t bytes, hipStream_t stream);
+
+// a0
+size_t prepare_ws_bytes(int64_t n, int64_t p, int64_t nnz);
+int32_t run_prepare(int32_t model, int64_t n, int64_t p, int64_t nnz,
+                    const double *y, const int8_t *status,
+                    const int64_t *col_ptr, const int32_t *rows,
+                    const double *vals, int32_t *perm, int32_t *inv_perm,
+                    uint8_t *d8, int32_t *d32, double *c,
+                    int32_t *rows_sorted, double *vals_sorted,
+                    int32_t *chunk_ptr, double *w_comp, double *g_end,
+                    void *ws, size_t ws_bytes, hipStream_t stream);
+
+// Device-side coordinate update shared by the fused epilogue and the
+// standalone scalar kernel (Secs. 2.3-2.4).
+__device__ __forceinline__ double ccd_newton_step(double g1, double g2,
+                                                  double b, int penalty,
+                                                  double lambda)
+{
+    if (penalty == SS_PENALTY_L2) {
+        double d1 = g1 - b / lambda;
+        double d2 = g2 - 1.0 / lambda;
+        return d2 < 0.0 ? -d1 / d2 : 0.0;
+    }
+    if (!(g2 < 0.0)) return 0.0;
+    if (penalty == SS_PENALTY_NONE) return -g1 / g2;
+    // l1
+    if (b != 0.0) {
+        double s = b > 0.0 ? 1.0 : -1.0;
+        double step = -(g1 - lambda * s) / g2;
+        if ((b + step) * s < 0.0) step = -b;
+        return step;
+    }
+    if (g1 - lambda > 0.0) return -(g1 - lambda) / g2;
+    if (g1 + lambda < 0.0) return -(g1 + lambda) / g2;
+    return 0.0;
+}
+
+__device__ __forceinline__ void ccd_apply(double g1, double g2, int penalty,
+                                          double lambda, double *beta_j,
+                                          double *delta_j, double *step_out)
+{
+    double b = *beta_j;
+    double dj = *delta_j;
+    double s = ccd_newton_step(g1, g2, b, penalty, lambda);
+    double a = 0.0;
+    if (s != 0.0) a = s > 0.0 ? fmin(s, dj) : -fmin(-s, dj);
+    *beta_j = b + a;
+    *delta_j = fmax(2.0 * fabs(s), 0.5 * dj);
+    *step_out = a;
+}
+
+}  // namespace ss

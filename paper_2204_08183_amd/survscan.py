@@ -1,0 +1,232 @@
+"""Thin ctypes binding of ``libsurvscan.so`` (declared in include/survscan.h).
+
+Argument marshalling only: every step runs in the HIP library.  torch
+supplies device memory and the current stream.  If the library has not been
+built the import of this module succeeds but every call raises
+``SurvScanError`` -- there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsurvscan.so")
+
+SS_OK = 0
+SS_EINVAL = -1
+SS_EWORKSPACE = -2
+SS_EUNSUPPORTED = -3
+SS_EDEVICE = -4
+
+COX = 0
+FINE_GRAY = 1
+PENALTY_NONE = 0
+PENALTY_L1 = 1
+PENALTY_L2 = 2
+CHUNK = 1024
+
+MODELS = {"cox": COX, "fg": FINE_GRAY, "fine_gray": FINE_GRAY}
+PENALTIES = {"none": PENALTY_NONE, "l1": PENALTY_L1, "l2": PENALTY_L2}
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_f64 = ctypes.c_double
+_sz = ctypes.c_size_t
+
+# name -> (restype, argtypes); the same names as the C declarations
+SIGNATURES = {
+    "ss_status_string": (ctypes.c_char_p, [_i32]),
+    "ss_chunk_count": (_i64, [_i64]),
+    "ss_prepare_workspace_bytes": (_sz, [_i64, _i64, _i64]),
+    "ss_prepare": (_i32, [_i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                          _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ss_workspace_bytes": (_sz, [_i32, _i64]),
+    "ss_workspace_init": (_i32, [_vp, _sz, _vp]),
+    "ss_workspace_error": (_i32, [_vp, ctypes.POINTER(_i32), _vp]),
+    "ss_grad_hess": (_i32, [_i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                            _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ss_loglik": (_i32, [_i32, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                         _sz, _vp]),
+    "ss_ccd_update": (_i32, [_i32, _f64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
+                             _vp, _vp, _vp, _vp]),
+    "ss_ccd_sweep": (_i32, [_i32, _i32, _f64, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp,
+                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                            _sz, _vp]),
+    "ss_exp": (_i32, [_i64, _vp, _vp, _vp]),
+    "ss_gather": (_i32, [_i64, _vp, _vp, _vp, _vp]),
+}
+
+
+class SurvScanError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SurvScanError(
+                "libsurvscan.so is not built (python -m paper_2204_08183_amd.build); "
+                "there is no fallback path")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def status_string(code):
+    return load().ss_status_string(code).decode()
+
+
+def check(code, what):
+    if code != SS_OK:
+        raise SurvScanError("%s failed: %s (%d)" % (what, status_string(code), code))
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def chunk_count(n):
+    return int(load().ss_chunk_count(n))
+
+
+class Workspace:
+    """A 256-byte aligned device scratch buffer owned by torch."""
+
+    def __init__(self, nbytes, device):
+        self.nbytes = int(nbytes)
+        self._buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        addr = self._buf.data_ptr()
+        self.offset = (-addr) % 256
+        self.ptr = ctypes.c_void_p(addr + self.offset)
+
+
+class Problem:
+    """One prepared data set on the GPU (sorted order, chunk index, KM)."""
+
+    def __init__(self, model, y, status, col_ptr, rows, vals=None, device="cuda"):
+        lib = load()
+        self.model_name = model
+        self.model = MODELS[model]
+        self.device = torch.device(device)
+        dev = self.device
+        y = torch.as_tensor(y, dtype=torch.float64).to(dev).contiguous()
+        status = torch.as_tensor(status, dtype=torch.int8).to(dev).contiguous()
+        col_ptr = torch.as_tensor(col_ptr, dtype=torch.int64).to(dev).contiguous()
+        rows = torch.as_tensor(rows, dtype=torch.int32).to(dev).contiguous()
+        self.n = n = int(y.numel())
+        self.p = p = int(col_ptr.numel() - 1)
+        self.nnz = nnz = int(rows.numel())
+        self.vals_in = None if vals is None else \
+            torch.as_tensor(vals, dtype=torch.float64).to(dev).contiguous()
+        self.col_ptr = col_ptr
+        self.perm = torch.empty(n, dtype=torch.int32, device=dev)
+        self.inv_perm = torch.empty(n, dtype=torch.int32, device=dev)
+        self.d8 = torch.empty(n, dtype=torch.uint8, device=dev)
+        self.d32 = torch.empty(n, dtype=torch.int32, device=dev)
+        self.c = torch.empty(p, dtype=torch.float64, device=dev)
+        self.rows_sorted = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        self.vals_sorted = None if vals is None else \
+            torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)
+        self.nchunk = chunk_count(n)
+        self.chunk_ptr = torch.empty(p * (self.nchunk + 1), dtype=torch.int32, device=dev)
+        fg = self.model == FINE_GRAY
+        self.w_comp = torch.empty(n, dtype=torch.float64, device=dev) if fg else None
+        self.g_end = torch.empty(n, dtype=torch.float64, device=dev) if fg else None
+        pws = Workspace(lib.ss_prepare_workspace_bytes(n, p, nnz), dev)
+        rc = lib.ss_prepare(self.model, n, p, nnz, _p(y), _p(status), _p(col_ptr), _p(rows),
+                            _p(self.vals_in), _p(self.perm), _p(self.inv_perm), _p(self.d8),
+                            _p(self.d32), _p(self.c), _p(self.rows_sorted),
+                            _p(self.vals_sorted), _p(self.chunk_ptr), _p(self.w_comp),
+                            _p(self.g_end), pws.ptr, pws.nbytes, _stream(dev))
+        check(rc, "ss_prepare")
+        del pws
+        self.ws = Workspace(lib.ss_workspace_bytes(self.model, n), dev)
+        check(lib.ss_workspace_init(self.ws.ptr, self.ws.nbytes, _stream(dev)),
+              "ss_workspace_init")
+        self.eta = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.e = torch.ones(n, dtype=torch.float64, device=dev)
+        self.beta = torch.zeros(p, dtype=torch.float64, device=dev)
+        self.delta = torch.ones(p, dtype=torch.float64, device=dev)
+        self.steps = torch.zeros(p, dtype=torch.float64, device=dev)
+        self.out = torch.zeros(3, dtype=torch.float64, device=dev)
+
+    # ---------------------------------------------------------------- state
+    def set_eta(self, eta_subject_order):
+        """Sets X beta from a per-subject vector (original order)."""
+        src = torch.as_tensor(eta_subject_order, dtype=torch.float64).to(self.device)
+        src = src.contiguous()
+        lib = load()
+        s = _stream(self.device)
+        check(lib.ss_gather(self.n, _p(self.perm), _p(src), _p(self.eta), s), "ss_gather")
+        check(lib.ss_exp(self.n, _p(self.eta), _p(self.e), s), "ss_exp")
+
+    def set_beta(self, beta, eta_subject_order):
+        self.beta.copy_(torch.as_tensor(beta, dtype=torch.float64))
+        self.set_eta(eta_subject_order)
+
+    def reset_trust(self):
+        self.delta.fill_(1.0)
+
+    # ---------------------------------------------------------------- calls
+    def grad_hess(self, j, out=None):
+        """(g', g'', sum d log S0) of coordinate j as a device tensor [3]."""
+        out = self.out if out is None else out
+        rc = load().ss_grad_hess(self.model, self.n, self.p, int(j), _p(self.e), _p(self.d8),
+                                 _p(self.d32), _p(self.w_comp), _p(self.g_end),
+                                 _p(self.col_ptr), _p(self.rows_sorted),
+                                 _p(self.vals_sorted), _p(self.chunk_ptr), _p(self.c),
+                                 _p(out), self.ws.ptr, self.ws.nbytes, _stream(self.device))
+        check(rc, "ss_grad_hess")
+        return out
+
+    def loglik(self, beta=None, out=None):
+        beta = self.beta if beta is None else \
+            torch.as_tensor(beta, dtype=torch.float64).to(self.device).contiguous()
+        out = torch.zeros(1, dtype=torch.float64, device=self.device) if out is None else out
+        rc = load().ss_loglik(self.model, self.n, self.p, _p(self.e), _p(self.d8),
+                              _p(self.d32), _p(self.w_comp), _p(self.g_end), _p(beta),
+                              _p(self.c), _p(out), self.ws.ptr, self.ws.nbytes,
+                              _stream(self.device))
+        check(rc, "ss_loglik")
+        return out
+
+    def ccd_update(self, j, g12, penalty="none", lam=0.0):
+        rc = load().ss_ccd_update(PENALTIES[penalty], float(lam), self.n, self.p, int(j),
+                                  _p(g12), _p(self.beta), _p(self.delta),
+                                  _p(self.steps[int(j):]), _p(self.eta), _p(self.e),
+                                  _p(self.col_ptr), _p(self.rows_sorted),
+                                  _p(self.vals_sorted), _stream(self.device))
+        check(rc, "ss_ccd_update")
+
+    def sweep(self, penalty="none", lam=0.0, j_begin=0, j_end=None, g12_out=None):
+        j_end = self.p if j_end is None else j_end
+        rc = load().ss_ccd_sweep(self.model, PENALTIES[penalty], float(lam), self.n, self.p,
+                                 int(j_begin), int(j_end), _p(self.eta), _p(self.e),
+                                 _p(self.d8), _p(self.d32), _p(self.w_comp), _p(self.g_end),
+                                 _p(self.col_ptr), _p(self.rows_sorted),
+                                 _p(self.vals_sorted), _p(self.chunk_ptr), _p(self.c),
+                                 _p(self.beta), _p(self.delta), _p(self.steps),
+                                 _p(g12_out), self.ws.ptr, self.ws.nbytes,
+                                 _stream(self.device))
+        check(rc, "ss_ccd_sweep")
+
+    def workspace_error(self):
+        flag = ctypes.c_int32(0)
+        check(load().ss_workspace_error(self.ws.ptr, ctypes.byref(flag),
+                                        _stream(self.device)), "ss_workspace_error")
+        return int(flag.value)

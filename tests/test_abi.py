@@ -1,0 +1,96 @@
+"""The C-ABI library loads, exports every symbol the header declares, and
+rejects invalid arguments on the host before any launch (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2204_08183_amd import survscan as ss
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "survscan.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ss_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ss.LIB_PATH):
+        from paper_2204_08183_amd import build
+        build.build()
+    return ss.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(ss.SIGNATURES), "binding and header disagree"
+
+
+def test_status_strings(lib):
+    for code in (ss.SS_OK, ss.SS_EINVAL, ss.SS_EWORKSPACE, ss.SS_EUNSUPPORTED,
+                 ss.SS_EDEVICE, 12345):
+        assert isinstance(ss.status_string(code), str)
+    assert ss.status_string(ss.SS_OK) == "ok"
+
+
+def test_sizes(lib):
+    assert lib.ss_chunk_count(1) == 1
+    assert lib.ss_chunk_count(ss.CHUNK) == 1
+    assert lib.ss_chunk_count(ss.CHUNK + 1) == 2
+    assert lib.ss_workspace_bytes(ss.COX, 1000) > 0
+    assert lib.ss_workspace_bytes(ss.FINE_GRAY, 10**6) >= lib.ss_workspace_bytes(ss.COX, 1000)
+    assert lib.ss_workspace_bytes(7, 1000) == 0
+    assert lib.ss_prepare_workspace_bytes(1000, 10, 500) > 0
+    assert lib.ss_prepare_workspace_bytes(0, 10, 500) == 0
+
+
+def _fake(addr=0x100000):
+    return ctypes.c_void_p(addr)
+
+
+def test_invalid_arguments_rejected_before_launch(lib):
+    f = _fake()
+    big = 1 << 30
+    # unknown model
+    assert lib.ss_grad_hess(5, 10, 2, 0, f, f, f, f, f, f, f, None, f, f, f, f, big,
+                            None) == ss.SS_EUNSUPPORTED
+    # n < 1, j out of range, null e
+    assert lib.ss_grad_hess(0, 0, 2, 0, f, f, f, None, None, f, f, None, f, f, f, f, big,
+                            None) == ss.SS_EINVAL
+    assert lib.ss_grad_hess(0, 10, 2, 2, f, f, f, None, None, f, f, None, f, f, f, f, big,
+                            None) == ss.SS_EINVAL
+    assert lib.ss_grad_hess(0, 10, 2, 0, None, f, f, None, None, f, f, None, f, f, f, f,
+                            big, None) == ss.SS_EINVAL
+    # Fine-Gray without its weights
+    assert lib.ss_grad_hess(1, 10, 2, 0, f, f, f, None, None, f, f, None, f, f, f, f, big,
+                            None) == ss.SS_EINVAL
+    # workspace too small or misaligned
+    assert lib.ss_grad_hess(0, 10, 2, 0, f, f, f, None, None, f, f, None, f, f, f, f, 16,
+                            None) == ss.SS_EWORKSPACE
+    assert lib.ss_grad_hess(0, 10, 2, 0, f, f, f, None, None, f, f, None, f, f, f,
+                            _fake(0x100008), big, None) == ss.SS_EWORKSPACE
+    # penalties
+    assert lib.ss_ccd_update(9, 1.0, 10, 2, 0, f, f, f, f, f, f, f, f, None,
+                             None) == ss.SS_EUNSUPPORTED
+    assert lib.ss_ccd_update(1, 0.0, 10, 2, 0, f, f, f, f, f, f, f, f, None,
+                             None) == ss.SS_EINVAL
+    assert lib.ss_ccd_sweep(0, 0, 0.0, 10, 2, 1, 0, f, f, f, f, None, None, f, f, None, f,
+                            f, f, f, f, None, f, big, None) == ss.SS_EINVAL
+    # prepare: bad sizes, missing outputs, nnz > 2^31 - 1
+    assert lib.ss_prepare(0, 0, 1, 0, f, f, f, f, None, f, f, f, f, f, f, None, f, None,
+                          None, f, big, None) == ss.SS_EINVAL
+    assert lib.ss_prepare(0, 10, 1, 1 << 31, f, f, f, f, None, f, f, f, f, f, f, None, f,
+                          None, None, f, big, None) == ss.SS_EINVAL
+    assert lib.ss_prepare(1, 10, 1, 5, f, f, f, f, None, f, f, f, f, f, f, None, f, None,
+                          None, f, big, None) == ss.SS_EINVAL
+    assert lib.ss_exp(0, f, f, None) == ss.SS_EINVAL
+    assert lib.ss_gather(5, None, f, f, None) == ss.SS_EINVAL
+    assert lib.ss_workspace_init(None, 100, None) == ss.SS_EWORKSPACE

@@ -1,0 +1,271 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Integer outputs of the preparation are compared bit for bit; g', g'' and the
+likelihood within the condition-scaled FP64 tolerance
+    |dg'|  <= 1e-10 (sum_events |x_j| + sum_k d_k |G_k|)
+    |dg''| <= 1e-10 sum_k d_k (|H_k| + G_k^2)
+    |dL|   <= 1e-10 sum_k d_k |log S0_k|
+(g' cancels near an optimum, so a plain relative bound would be meaningless
+there; the rounding of a tree scan of N terms is ~ (log2 N + IPT) u).
+"""
+import numpy as np
+import pytest
+
+import gen
+from oracle import ccd as occd, km as okm, prep as oprep, risk, scan as oscan
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2204_08183_amd import survscan as ss  # noqa: E402
+
+TOL = 1e-10
+DEV = "cuda:0"
+
+
+# ------------------------------------------------------------------ data
+def make_case(model, n, p, seed, ties=0, density=0.05, valued=False, status=None,
+              eta_shift=0.0):
+    rng = np.random.default_rng(seed + 1000)
+    d = gen.cox_data(seed, n, p, density) if model == "cox" else gen.fg_data(seed, n, p, density)
+    y = d["y"]
+    if ties:
+        y = gen.force_ties(y, ties)
+    st = d["status"].astype(np.int8)
+    if status == "censored":
+        st = np.zeros(n, np.int8)
+    elif status == "events":
+        st = np.ones(n, np.int8)
+    vals = rng.normal(0.0, 1.0, d["rows"].size) if valued else None
+    eta = rng.normal(0.0, 0.5, n) + eta_shift
+    return {"y": y, "status": st, "col_ptr": d["col_ptr"], "rows": d["rows"], "vals": vals,
+            "eta": eta, "n": n, "p": p}
+
+
+def gpu_problem(model, c):
+    prob = ss.Problem(model, c["y"], c["status"], c["col_ptr"], c["rows"], c["vals"], DEV)
+    prob.set_eta(c["eta"])
+    return prob
+
+
+def xcol(c, j):
+    return gen.dense_column(c["n"], c["col_ptr"], c["rows"], c["vals"], j)
+
+
+def oracle_coord(model, c, j, prepared=None):
+    x = xcol(c, j)
+    if c["n"] <= 2000:
+        r = risk.brute(model, c["y"], c["status"], c["eta"], x)
+        ev = oprep.event_indicator(model, c["status"]) == 1
+        return {"g1": r["g1"], "g2": r["g2"], "L": float(np.sum(np.log(r["S0"]))),
+                "scale_g1": float(np.sum(np.abs(x[ev])) + np.sum(np.abs(r["G"]))),
+                "scale_g2": float(np.sum(np.abs(r["H"]) + r["G"] ** 2)),
+                "scale_L": float(np.sum(np.abs(np.log(r["S0"]))))}
+    pr = prepared or oscan.Prepared(model, c["y"], c["status"])
+    return pr.coordinate(c["eta"], x)
+
+
+def assert_coord(got, want, what=""):
+    g1, g2, L = (float(v) for v in got)
+    assert abs(g1 - want["g1"]) <= TOL * want["scale_g1"] + 1e-300, (what, g1, want["g1"])
+    assert abs(g2 - want["g2"]) <= TOL * want["scale_g2"] + 1e-300, (what, g2, want["g2"])
+    assert abs(L - want["L"]) <= TOL * want["scale_L"] + 1e-300, (what, L, want["L"])
+
+
+# ------------------------------------------------------------------ a0
+PREP_CASES = [
+    ("cox", 1, 3, 0, 0, 0.9), ("cox", 2, 3, 1, 0, 0.6), ("cox", 2049, 7, 2, 0, 0.05),
+    ("cox", 6151, 9, 3, 40, 0.1), ("fg", 5000, 5, 4, 3, 0.3), ("fg", 3000, 6, 5, 0, 0.05),
+    ("fg", 1, 2, 6, 0, 1.0),
+]
+
+
+@pytest.mark.parametrize("model,n,p,seed,ties,density", PREP_CASES)
+@pytest.mark.parametrize("valued", [False, True])
+def test_prepare_matches_oracle(model, n, p, seed, ties, density, valued):
+    c = make_case(model, n, p, seed, ties, density, valued)
+    prob = gpu_problem(model, c)
+    order = oprep.order(c["y"])
+    inv = np.empty_like(order)
+    inv[order] = np.arange(n)
+    ys = c["y"][order]
+    ev = oprep.event_indicator(model, c["status"])[order]
+    d = oprep.d_end(ys, ev)
+    np.testing.assert_array_equal(prob.perm.cpu().numpy(), order)
+    np.testing.assert_array_equal(prob.inv_perm.cpu().numpy(), inv)
+    np.testing.assert_array_equal(prob.d32.cpu().numpy(), d)
+    np.testing.assert_array_equal(prob.d8.cpu().numpy(), np.minimum(d, 255))
+    rs, vs = oprep.csc_sorted_rows(c["col_ptr"], c["rows"], c["vals"], inv)
+    nnz = c["rows"].size
+    np.testing.assert_array_equal(prob.rows_sorted.cpu().numpy()[:nnz], rs)
+    if valued:
+        np.testing.assert_array_equal(prob.vals_sorted.cpu().numpy()[:nnz], vs)
+    # chunk index: first offset in the column with position >= t * CHUNK
+    cp = prob.chunk_ptr.cpu().numpy().reshape(p, prob.nchunk + 1)
+    for j in range(p):
+        a, b = c["col_ptr"][j], c["col_ptr"][j + 1]
+        want = np.searchsorted(rs[a:b], np.arange(prob.nchunk + 1) * ss.CHUNK, side="left")
+        np.testing.assert_array_equal(cp[j], want)
+    # c_j = sum over events of x_ij
+    ev_orig = oprep.event_indicator(model, c["status"])
+    want_c = np.array([np.sum(xcol(c, j) * ev_orig) for j in range(p)])
+    if valued:
+        np.testing.assert_allclose(prob.c.cpu().numpy(), want_c, rtol=1e-13, atol=1e-12)
+    else:
+        np.testing.assert_array_equal(prob.c.cpu().numpy(), want_c)
+    if model == "fg":
+        t, v = okm.km_censoring(c["y"], c["status"])
+        G = okm.km_eval(t, v, ys)
+        np.testing.assert_allclose(prob.g_end.cpu().numpy(), G, rtol=1e-12, atol=0)
+        W = np.where(c["status"][order] == 2, 1.0 / G, 0.0)
+        np.testing.assert_allclose(prob.w_comp.cpu().numpy(), W, rtol=1e-12, atol=0)
+
+
+# ------------------------------------------------------------------ a2 / a4
+GH_CASES = [
+    # n, p, seed, ties, density, valued, status, eta_shift
+    (1, 2, 10, 0, 1.0, False, None, 0.0),
+    (2, 2, 11, 0, 1.0, True, "events", 0.0),
+    (2047, 4, 12, 0, 0.05, False, None, 0.0),
+    (2048, 4, 13, 0, 0.05, True, None, 0.0),
+    (2049, 4, 14, 0, 0.3, False, None, 0.0),
+    (6151, 5, 15, 0, 0.05, False, None, 0.0),
+    (6151, 5, 16, 25, 0.1, True, None, 0.0),
+    (20000, 4, 17, 0, 0.05, False, None, 0.0),
+    (20000, 3, 18, 3, 0.2, False, None, 0.0),     # runs with > 255 events
+    (5000, 3, 19, 0, 0.05, False, "censored", 0.0),
+    (5000, 3, 20, 0, 0.05, True, "events", 0.0),
+    (9000, 3, 21, 0, 1.0, False, None, 0.0),      # dense column
+    (9000, 3, 22, 0, 0.05, False, None, 600.0),   # large eta, FP64 range
+    (100000, 3, 23, 50, 0.05, True, None, 0.0),
+]
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+@pytest.mark.parametrize("n,p,seed,ties,density,valued,status,shift", GH_CASES)
+def test_grad_hess_matches_oracle(model, n, p, seed, ties, density, valued, status, shift):
+    c = make_case(model, n, p, seed, ties, density, valued, status, shift)
+    prob = gpu_problem(model, c)
+    pr = oscan.Prepared(model, c["y"], c["status"]) if n > 2000 else None
+    for j in range(p):
+        got = prob.grad_hess(j).cpu().numpy()
+        assert_coord(got, oracle_coord(model, c, j, pr), (model, n, j))
+    assert prob.workspace_error() == 0
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+def test_empty_column(model):
+    c = make_case(model, 3000, 2, 30, 0, 0.05)
+    c["col_ptr"] = np.array([0, 0, c["col_ptr"][1]], dtype=np.int64)
+    c["rows"] = c["rows"][: c["col_ptr"][2]]
+    prob = gpu_problem(model, c)
+    got = prob.grad_hess(0).cpu().numpy()
+    want = oracle_coord(model, c, 0)
+    assert got[0] == 0.0 and got[1] == 0.0
+    assert abs(got[2] - want["L"]) <= TOL * want["scale_L"]
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+def test_repeated_calls_reuse_workspace(model):
+    """The launch counters reset themselves: 50 calls in a row agree."""
+    c = make_case(model, 30000, 2, 31, 0, 0.05)
+    prob = gpu_problem(model, c)
+    outs = torch.stack([prob.grad_hess(1, out=torch.empty(3, dtype=torch.float64,
+                                                           device=DEV)) for _ in range(50)])
+    want = oracle_coord(model, c, 1)
+    for row in outs.cpu().numpy():
+        assert_coord(row, want)
+    assert prob.workspace_error() == 0
+
+
+# ------------------------------------------------------------------ likelihood
+@pytest.mark.parametrize("model", ["cox", "fg"])
+@pytest.mark.parametrize("n,ties", [(1500, 0), (40000, 30)])
+def test_loglik_matches_oracle(model, n, ties):
+    c = make_case(model, n, 6, 40, ties, 0.1)
+    rng = np.random.default_rng(1)
+    beta = rng.normal(0, 0.3, 6)
+    c["eta"] = gen.linear_predictor(n, c["col_ptr"], c["rows"], None, beta)
+    prob = gpu_problem(model, c)
+    got = float(prob.loglik(beta).cpu().numpy()[0])
+    if n <= 2000:
+        want = risk.loglik(model, c["y"], c["status"], c["eta"])
+        scale = abs(want) * 1.0
+    else:
+        r = oscan.Prepared(model, c["y"], c["status"]).coordinate(c["eta"], np.zeros(n))
+        want, scale = r["loglik"], r["scale_L"] + abs(r["loglik"])
+    assert abs(got - want) <= TOL * scale
+
+
+# ------------------------------------------------------------------ a3 + a1
+@pytest.mark.parametrize("penalty,lam,g1,g2,b,dj", [
+    ("none", 0.0, 3.0, -2.0, 0.1, 1.0), ("none", 0.0, 3.0, -2.0, 0.1, 0.25),
+    ("l2", 0.5, 1.0, -4.0, 0.3, 1.0), ("l1", 1.0, 3.0, -2.0, 0.0, 5.0),
+    ("l1", 1.0, -3.0, -2.0, 0.0, 5.0), ("l1", 1.0, 0.2, -2.0, 0.0, 5.0),
+    ("l1", 1.0, -5.0, -2.0, 0.5, 5.0), ("l1", 1.0, 1.5, -2.0, -0.2, 5.0),
+    ("none", 0.0, 1.0, 0.0, 0.0, 1.0),
+])
+def test_ccd_update_matches_oracle(penalty, lam, g1, g2, b, dj):
+    c = make_case("cox", 5000, 3, 50, 0, 0.1, valued=True)
+    prob = gpu_problem("cox", c)
+    j = 1
+    prob.beta[j] = b
+    prob.delta[j] = dj
+    g12 = torch.tensor([g1, g2, 0.0], dtype=torch.float64, device=DEV)
+    eta0 = prob.eta.cpu().numpy().copy()
+    prob.ccd_update(j, g12, penalty, lam)
+    pen = {"none": occd.PENALTY_NONE, "l1": occd.PENALTY_L1, "l2": occd.PENALTY_L2}[penalty]
+    nb, nd, step = occd.update(g1, g2, b, dj, pen, lam)
+    assert float(prob.beta[j]) == nb
+    assert float(prob.delta[j]) == nd
+    assert float(prob.steps[j]) == step
+    x_s = xcol(c, j)[prob.perm.cpu().numpy()]
+    want_eta = eta0 + x_s * step
+    np.testing.assert_allclose(prob.eta.cpu().numpy(), want_eta, rtol=1e-15, atol=1e-15)
+    np.testing.assert_allclose(prob.e.cpu().numpy(), np.exp(want_eta), rtol=1e-14)
+
+
+# ------------------------------------------------------------------ fused sweep
+def oracle_sweeps(model, c, penalty, lam, sweeps):
+    pr = oscan.Prepared(model, c["y"], c["status"])
+    eta = c["eta"].copy()
+    beta = np.zeros(c["p"])
+    delta = np.ones(c["p"])
+    hist = []
+    for _ in range(sweeps):
+        for j in range(c["p"]):
+            x = xcol(c, j)
+            r = pr.coordinate(eta, x)
+            beta[j], delta[j], step = occd.update(r["g1"], r["g2"], beta[j], delta[j],
+                                                 penalty, lam)
+            eta = eta + step * x
+            hist.append((r["g1"], r["g2"], r["scale_g1"], r["scale_g2"]))
+    return beta, delta, eta, hist
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+@pytest.mark.parametrize("penalty,lam", [(occd.PENALTY_L1, 2.0), (occd.PENALTY_L2, 1.0),
+                                         (occd.PENALTY_NONE, 0.0)])
+def test_sweep_matches_oracle_ccd(model, penalty, lam):
+    c = make_case(model, 7000, 10, 60, 0, 0.2)
+    c["eta"] = np.zeros(c["n"])
+    prob = gpu_problem(model, c)
+    name = {occd.PENALTY_NONE: "none", occd.PENALTY_L1: "l1", occd.PENALTY_L2: "l2"}[penalty]
+    g12 = torch.zeros(3 * c["p"], dtype=torch.float64, device=DEV)
+    beta, delta, eta, hist = oracle_sweeps(model, c, penalty, lam, 2)
+    for s in range(2):
+        prob.sweep(name, lam, g12_out=g12)
+        got = g12.cpu().numpy().reshape(-1, 3)
+        for j in range(c["p"]):
+            g1, g2, s1, s2 = hist[s * c["p"] + j]
+            assert abs(got[j, 0] - g1) <= 1e-9 * s1, (s, j)
+            assert abs(got[j, 1] - g2) <= 1e-9 * s2, (s, j)
+    np.testing.assert_allclose(prob.beta.cpu().numpy(), beta, rtol=1e-8, atol=1e-12)
+    np.testing.assert_allclose(prob.delta.cpu().numpy(), delta, rtol=1e-8, atol=1e-12)
+    order = prob.perm.cpu().numpy()
+    np.testing.assert_allclose(prob.eta.cpu().numpy(), eta[order], rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(prob.e.cpu().numpy(), np.exp(eta[order]), rtol=1e-8)
+    assert prob.workspace_error() == 0
