@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Throughput of the Cox / Fine-Gray coordinate-descent hot path on one GPU.
+
+A step is one cyclic-coordinate-descent sweep over all P coordinates of the
+l1-regularised Cox model followed by one sweep of the l1-regularised
+Fine-Gray model (gamma = sqrt(2)), each coordinate being the sparse update
+of X beta, the fused scan -> transform -> reduce for g' and g'', and the
+coordinate update, all on the GPU.  Data: the paper's synthetic design at
+its largest size, N = 1e6 subjects, P = 1000 indicator covariates at 5%
+density (seed 0), already prepared and resident in HBM when timing starts.
+
+One JSON line is printed.  Besides the throughput it carries
+  roofline      the fused Cox kernel at N = 2^27 (its HBM-bound size), timed
+                with HIP events on its own stream;
+  cpu_baseline  the FP64 oracle (serial C scan) on a bounded sample;
+  context       our fused kernel at N = 1e5 next to the paper's GV100 time.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FUSED_SRC = os.path.join(ROOT, "paper_2204_08183_amd", "csrc", "fused.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_cox_n134217728_traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--p", type=int, default=1000)
+    ap.add_argument("--density", type=float, default=0.05)
+    ap.add_argument("--roof-n", type=int, default=1 << 27)
+    ap.add_argument("--roof-reps", type=int, default=20)
+    ap.add_argument("--cpu-coords", type=int, default=150,
+                    help="coordinates per model in the CPU oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-context", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(FUSED_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def event_time_us(torch, fn, reps):
+    """Average device time per call of fn() between two events on the
+    current stream (the stream the library launches on)."""
+    s = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        fn()
+    b.record(s)
+    b.synchronize()
+    return a.elapsed_time(b) * 1e3 / reps
+
+
+def roofline(torch, ss, gen, n, reps):
+    log("roofline workload: uniform(1,2) tuple, dense valued column, N=%d" % n)
+    u = gen.uniform_tuple_data(1, n)
+    prob = ss.Problem("cox", u["y"], u["status"], u["col_ptr"], u["rows"], u["vals"],
+                      "cuda:0")
+    prob.set_eta(u["eta"])
+    nnz = int(u["rows"].size)
+    del u
+    out = torch.empty(3, dtype=torch.float64, device="cuda:0")
+    for _ in range(3):
+        prob.grad_hess(0, out=out)
+    torch.cuda.synchronize()
+    us = event_time_us(torch, lambda: prob.grad_hess(0, out=out), reps)
+    # algorithmic bytes: e (8) and the event count (1) per subject, plus the
+    # column's row index (4) and value (8) per non-zero
+    algo = n * (8 + 1) + nnz * (4 + 8)
+    achieved = algo / (us * 1e-6) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        if t.get("kernel_sha") == kernel_hash() and t.get("n") == n:
+            traffic = t.get("bytes_per_launch")
+    err = prob.workspace_error()
+    del prob
+    torch.cuda.empty_cache()
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_fused<256,8,cox,vals>", "n": n, "nnz": nnz,
+            "algo_bytes_per_launch": algo, "avg_us": round(us, 2), "reps": reps,
+            "wait_errors": err}
+
+
+def context(torch, ss, gen):
+    """Our fused kernel at the paper's Table 1 size (N = 1e5, U(1,2))."""
+    u = gen.uniform_tuple_data(2, 100_000)
+    prob = ss.Problem("cox", u["y"], u["status"], u["col_ptr"], u["rows"], u["vals"],
+                      "cuda:0")
+    prob.set_eta(u["eta"])
+    out = torch.empty(3, dtype=torch.float64, device="cuda:0")
+    for _ in range(5):
+        prob.grad_hess(0, out=out)
+    torch.cuda.synchronize()
+    us = event_time_us(torch, lambda: prob.grad_hess(0, out=out), 200)
+    return {"fused_us_n1e5_ours_back_to_back": round(us, 2),
+            "fused_us_n1e5_paper_gv100": 5.2,
+            "note": "paper Table 1, steps (2)-(4) fused, N=1e5, Uniform(1,2); other GPU"}
+
+
+def cpu_baseline(gen, cox, fg, coords):
+    """The oracle as it stands: serial C scan per coordinate + CCD update."""
+    import numpy as np
+
+    from oracle import ccd as occd, scan as oscan
+    total = 0
+    t0 = time.perf_counter()
+    for model, d in (("cox", cox), ("fg", fg)):
+        pr = oscan.Prepared(model, d["y"], d["status"])
+        eta = np.zeros(d["n"])
+        beta = np.zeros(d["p"])
+        delta = np.ones(d["p"])
+        for j in range(min(coords, d["p"])):
+            x = gen.dense_column(d["n"], d["col_ptr"], d["rows"], None, j)
+            r = pr.coordinate(eta, x)
+            beta[j], delta[j], step = occd.update(r["g1"], r["g2"], beta[j], delta[j],
+                                                  occd.PENALTY_L1, math.sqrt(2.0))
+            if step != 0.0:
+                eta = eta + step * x
+            total += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(total / dt, 2), "unit": "coords/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d coordinates of one l1 CCD sweep (gamma=sqrt 2) on each of the "
+                      "Cox and Fine-Gray N=%d P=%d data sets, from beta=0; serial C scan with "
+                      "compensated sums, single thread; %.1f s" % (coords, cox["n"], cox["p"],
+                                                                  dt)}
+
+
+def copy_calibration(torch):
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8}))
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np  # noqa: F401
+    import torch
+
+    import gen
+    from paper_2204_08183_amd import survscan as ss
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    ss.load()
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+
+    log("generating Cox and Fine-Gray data N=%d P=%d density=%g" % (args.n, args.p,
+                                                                   args.density))
+    cox = gen.cox_data(0, args.n, args.p, args.density)
+    fg = gen.fg_data(0, args.n, args.p, args.density)
+    t0 = time.perf_counter()
+    pc = ss.Problem("cox", cox["y"], cox["status"], cox["col_ptr"], cox["rows"], None,
+                    "cuda:0")
+    pf = ss.Problem("fg", fg["y"], fg["status"], fg["col_ptr"], fg["rows"], None, "cuda:0")
+    torch.cuda.synchronize()
+    prepare_s = time.perf_counter() - t0
+    gamma = math.sqrt(2.0)
+
+    def step():
+        pc.sweep("l1", gamma)
+        pf.sweep("l1", gamma)
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("timing %d steps" % args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    coords = 2 * args.p * args.steps
+    value = coords / elapsed
+    # per-model sweep time (events, after the timed region)
+    cox_us = event_time_us(torch, lambda: pc.sweep("l1", gamma), 2)
+    fg_us = event_time_us(torch, lambda: pf.sweep("l1", gamma), 2)
+    wait_errors = pc.workspace_error() + pf.workspace_error()
+    log("step %.3f ms (cox sweep %.3f ms, fg sweep %.3f ms)" % (ms_per_step, cox_us / 1e3,
+                                                                 fg_us / 1e3))
+    nnz = int(cox["rows"].size)
+    del pc, pf
+    torch.cuda.empty_cache()
+
+    line = {
+        "metric": "CCD coordinate gradient+Hessian evaluations/s (Cox + Fine-Gray, FP64)",
+        "value": round(value, 1),
+        "unit": "coords/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "l1 CCD sweep, Cox then Fine-Gray, N=%d subjects, P=%d indicator "
+                        "covariates at %g density, gamma=sqrt(2) (paper Sec. 3.2 design)"
+                        % (args.n, args.p, args.density),
+            "n": args.n, "p": args.p, "density": args.density, "nnz_cox": nnz,
+            "penalty": "l1", "gamma": gamma, "seed": 0,
+        },
+        "rows_per_s": round(value * args.n, 1),
+        "cox_sweep_ms": round(cox_us / 1e3, 4),
+        "fg_sweep_ms": round(fg_us / 1e3, 4),
+        "us_per_coordinate_cox": round(cox_us / args.p, 3),
+        "us_per_coordinate_fg": round(fg_us / args.p, 3),
+        "prepare_s_both_models": round(prepare_s, 3),
+        "wait_errors": wait_errors,
+    }
+    if not args.no_roofline:
+        line["roofline"] = roofline(torch, ss, gen, args.roof_n, args.roof_reps)
+    if not args.no_context:
+        line["context"] = context(torch, ss, gen)
+    if not args.no_cpu:
+        log("cpu baseline (oracle) on %d coordinates per model" % args.cpu_coords)
+        line["cpu_baseline"] = cpu_baseline(gen, cox, fg, args.cpu_coords)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -146,7 +146,8 @@ def uniform_tuple_data(seed, n, density=1.0):
 
     e ~ U(1,2) (the exp(X beta) vector), one covariate column whose
     non-zero values are U(1,2) (dense by default), event indicator
-    Bernoulli(0.5), all observed times distinct (a random permutation).
+    Bernoulli(0.5), observed times U(0,1) (distinct with overwhelming
+    probability; a tie would be handled exactly anyway).
     Draw order: e, x values, design rows (if sparse), delta, times."""
     rng = np.random.default_rng(seed)
     e = rng.uniform(1.0, 2.0, size=n)
@@ -157,7 +158,7 @@ def uniform_tuple_data(seed, n, density=1.0):
         rows = np.nonzero(rng.random(n) < density)[0].astype(np.int32)
     vals = xv[rows]
     status = (rng.random(n) < 0.5).astype(np.int8)
-    y = rng.permutation(n).astype(np.float64) + 1.0
+    y = rng.random(n)
     col_ptr = np.array([0, rows.size], dtype=np.int64)
     return {"n": n, "p": 1, "y": y, "status": status, "col_ptr": col_ptr,
             "rows": rows, "vals": vals, "eta": np.log(e)}

@@ -26,8 +26,10 @@
  *  - "Sorted order" is the order of decreasing observed time produced by
  *    ss_prepare: position k holds subject perm[k]; equal times keep
  *    increasing original index.
- *  - Sizes: 1 <= n < 2^31, 1 <= p < 2^31; each column has at most n
- *    non-zeros; the total number of non-zeros nnz may exceed 2^31.
+ *  - Sizes: 1 <= n < 2^31, 1 <= p < 2^31, 0 <= nnz < 2^31.
+ *  - Alignment: e, w_comp and g_end must be 16-byte aligned and d8 8-byte
+ *    aligned (any torch CUDA allocation is); the fused kernels read them
+ *    with vector loads.  A misaligned pointer is rejected with SS_EINVAL.
  *  - A workspace `ws` belongs to one stream at a time: two calls that use
  *    the same workspace must not run concurrently.
  */
@@ -101,7 +103,11 @@ int64_t ss_chunk_count(int64_t n);
  *   g_end[n]     Fine-Gray only (else may be NULL): G(y_k), the Kaplan-Meier
  *                estimate of Pr(C > y_k), right-continuous.
  * ws/ws_bytes   device scratch of at least ss_prepare_workspace_bytes().
- * The integer outputs are bit-exact and deterministic. */
+ * The integer outputs are bit-exact and deterministic.
+ * Unlike the other calls, ss_prepare synchronises `stream`: it reads col_ptr
+ * on the host first, and it reports data errors found on the device (a row
+ * index outside [0, n), a duplicate row in a column, a status outside
+ * {0, 1, 2}, invalid column pointers) as SS_EINVAL before returning. */
 size_t ss_prepare_workspace_bytes(int64_t n, int64_t p, int64_t nnz);
 int32_t ss_prepare(int32_t model, int64_t n, int64_t p, int64_t nnz,
                    const double *y, const int8_t *status,

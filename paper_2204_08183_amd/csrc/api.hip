@@ -33,12 +33,20 @@ static Column column(const int64_t *col_ptr, const int32_t *rows, const double *
     return c;
 }
 
+static bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+// The fused kernels read e, w_comp and g_end with 16-byte loads and d8 with
+// 8-byte loads.
 static bool model_arrays_ok(int32_t model, const double *e, const uint8_t *d8,
                             const int32_t *d32, const double *w_comp,
                             const double *g_end)
 {
     if (!e || !d8 || !d32) return false;
-    if (model == SS_FINE_GRAY && (!w_comp || !g_end)) return false;
+    if (!aligned(e, 16) || !aligned(d8, 8)) return false;
+    if (model == SS_FINE_GRAY) {
+        if (!w_comp || !g_end) return false;
+        if (!aligned(w_comp, 16) || !aligned(g_end, 16)) return false;
+    }
     return true;
 }
 

@@ -98,7 +98,7 @@ __device__ void look_back(const TileState *tiles, int64_t tile, uint64_t epoch,
         // every lane runs the same iterations, so the loop stays wave-uniform
         for (;;) {
             if (t >= 0) {
-                const uint64_t f = ld_acquire(&tiles[t].flag);
+                const uint64_t f = ld_flag(&tiles[t].flag);
                 state = (f >> 2) == epoch ? (f & 3u) : 0u;
             }
             if (!__any(state == 0)) break;
@@ -110,6 +110,7 @@ __device__ void look_back(const TileState *tiles, int64_t tile, uint64_t epoch,
                                               __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
+        order_acquire();  // payload loads stay after the flag loads
         const uint64_t inc_mask = __ballot(state == kStateInc);
         const int first_inc = inc_mask ? __ffsll((unsigned long long)inc_mask) - 1 : kWave;
         double v[NC];
@@ -134,7 +135,8 @@ __device__ __forceinline__ void publish(TileState *ts, const double (&val)[NC],
     double *dst = inclusive ? ts->inc : ts->agg;
 #pragma unroll
     for (int c = 0; c < NC; ++c) st_relaxed(dst + c, val[c]);
-    st_release_u64(&ts->flag, (epoch << 2) | (inclusive ? kStateInc : kStateAgg));
+    order_release();  // the payload is at the coherence point before the flag
+    st_flag(&ts->flag, (epoch << 2) | (inclusive ? kStateInc : kStateAgg));
 }
 
 // Applies a pending step of column jprev to eta and e inside [t0, t1).
@@ -214,7 +216,7 @@ __device__ void finish(const FusedCall &a, const WsView &ws, int64_t ntiles,
         st_relaxed_u32(&h->ticket, 0u);
         st_relaxed_u32(&h->done, 0u);
         const uint64_t ep = ld_relaxed_u64(&h->epoch);
-        st_release_u64(&h->epoch, ep + 1);
+        st_relaxed_u64(&h->epoch, ep + 1);
     }
 }
 
@@ -242,8 +244,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
     const int w = tid / kWave;
 
     if (tid == 0) {
-        s_tile = (int64_t)__hip_atomic_fetch_add(&ws.hdr->ticket, 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
+        s_tile = (int64_t)fetch_add_relaxed(&ws.hdr->ticket, 1u);
         s_epoch = ld_relaxed_u64(&ws.hdr->epoch);
     }
     __syncthreads();
@@ -260,34 +261,73 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
     }
     load_column<BLOCK, TILE, VALS>(a, t0, chunk0, chunk1, s_x);
 
-    // ---- load and thread-serial inclusive scan of the tuple
+    // ---- load the tile (vector loads when the tile is full)
     const int64_t base = t0 + (int64_t)tid * IPT;
-    double pre[IPT][NC];
+    const bool full = t0 + TILE <= a.n;
+    double ev[IPT];
+    double xv[IPT];
+    double wv[MODEL == SS_FINE_GRAY ? IPT : 1];
     int dk[IPT];
+    if (full) {
+        const double2 *ep = reinterpret_cast<const double2 *>(a.e + base);
+#pragma unroll
+        for (int q = 0; q < IPT / 2; ++q) {
+            const double2 v = ep[q];
+            ev[2 * q] = v.x;
+            ev[2 * q + 1] = v.y;
+        }
+        if (IPT >= 8) {
+            const uint64_t *dp = reinterpret_cast<const uint64_t *>(a.d8 + base);
+#pragma unroll
+            for (int q = 0; q < IPT / 8; ++q) {
+                const uint64_t dd = dp[q];
+#pragma unroll
+                for (int b = 0; b < 8; ++b) dk[8 * q + b] = (int)((dd >> (8 * b)) & 255u);
+            }
+        } else {
+            const uint32_t dd = *reinterpret_cast<const uint32_t *>(a.d8 + base);
+#pragma unroll
+            for (int b = 0; b < IPT; ++b) dk[b] = (int)((dd >> (8 * b)) & 255u);
+        }
+        if (MODEL == SS_FINE_GRAY) {
+            const double2 *wp = reinterpret_cast<const double2 *>(a.w_comp + base);
+#pragma unroll
+            for (int q = 0; q < IPT / 2; ++q) {
+                const double2 v = wp[q];
+                wv[2 * q] = v.x;
+                wv[2 * q + 1] = v.y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const int64_t k = base + i;
+            const bool ok = k < a.n;
+            ev[i] = ok ? a.e[k] : 0.0;
+            dk[i] = ok ? (int)a.d8[k] : 0;
+            if (MODEL == SS_FINE_GRAY) wv[i] = ok ? a.w_comp[k] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) xv[i] = s_x[tid * IPT + i];
+
+    // ---- thread totals of the tuple
     double run[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) run[c] = 0.0;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const int64_t k = base + i;
-        const bool ok = k < a.n;
-        const double ek = ok ? a.e[k] : 0.0;
-        const double xk = s_x[tid * IPT + i];
-        dk[i] = ok ? (int)a.d8[k] : 0;
-        const double ex = ek * xk;
-        run[0] += ek;
+        const double ex = ev[i] * xv[i];
+        run[0] += ev[i];
         run[1] += ex;
-        run[2] += ex * xk;
+        run[2] += ex * xv[i];
         if (MODEL == SS_FINE_GRAY) {
-            const double wk = ok ? a.w_comp[k] : 0.0;
-            const double ew = ek * wk;
-            const double exw = ew * xk;
+            const double ew = ev[i] * wv[i];
+            const double exw = ew * xv[i];
             run[3] += ew;
             run[4] += exw;
-            run[5] += exw * xk;
+            run[5] += exw * xv[i];
         }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) pre[i][c] = run[c];
     }
 
     // ---- block scan of the thread totals
@@ -347,22 +387,34 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
         for (int c = 0; c < 3; ++c) tot[c] = ws.hdr->fg_tot[c];
     }
 
-    // ---- transform at run ends and reduction
+    // ---- running prefix, transform at run ends, reduction
     double acc[3] = {0.0, 0.0, 0.0};
+    double S[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) S[c] = texcl[c];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
+        const double ex = ev[i] * xv[i];
+        S[0] += ev[i];
+        S[1] += ex;
+        S[2] += ex * xv[i];
+        if (MODEL == SS_FINE_GRAY) {
+            const double ew = ev[i] * wv[i];
+            const double exw = ew * xv[i];
+            S[3] += ew;
+            S[4] += exw;
+            S[5] += exw * xv[i];
+        }
         int d = dk[i];
         if (d != 0) {
             const int64_t k = base + i;
             if (d == 255) d = a.d32[k];
-            double S0 = texcl[0] + pre[i][0];
-            double S1 = texcl[1] + pre[i][1];
-            double S2 = texcl[2] + pre[i][2];
+            double S0 = S[0], S1 = S[1], S2 = S[2];
             if (MODEL == SS_FINE_GRAY) {
                 const double g = a.g_end[k];
-                S0 += g * (tot[0] - (texcl[3] + pre[i][3]));
-                S1 += g * (tot[1] - (texcl[4] + pre[i][4]));
-                S2 += g * (tot[2] - (texcl[5] + pre[i][5]));
+                S0 += g * (tot[0] - S[3]);
+                S1 += g * (tot[1] - S[4]);
+                S2 += g * (tot[2] - S[5]);
             }
             const double r = 1.0 / S0;
             const double G = S1 * r;
@@ -377,12 +429,13 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
     if (tid == 0) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) st_relaxed(ws.partials + 4 * tile + c, acc[c]);
-        const uint32_t prev = fetch_add_acq_rel(&ws.hdr->done, 1u);
+        order_release();
+        const uint32_t prev = fetch_add_relaxed(&ws.hdr->done, 1u);
         s_last = prev == (uint32_t)(ntiles - 1);
     }
     __syncthreads();
     if (s_last) {
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        order_acquire();
         finish<BLOCK>(a, ws, ntiles, s_red);
     }
 }
@@ -425,12 +478,13 @@ __global__ __launch_bounds__(BLOCK) void k_fg_totals(FusedCall a, WsView ws,
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) st_relaxed(ws.fg_partials + 4 * tile + c, acc[c]);
-        const uint32_t prev = fetch_add_acq_rel(&ws.hdr->fg_done, 1u);
+        order_release();
+        const uint32_t prev = fetch_add_relaxed(&ws.hdr->fg_done, 1u);
         s_last = prev == (uint32_t)(ntiles - 1);
     }
     __syncthreads();
     if (s_last) {
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        order_acquire();
         double t[3] = {0.0, 0.0, 0.0};
         for (int64_t q = threadIdx.x; q < ntiles; q += BLOCK) {
 #pragma unroll
@@ -498,8 +552,6 @@ __global__ void k_fill_zero(uint64_t *p, int64_t words)
 }
 
 constexpr int kBlock = 256;
-constexpr int kIpt = 8;
-constexpr int kTile = kBlock * kIpt;
 
 int grid_for(int64_t work, int per_block, int cap)
 {
@@ -537,45 +589,76 @@ bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v)
     return true;
 }
 
-template <int MODEL, bool VALS, bool PREV>
-static void launch_fused_t(const FusedCall &a, const WsView &ws, int64_t ntiles,
-                           hipStream_t s)
+namespace {
+
+// Items per thread by problem size: small problems take small tiles so that
+// every CU gets work, large ones take big tiles to amortise the per-tile
+// look-back and bookkeeping.
+int pick_ipt(int64_t n)
 {
-    hipLaunchKernelGGL((k_fused<kBlock, kIpt, MODEL, VALS, PREV>), dim3((unsigned)ntiles),
+    if (n <= (int64_t)4 << 20) return 4;
+    if (n <= (int64_t)32 << 20) return 8;
+    return 16;
+}
+
+template <int IPT, int MODEL, bool VALS, bool PREV>
+void launch_fused_t(const FusedCall &a, const WsView &ws, int64_t ntiles, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fused<kBlock, IPT, MODEL, VALS, PREV>), dim3((unsigned)ntiles),
                        dim3(kBlock), 0, s, a, ws, ntiles);
 }
 
-int32_t launch_fused(const FusedCall &a, const WsView &ws, hipStream_t s)
+template <int IPT>
+void launch_fg_totals_t(const FusedCall &a, const WsView &ws, int64_t ntiles, bool vals,
+                        bool prev, hipStream_t s)
 {
-    const int64_t ntiles = ceil_div(a.n, kTile);
+    const dim3 g((unsigned)ntiles), b(kBlock);
+    if (vals) {
+        if (prev) hipLaunchKernelGGL((k_fg_totals<kBlock, IPT, true, true>), g, b, 0, s, a, ws, ntiles);
+        else      hipLaunchKernelGGL((k_fg_totals<kBlock, IPT, true, false>), g, b, 0, s, a, ws, ntiles);
+    } else {
+        if (prev) hipLaunchKernelGGL((k_fg_totals<kBlock, IPT, false, true>), g, b, 0, s, a, ws, ntiles);
+        else      hipLaunchKernelGGL((k_fg_totals<kBlock, IPT, false, false>), g, b, 0, s, a, ws, ntiles);
+    }
+}
+
+template <int IPT>
+int32_t launch_fused_ipt(const FusedCall &a, const WsView &ws, hipStream_t s)
+{
+    const int64_t ntiles = ceil_div(a.n, (int64_t)kBlock * IPT);
     if (ntiles > ws.max_tiles) return SS_EWORKSPACE;
     const bool vals = a.col.vals != nullptr;
     const bool prev = a.jprev >= 0;
     FusedCall b = a;
     if (a.model == SS_FINE_GRAY) {
         // totals pass (and the pending a1 update), then the scan pass
-        if (vals) {
-            if (prev) hipLaunchKernelGGL((k_fg_totals<kBlock, kIpt, true, true>), dim3((unsigned)ntiles), dim3(kBlock), 0, s, a, ws, ntiles);
-            else      hipLaunchKernelGGL((k_fg_totals<kBlock, kIpt, true, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, s, a, ws, ntiles);
-        } else {
-            if (prev) hipLaunchKernelGGL((k_fg_totals<kBlock, kIpt, false, true>), dim3((unsigned)ntiles), dim3(kBlock), 0, s, a, ws, ntiles);
-            else      hipLaunchKernelGGL((k_fg_totals<kBlock, kIpt, false, false>), dim3((unsigned)ntiles), dim3(kBlock), 0, s, a, ws, ntiles);
-        }
+        launch_fg_totals_t<IPT>(a, ws, ntiles, vals, prev, s);
         SS_LAUNCH_CHECK();
         b.jprev = -1;
-        if (vals) launch_fused_t<SS_FINE_GRAY, true, false>(b, ws, ntiles, s);
-        else      launch_fused_t<SS_FINE_GRAY, false, false>(b, ws, ntiles, s);
+        if (vals) launch_fused_t<IPT, SS_FINE_GRAY, true, false>(b, ws, ntiles, s);
+        else      launch_fused_t<IPT, SS_FINE_GRAY, false, false>(b, ws, ntiles, s);
     } else {
         if (vals) {
-            if (prev) launch_fused_t<SS_COX, true, true>(b, ws, ntiles, s);
-            else      launch_fused_t<SS_COX, true, false>(b, ws, ntiles, s);
+            if (prev) launch_fused_t<IPT, SS_COX, true, true>(b, ws, ntiles, s);
+            else      launch_fused_t<IPT, SS_COX, true, false>(b, ws, ntiles, s);
         } else {
-            if (prev) launch_fused_t<SS_COX, false, true>(b, ws, ntiles, s);
-            else      launch_fused_t<SS_COX, false, false>(b, ws, ntiles, s);
+            if (prev) launch_fused_t<IPT, SS_COX, false, true>(b, ws, ntiles, s);
+            else      launch_fused_t<IPT, SS_COX, false, false>(b, ws, ntiles, s);
         }
     }
     SS_LAUNCH_CHECK();
     return SS_OK;
+}
+
+}  // namespace
+
+int32_t launch_fused(const FusedCall &a, const WsView &ws, hipStream_t s)
+{
+    switch (pick_ipt(a.n)) {
+    case 4: return launch_fused_ipt<4>(a, ws, s);
+    case 8: return launch_fused_ipt<8>(a, ws, s);
+    default: return launch_fused_ipt<16>(a, ws, s);
+    }
 }
 
 int32_t launch_apply(int64_t n, int32_t j, const double *step, double *eta,

@@ -10,6 +10,8 @@
 //    column, the per-column chunk index and c_j = sum over events of x_ij.
 // Every integer output is produced with exact integer arithmetic, so it is
 // identical from run to run.
+#include <vector>
+
 #include "ss_internal.h"
 
 namespace ss {
@@ -335,45 +337,29 @@ __global__ void k_fg_weights(int64_t n, const int8_t *st_s, const double *g_end,
         w_comp[k] = st_s[k] == 2 ? 1.0 / g_end[k] : 0.0;
 }
 
-__global__ void k_check_colptr(const int64_t *col_ptr, int64_t p, int64_t nnz,
-                               uint32_t *err)
-{
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= p;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t v = col_ptr[j];
-        bool bad = v < 0 || v > nnz;
-        if (j == 0) bad |= v != 0;
-        if (j == p) bad |= v != nnz;
-        if (j > 0) bad |= col_ptr[j - 1] > v;
-        if (bad) atomicOr(err, 4u);
-    }
-}
+// A balanced work list over the non-zeros: chunk q covers entries
+// [begin, end) of column col, with at most kEntChunk entries.
+constexpr int64_t kEntChunk = 4096;
+struct EntChunk {
+    int64_t col;
+    int64_t begin;
+    int64_t end;
+};
 
-__device__ __forceinline__ void col_range(const int64_t *col_ptr, int64_t j, int64_t nnz,
-                                          int64_t *lo, int64_t *hi)
-{
-    int64_t a = col_ptr[j], b = col_ptr[j + 1];
-    a = a < 0 ? 0 : (a > nnz ? nnz : a);
-    b = b < a ? a : (b > nnz ? nnz : b);
-    *lo = a;
-    *hi = b;
-}
-
-__global__ void k_csc_keys(int64_t p, int64_t n, int64_t nnz, const int64_t *col_ptr,
+__global__ void k_csc_keys(const EntChunk *chunks, int64_t nchunks, int64_t n,
                            const int32_t *rows, const double *vals,
                            const int32_t *inv_perm, int posbits, uint64_t *keys,
                            uint64_t *kv, uint32_t *err)
 {
-    for (int64_t j = blockIdx.x; j < p; j += gridDim.x) {
-        int64_t lo, hi;
-        col_range(col_ptr, j, nnz, &lo, &hi);
-        for (int64_t o = lo + threadIdx.x; o < hi; o += blockDim.x) {
+    for (int64_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
+        const EntChunk ch = chunks[q];
+        for (int64_t o = ch.begin + threadIdx.x; o < ch.end; o += blockDim.x) {
             int32_t r = rows[o];
             if (r < 0 || r >= n) {
                 atomicOr(err, 8u);
                 r = 0;
             }
-            keys[o] = ((uint64_t)j << posbits) | (uint64_t)inv_perm[r];
+            keys[o] = ((uint64_t)ch.col << posbits) | (uint64_t)inv_perm[r];
             if (vals) kv[o] = (uint64_t)__double_as_longlong(vals[o]);
         }
     }
@@ -389,19 +375,17 @@ __global__ void k_csc_unpack(int64_t nnz, const uint64_t *keys, const uint64_t *
     }
 }
 
-// c_j = sum over events of x_ij, one workgroup per column, fixed order.
-__global__ __launch_bounds__(256) void k_col_c(int64_t p, int64_t n, int64_t nnz,
-                                               const int64_t *col_ptr,
-                                               const int32_t *rows_sorted,
-                                               const double *vals_sorted,
-                                               const uint8_t *ev_s, double *c)
+// c_j, step 1: every chunk sums x over its event rows in a fixed order.
+__global__ __launch_bounds__(256) void k_col_c_part(const EntChunk *chunks, int64_t nchunks,
+                                                    int64_t n, const int32_t *rows_sorted,
+                                                    const double *vals_sorted,
+                                                    const uint8_t *ev_s, double *part)
 {
     __shared__ double s_red[256 / kWave];
-    for (int64_t j = blockIdx.x; j < p; j += gridDim.x) {
-        int64_t lo, hi;
-        col_range(col_ptr, j, nnz, &lo, &hi);
+    for (int64_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
+        const EntChunk ch = chunks[q];
         double acc = 0.0;
-        for (int64_t o = lo + threadIdx.x; o < hi; o += blockDim.x) {
+        for (int64_t o = ch.begin + threadIdx.x; o < ch.end; o += blockDim.x) {
             const int32_t r = rows_sorted[o];
             if (r >= 0 && r < n && ev_s[r]) acc += vals_sorted ? vals_sorted[o] : 1.0;
         }
@@ -410,41 +394,66 @@ __global__ __launch_bounds__(256) void k_col_c(int64_t p, int64_t n, int64_t nnz
         if (lane_id() == 0) s_red[threadIdx.x / kWave] = acc;
         __syncthreads();
         if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int q = 0; q < 256 / kWave; ++q) s += s_red[q];
-            c[j] = s;
+            double t = 0.0;
+            for (int i = 0; i < 256 / kWave; ++i) t += s_red[i];
+            part[q] = t;
         }
         __syncthreads();
     }
 }
 
-// chunk_ptr[j*(C+1)+t] = first offset in column j with position >= t*CHUNK.
-__global__ void k_chunk_ptr(int64_t p, int64_t nnz, int64_t nchunk,
-                            const int64_t *col_ptr, const int32_t *rows_sorted,
-                            int32_t *chunk_ptr, uint32_t *err)
+// c_j, step 2: one thread per column adds its chunks in order.
+__global__ void k_col_c_final(int64_t p, const int64_t *col_first_chunk, const double *part,
+                              double *c)
 {
-    for (int64_t j = blockIdx.x; j < p; j += gridDim.x) {
-        int64_t lo, hi;
-        col_range(col_ptr, j, nnz, &lo, &hi);
-        const int64_t m = hi - lo;
-        const int32_t *r = rows_sorted + lo;
-        int32_t *cp = chunk_ptr + j * (nchunk + 1);
-        for (int64_t o = threadIdx.x; o < m; o += blockDim.x) {
-            int64_t cur = r[o] / SS_CHUNK;
-            if (r[o] < 0 || cur >= nchunk) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < p;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        double t = 0.0;
+        for (int64_t q = col_first_chunk[j]; q < col_first_chunk[j + 1]; ++q) t += part[q];
+        c[j] = t;
+    }
+}
+
+// chunk_ptr[j*(C+1)+t] = first offset in column j with position >= t*SS_CHUNK.
+// Step 1: every non-zero writes the boundaries between its predecessor's
+// chunk and its own.
+__global__ void k_chunk_ptr_entries(const EntChunk *chunks, int64_t nchunks, int64_t nchunk,
+                                    const int64_t *col_ptr, const int32_t *rows_sorted,
+                                    int32_t *chunk_ptr, uint32_t *err)
+{
+    for (int64_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
+        const EntChunk ch = chunks[q];
+        const int64_t c0 = col_ptr[ch.col];
+        int32_t *cp = chunk_ptr + ch.col * (nchunk + 1);
+        for (int64_t o = ch.begin + threadIdx.x; o < ch.end; o += blockDim.x) {
+            const int32_t r = rows_sorted[o];
+            int64_t cur = r / SS_CHUNK;
+            if (r < 0 || cur >= nchunk) {
                 atomicOr(err, 256u);
-                cur = nchunk - 1;
+                continue;
             }
             int64_t prev = -1;
-            if (o > 0) {
-                prev = r[o - 1] / SS_CHUNK;
-                if (r[o - 1] >= r[o]) atomicOr(err, 16u);  // duplicate row
-                if (prev < -1 || prev > cur) prev = cur;
+            if (o > c0) {
+                const int32_t rp = rows_sorted[o - 1];
+                if (rp >= r) atomicOr(err, 16u);  // duplicate row in a column
+                prev = rp / SS_CHUNK;
+                if (rp < 0 || prev > cur) prev = cur;
             }
-            for (int64_t t = prev + 1; t <= cur; ++t) cp[t] = (int32_t)o;
+            for (int64_t t = prev + 1; t <= cur; ++t) cp[t] = (int32_t)(o - c0);
         }
-        int64_t last = m == 0 ? -1 : r[m - 1] / SS_CHUNK;
+    }
+}
+
+// Step 2: the boundaries after the last non-zero of every column.
+__global__ void k_chunk_ptr_tail(int64_t p, int64_t nchunk, const int64_t *col_ptr,
+                                 const int32_t *rows_sorted, int32_t *chunk_ptr)
+{
+    for (int64_t j = blockIdx.x; j < p; j += gridDim.x) {
+        const int64_t c0 = col_ptr[j];
+        const int64_t m = col_ptr[j + 1] - c0;
+        int64_t last = m == 0 ? -1 : rows_sorted[c0 + m - 1] / SS_CHUNK;
         if (last < -1 || last >= nchunk) last = nchunk - 1;
+        int32_t *cp = chunk_ptr + j * (nchunk + 1);
         for (int64_t t = last + 1 + threadIdx.x; t <= nchunk; t += blockDim.x)
             cp[t] = (int32_t)m;
     }
@@ -478,10 +487,14 @@ struct PrepWs {
     int8_t *st_s;
     uint8_t *ev_s;
     uint32_t *err;
+    EntChunk *chunks;
+    double *part;
+    int64_t *col_first;
 };
 
-size_t layout(int64_t n, int64_t nnz, char *base, PrepWs *w)
+size_t layout(int64_t n, int64_t p, int64_t nnz, char *base, PrepWs *w)
 {
+    const int64_t max_chunks = nnz / kEntChunk + p + 1;
     const int64_t m = n > nnz ? n : nnz;
     const int64_t nbr = ceil_div(m, RT);
     const int64_t hist_len = 256 * nbr;
@@ -508,6 +521,9 @@ size_t layout(int64_t n, int64_t nnz, char *base, PrepWs *w)
     t.st_s = (int8_t *)take((size_t)n);
     t.ev_s = (uint8_t *)take((size_t)n);
     t.err = (uint32_t *)take(256);
+    t.chunks = (EntChunk *)take(sizeof(EntChunk) * (size_t)max_chunks);
+    t.part = (double *)take(8 * (size_t)max_chunks);
+    t.col_first = (int64_t *)take(8 * (size_t)(p + 1));
     if (w) *w = t;
     return off;
 }
@@ -562,8 +578,7 @@ int32_t radix_sort(int64_t m, int nbits, bool has_val, PrepWs &w, uint64_t **key
 
 size_t prepare_ws_bytes(int64_t n, int64_t p, int64_t nnz)
 {
-    (void)p;
-    return layout(n, nnz, nullptr, nullptr);
+    return layout(n, p, nnz, nullptr, nullptr);
 }
 
 int32_t run_prepare(int32_t model, int64_t n, int64_t p, int64_t nnz, const double *y,
@@ -574,14 +589,36 @@ int32_t run_prepare(int32_t model, int64_t n, int64_t p, int64_t nnz, const doub
                     size_t ws_bytes, hipStream_t s)
 {
     PrepWs w;
-    if (layout(n, nnz, (char *)ws, &w) > ws_bytes) return SS_EWORKSPACE;
+    if (layout(n, p, nnz, (char *)ws, &w) > ws_bytes) return SS_EWORKSPACE;
     const bool fg = model == SS_FINE_GRAY;
     int32_t rc;
 
+    // ---- the column pointers on the host: checked there, and cut into a
+    // balanced list of non-zero chunks for the design kernels
+    std::vector<int64_t> cp_host((size_t)p + 1);
+    SS_HIP_CHECK(hipMemcpyAsync(cp_host.data(), col_ptr, sizeof(int64_t) * (size_t)(p + 1),
+                                hipMemcpyDeviceToHost, s));
+    SS_HIP_CHECK(hipStreamSynchronize(s));
+    if (cp_host[0] != 0 || cp_host[(size_t)p] != nnz) return SS_EINVAL;
+    std::vector<EntChunk> chunks;
+    std::vector<int64_t> first((size_t)p + 1);
+    chunks.reserve((size_t)(nnz / kEntChunk + p + 1));
+    for (int64_t j = 0; j < p; ++j) {
+        const int64_t a = cp_host[(size_t)j], b = cp_host[(size_t)j + 1];
+        if (b < a || a < 0 || b > nnz) return SS_EINVAL;
+        first[(size_t)j] = (int64_t)chunks.size();
+        for (int64_t o = a; o < b; o += kEntChunk)
+            chunks.push_back(EntChunk{j, o, o + kEntChunk < b ? o + kEntChunk : b});
+    }
+    first[(size_t)p] = (int64_t)chunks.size();
+    const int64_t nchunks = (int64_t)chunks.size();
+    if (nchunks > 0)
+        SS_HIP_CHECK(hipMemcpyAsync(w.chunks, chunks.data(), sizeof(EntChunk) * chunks.size(),
+                                    hipMemcpyHostToDevice, s));
+    SS_HIP_CHECK(hipMemcpyAsync(w.col_first, first.data(), sizeof(int64_t) * first.size(),
+                                hipMemcpyHostToDevice, s));
+
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int32_t *)w.err, (int64_t)1, 0);
-    SS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_check_colptr, dim3(grid_1d(p + 1)), dim3(256), 0, s, col_ptr, p, nnz,
-                       w.err);
     SS_LAUNCH_CHECK();
 
     // ---- ordering by decreasing time, stable in the subject index
@@ -622,10 +659,10 @@ int32_t run_prepare(int32_t model, int64_t n, int64_t p, int64_t nnz, const doub
     // ---- design: re-label to sorted positions, sort inside columns
     const int posbits = bits_for(n - 1);
     const int colbits = bits_for(p - 1);
+    const unsigned gch = (unsigned)(nchunks < 65536 ? (nchunks > 0 ? nchunks : 1) : 65536);
     if (nnz > 0) {
-        hipLaunchKernelGGL(k_csc_keys, dim3((unsigned)(p < 4096 ? p : 4096)), dim3(256), 0, s,
-                           p, n, nnz, col_ptr, rows, vals, inv_perm, posbits, w.keyA, w.valA,
-                           w.err);
+        hipLaunchKernelGGL(k_csc_keys, dim3(gch), dim3(256), 0, s, w.chunks, nchunks, n, rows,
+                           vals, inv_perm, posbits, w.keyA, w.valA, w.err);
         SS_LAUNCH_CHECK();
         rc = radix_sort(nnz, posbits + colbits, vals != nullptr, w, &ks, &vs, s);
         if (rc) return rc;
@@ -633,14 +670,22 @@ int32_t run_prepare(int32_t model, int64_t n, int64_t p, int64_t nnz, const doub
         hipLaunchKernelGGL(k_csc_unpack, dim3(grid_1d(nnz)), dim3(256), 0, s, nnz, ks, vs,
                            posmask, rows_sorted, vals ? vals_sorted : (double *)nullptr);
         SS_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_col_c_part, dim3(gch), dim3(256), 0, s, w.chunks, nchunks, n,
+                           rows_sorted, vals ? vals_sorted : (const double *)nullptr, w.ev_s,
+                           w.part);
+        SS_LAUNCH_CHECK();
     }
-    const unsigned gcol = (unsigned)(p < 8192 ? p : 8192);
-    hipLaunchKernelGGL(k_col_c, dim3(gcol), dim3(256), 0, s, p, n, nnz, col_ptr, rows_sorted,
-                       vals ? vals_sorted : (const double *)nullptr, w.ev_s, c);
+    hipLaunchKernelGGL(k_col_c_final, dim3(grid_1d(p)), dim3(256), 0, s, p, w.col_first,
+                       w.part, c);
     SS_LAUNCH_CHECK();
     const int64_t nchunk = ceil_div(n, SS_CHUNK);
-    hipLaunchKernelGGL(k_chunk_ptr, dim3(gcol), dim3(256), 0, s, p, nnz, nchunk, col_ptr,
-                       rows_sorted, chunk_ptr, w.err);
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_chunk_ptr_entries, dim3(gch), dim3(256), 0, s, w.chunks, nchunks,
+                           nchunk, col_ptr, rows_sorted, chunk_ptr, w.err);
+        SS_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_chunk_ptr_tail, dim3((unsigned)(p < 8192 ? p : 8192)), dim3(256), 0, s,
+                       p, nchunk, col_ptr, rows_sorted, chunk_ptr);
     SS_LAUNCH_CHECK();
 
     // ---- data errors found on the device

@@ -25,16 +25,34 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ------------------------------------------------------------ device helpers
-// Cross-workgroup communication goes through agent-scope atomics: the eight
-// XCDs of an MI355X each have their own L2, so ordinary stores are not
-// guaranteed to be seen by a workgroup on another XCD.
-__device__ __forceinline__ uint64_t ld_acquire(const uint64_t *p)
+// Cross-workgroup exchange on gfx950.  The eight XCDs of an MI355X each have
+// their own L2, and an agent-scope acquire or release fence writes back or
+// invalidates a whole L2, which costs microseconds and serialises every
+// workgroup of the XCD behind it.  So the values exchanged between
+// workgroups (look-back states, partial sums, counters) are only ever
+// written and read with agent-scope atomic stores and loads, which the
+// hardware performs at the device coherence point, and the two fences below
+// only order those accesses: all outstanding vector memory operations of the
+// wave complete (s_waitcnt vmcnt(0)), and a workgroup-scope fence keeps the
+// compiler from moving accesses across.
+__device__ __forceinline__ void order_release()
 {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0); expcnt, lgkmcnt unchanged
 }
-__device__ __forceinline__ void st_release(uint64_t *p, uint64_t v)
+__device__ __forceinline__ void order_acquire()
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0xF70);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ uint64_t ld_flag(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_flag(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double ld_relaxed(const double *p)
 {
@@ -56,14 +74,13 @@ __device__ __forceinline__ void st_relaxed_u32(uint32_t *p, uint32_t v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_release_u64(uint64_t *p, uint64_t v)
+__device__ __forceinline__ void st_relaxed_u64(uint64_t *p, uint64_t v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ uint32_t fetch_add_acq_rel(uint32_t *p, uint32_t v)
+__device__ __forceinline__ uint32_t fetch_add_relaxed(uint32_t *p, uint32_t v)
 {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL,
-                                  __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
