@@ -2,6 +2,8 @@
 // validates its arguments on the host before launching anything and returns
 // a status code; no exception crosses the interface.
 #include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
 
 #include "ss_internal.h"
 
@@ -227,6 +229,32 @@ int32_t ss_ccd_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, i
     if (!fused_ws_view(ws, ws_bytes, n, &v)) return SS_EWORKSPACE;
     if (j_begin == j_end) return SS_OK;
     hipStream_t s = (hipStream_t)stream;
+    // SURVSCAN_SWEEP=launch forces one launch per coordinate (comparison and
+    // tests); by default the sweep is one cooperative launch when it fits.
+    const char *mode = getenv("SURVSCAN_SWEEP");
+    if (!(mode && strcmp(mode, "launch") == 0)) {
+        SweepCall sc = {};
+        sc.model = model;
+        sc.n = n;
+        sc.j_begin = (int32_t)j_begin;
+        sc.j_end = (int32_t)j_end;
+        sc.eta = eta;
+        sc.e = e;
+        sc.d8 = d8;
+        sc.d32 = d32;
+        sc.w_comp = w_comp;
+        sc.g_end = g_end;
+        sc.col = column(col_ptr, rows_sorted, vals_sorted, chunk_ptr, n);
+        sc.c = c;
+        sc.beta = beta;
+        sc.delta = delta;
+        sc.steps = steps;
+        sc.g12_out = g12_out;
+        sc.penalty = penalty;
+        sc.lambda = lambda;
+        const int32_t rc = launch_sweep_persistent(sc, v, s);
+        if (rc != SS_EUNSUPPORTED) return rc;
+    }
     FusedCall a = {};
     a.model = model;
     a.n = n;

@@ -19,69 +19,42 @@
 // (Sec. 2.7).  The Fine-Gray suffix over later competing events is the
 // grand total minus the inclusive prefix of the weighted components; the
 // totals come from a short reduction pass launched just before.
-#include "ss_internal.h"
+#include "ss_device.h"
 
 namespace ss {
 
 namespace {
+
+using namespace dev;
+
+// Phase timestamps per tile for performance analysis builds only
+// (-DSS_TRACE_TIMES): 100 MHz real-time counter, 8 slots per tile, written
+// behind the regular workspace.
+#ifdef SS_TRACE_TIMES
+#define SS_TRACE(ws, tile, slot)                                                   \
+    do {                                                                           \
+        if (threadIdx.x == 0)                                                      \
+            reinterpret_cast<uint64_t *>((ws).sflags + (ws).max_tiles)             \
+                [(tile) * 8 + (slot)] = __builtin_amdgcn_s_memrealtime();          \
+    } while (0)
+#else
+#define SS_TRACE(ws, tile, slot) do { } while (0)
+#endif
 
 template <int NC>
 struct Vec {
     double v[NC];
 };
 
-// Inclusive wave-wide scan of NC doubles (wave64 shuffles).
-template <int NC>
-__device__ __forceinline__ void wave_inclusive_scan(double (&x)[NC])
-{
-    const int lane = lane_id();
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            double y = __shfl_up(x[c], off, kWave);
-            if (lane >= off) x[c] += y;
-        }
-    }
-}
-
-__device__ __forceinline__ double wave_sum(double x)
-{
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
-    return x;
-}
-
-// Block-wide sum of NC doubles in a fixed order; result valid in thread 0.
-template <int NC, int BLOCK>
-__device__ __forceinline__ void block_sum(double (&x)[NC], double *s_red)
-{
-    constexpr int NW = BLOCK / kWave;
-    const int lane = lane_id();
-    const int w = threadIdx.x / kWave;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) x[c] = wave_sum(x[c]);
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) s_red[w * NC + c] = x[c];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            double s = 0.0;
-            for (int i = 0; i < NW; ++i) s += s_red[i * NC + c];
-            x[c] = s;
-        }
-    }
-}
-
 // Decoupled look-back (single-pass chained scan, Sec. 2.6): wave 0 of tile
-// `tile` walks back over its predecessors 64 at a time until it meets an
-// inclusive prefix.  Returns the tile's exclusive prefix in every lane of
-// wave 0.  Every predecessor took its ticket earlier and publishes its
-// aggregate without waiting, so the wait ends; it is still bounded.
+// `tile` inspects its predecessors kLbK*64 at a time (kLbK flags per lane,
+// all in flight together) and stops at the nearest inclusive prefix.
+// Returns the tile's exclusive prefix in every lane of wave 0.  Every
+// predecessor started earlier (workgroups start in index order on each
+// XCD) and publishes its aggregate without waiting on anyone, so the wait
+// ends; it is bounded all the same.
+constexpr int kLbK = 4;
+
 template <int NC>
 __device__ void look_back(const TileState *tiles, int64_t tile, uint64_t epoch,
                           WsHeader *hdr, double (&excl)[NC])
@@ -91,40 +64,62 @@ __device__ void look_back(const TileState *tiles, int64_t tile, uint64_t epoch,
     for (int c = 0; c < NC; ++c) excl[c] = 0.0;
     int64_t top = tile - 1;
     uint32_t spins = 0;
-    bool give_up = false;
     while (top >= 0) {
-        const int64_t t = top - lane;
-        uint64_t state = kStateInc;  // before tile 0: empty inclusive prefix
+        uint64_t st[kLbK];
+        int found = -1;  // sub-window holding the nearest inclusive prefix
         // every lane runs the same iterations, so the loop stays wave-uniform
         for (;;) {
-            if (t >= 0) {
-                const uint64_t f = ld_flag(&tiles[t].flag);
-                state = (f >> 2) == epoch ? (f & 3u) : 0u;
+#pragma unroll
+            for (int q = 0; q < kLbK; ++q) {
+                const int64_t t = top - lane - (int64_t)kWave * q;
+                st[q] = kStateInc;  // before tile 0: an empty inclusive prefix
+                if (t >= 0) {
+                    const uint64_t f = ld_flag(&tiles[t].flag);
+                    st[q] = (f >> 2) == epoch ? (f & 3u) : 0u;
+                }
             }
-            if (!__any(state == 0)) break;
-            if (++spins > kSpinLimit) { give_up = true; break; }
+            bool ready = true;
+            found = -1;
+#pragma unroll
+            for (int q = 0; q < kLbK; ++q) {
+                if (ready && found < 0) {
+                    if (__any(st[q] == 0)) ready = false;
+                    else if (__any(st[q] == kStateInc)) found = q;
+                }
+            }
+            if (ready) break;
+            if (++spins > kSpinLimit) {
+                if (lane == 0) __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
             __builtin_amdgcn_s_sleep(1);
         }
-        if (give_up) {
-            if (lane == 0) __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-            return;
-        }
         order_acquire();  // payload loads stay after the flag loads
-        const uint64_t inc_mask = __ballot(state == kStateInc);
-        const int first_inc = inc_mask ? __ffsll((unsigned long long)inc_mask) - 1 : kWave;
-        double v[NC];
+        const int qmax = found < 0 ? kLbK - 1 : found;
+        double pay[kLbK][NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) v[c] = 0.0;
-        if (t >= 0 && lane <= first_inc) {
-            const double *src = (state == kStateInc) ? tiles[t].inc : tiles[t].agg;
+        for (int q = 0; q < kLbK; ++q) {
+            const int64_t t = top - lane - (int64_t)kWave * q;
+            bool take = q <= qmax && t >= 0;
+            if (q == found) {
+                const uint64_t m = __ballot(st[q] == kStateInc);
+                take = take && lane <= __ffsll((unsigned long long)m) - 1;
+            }
+            const double *src = st[q] == kStateInc ? tiles[take ? t : 0].inc
+                                                   : tiles[take ? t : 0].agg;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) v[c] = ld_relaxed(src + c);
+            for (int c = 0; c < NC; ++c) pay[q][c] = take ? ld_relaxed(src + c) : 0.0;
         }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) excl[c] += wave_sum(v[c]);
-        if (inc_mask) break;
-        top -= kWave;
+        for (int c = 0; c < NC; ++c) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < kLbK; ++q) v += pay[q][c];
+            excl[c] += wave_sum(v);
+        }
+        if (found >= 0) break;
+        top -= (int64_t)kWave * kLbK;
     }
 }
 
@@ -139,58 +134,69 @@ __device__ __forceinline__ void publish(TileState *ts, const double (&val)[NC],
     st_flag(&ts->flag, (epoch << 2) | (inclusive ? kStateInc : kStateAgg));
 }
 
-// Applies a pending step of column jprev to eta and e inside [t0, t1).
-template <int BLOCK, bool VALS>
-__device__ __forceinline__ void apply_prev(const FusedCall &a, int64_t chunk0,
-                                           int64_t chunk1)
+// The last workgroup of a launch waits until every tile has published its
+// partial sums (flag == tag), U flags in flight per thread, then adds the
+// partials in tile order (deterministic for given partials).  Returns false
+// if a bounded wait gave up.
+template <int BLOCK>
+__device__ bool gather_partials(const double *partials, const uint64_t *pflags,
+                                int64_t ntiles, uint64_t tag, WsHeader *hdr, double (&acc)[3])
 {
-    const double st = *a.step_prev;
-    if (st == 0.0) return;
-    const int64_t cb = a.col.col_ptr[a.jprev];
-    const int32_t *cp = a.col.chunk_ptr + (int64_t)a.jprev * a.col.nchunk1;
-    const int32_t lo = cp[chunk0];
-    const int32_t hi = cp[chunk1];
-    for (int32_t o = lo + (int32_t)threadIdx.x; o < hi; o += BLOCK) {
-        const int32_t r = a.col.rows[cb + o];
-        const double x = VALS ? a.col.vals[cb + o] : 1.0;
-        const double et = a.eta[r] + x * st;
-        a.eta[r] = et;
-        a.e[r] = exp(et);
-    }
-}
-
-// Scatters the non-zeros of column j inside the tile into s_x (zeroed).
-template <int BLOCK, int TILE, bool VALS>
-__device__ __forceinline__ void load_column(const FusedCall &a, int64_t t0,
-                                            int64_t chunk0, int64_t chunk1,
-                                            double *s_x)
-{
-    for (int i = threadIdx.x; i < TILE; i += BLOCK) s_x[i] = 0.0;
-    __syncthreads();
-    if (a.j >= 0) {
-        const int64_t cb = a.col.col_ptr[a.j];
-        const int32_t *cp = a.col.chunk_ptr + (int64_t)a.j * a.col.nchunk1;
-        const int32_t lo = cp[chunk0];
-        const int32_t hi = cp[chunk1];
-        for (int32_t o = lo + (int32_t)threadIdx.x; o < hi; o += BLOCK) {
-            const int32_t r = a.col.rows[cb + o];
-            s_x[r - t0] = VALS ? a.col.vals[cb + o] : 1.0;
+    constexpr int U = 8;
+    bool ok = true;
+    acc[0] = acc[1] = acc[2] = 0.0;
+    for (int64_t t0 = threadIdx.x; t0 < ntiles; t0 += (int64_t)BLOCK * U) {
+        uint32_t spins = 0;
+        for (;;) {
+            bool ready = true;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t t = t0 + (int64_t)u * BLOCK;
+                if (t < ntiles && ld_flag(pflags + t) != tag) ready = false;
+            }
+            if (ready) break;
+            if (++spins > kSpinLimit) {
+                __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        order_acquire();
+        double v[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t t = t0 + (int64_t)u * BLOCK;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[u][c] = t < ntiles ? ld_relaxed(partials + 4 * t + c) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] += v[u][c];
         }
     }
-    __syncthreads();
+    return ok;
 }
 
-// Last tile: fixed-order sum of the per-tile partials, then g', g'', the
-// likelihood or the coordinate update, then reset of the launch counters.
+// Publishes one tile's partial sums (thread 0).
+__device__ __forceinline__ void publish_partial(double *partials, uint64_t *pflags, int64_t tile,
+                                                const double (&acc)[3], uint64_t tag)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) st_relaxed(partials + 4 * tile + c, acc[c]);
+    order_release();
+    st_flag(pflags + tile, tag);
+}
+
+// Last tile: sum of the per-tile partials, then g', g'', the likelihood or
+// the coordinate update, then the launch epoch moves on.
 template <int BLOCK>
-__device__ void finish(const FusedCall &a, const WsView &ws, int64_t ntiles,
+__device__ void finish(const FusedCall &a, const WsView &ws, int64_t ntiles, uint64_t epoch,
                        double *s_red)
 {
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t t = threadIdx.x; t < ntiles; t += BLOCK) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] += ld_relaxed(ws.partials + 4 * t + c);
-    }
+    double acc[3];
+    gather_partials<BLOCK>(ws.partials, ws.pflags, ntiles, (epoch << 1) | 1u, ws.hdr, acc);
     double btc = 0.0;
     if (a.beta_ll) {
         for (int64_t q = threadIdx.x; q < a.p; q += BLOCK) btc += a.beta_ll[q] * a.c[q];
@@ -212,62 +218,36 @@ __device__ void finish(const FusedCall &a, const WsView &ws, int64_t ntiles,
                           a.delta + a.j, a.steps + a.j);
             }
         }
-        WsHeader *h = ws.hdr;
-        st_relaxed_u32(&h->ticket, 0u);
-        st_relaxed_u32(&h->done, 0u);
-        const uint64_t ep = ld_relaxed_u64(&h->epoch);
-        st_relaxed_u64(&h->epoch, ep + 1);
+        // every tile has read the epoch (it published a partial tagged with it)
+        st_relaxed_u64(&ws.hdr->epoch, epoch + 1);
     }
 }
 
-// The fused scan -> transform -> reduce kernel (one coordinate).
-// MODEL: SS_COX (3 tuple components) or SS_FINE_GRAY (6).
-template <int BLOCK, int IPT, int MODEL, bool VALS, bool PREV>
-__global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
-                                                 int64_t ntiles)
+// Stages one tile (positions [t0, t0+cnt)) in registers: e (patched by the
+// pending step of column jprev, which is also written back to eta and e),
+// the weights w (Fine-Gray), the event counts d, and x of column j.  All
+// independent loads are issued together; the column and the patch travel
+// through LDS flag bytes.  s_flag must be zero and visible on entry; ends
+// with the tile's data in registers after one workgroup barrier.
+template <int BLOCK, int IPT, bool WANT_W, bool VALS, bool PREV, bool WANT_D>
+__device__ __forceinline__ void stage_tile(const FusedCall &a, int64_t t0, int64_t cnt,
+                                           int64_t chunk0, int64_t chunk1, uint8_t *s_flag,
+                                           double *s_xv, double *s_ep, double (&ev)[IPT],
+                                           double (&xv)[IPT],
+                                           double (&wv)[WANT_W ? IPT : 1], int (&dk)[IPT])
 {
     constexpr int TILE = BLOCK * IPT;
-    constexpr int NC = MODEL == SS_FINE_GRAY ? 6 : 3;
-    constexpr int NW = BLOCK / kWave;
-    static_assert(TILE % SS_CHUNK == 0, "tile must be whole chunks");
-
-    __shared__ double s_x[TILE];
-    __shared__ double s_wsum[NW][NC];
-    __shared__ double s_excl[NC];
-    __shared__ double s_red[NW * 4];
-    __shared__ int64_t s_tile;
-    __shared__ uint64_t s_epoch;
-    __shared__ int s_last;
-
     const int tid = threadIdx.x;
-    const int lane = lane_id();
-    const int w = tid / kWave;
-
-    if (tid == 0) {
-        s_tile = (int64_t)fetch_add_relaxed(&ws.hdr->ticket, 1u);
-        s_epoch = ld_relaxed_u64(&ws.hdr->epoch);
-    }
-    __syncthreads();
-    const int64_t tile = s_tile;
-    const uint64_t epoch = s_epoch;
-    const int64_t t0 = tile * TILE;
-    const int64_t nchunk = a.col.nchunk1 - 1;
-    const int64_t chunk0 = t0 / SS_CHUNK;
-    const int64_t chunk1 = min(chunk0 + TILE / SS_CHUNK, nchunk);
-
+    ColTile cj = {0, 0, 0};
+    if (a.j >= 0) cj = col_tile(a.col, a.j, chunk0, chunk1);
+    ColTile cprev = {0, 0, 0};
+    double step_prev = 0.0;
     if (PREV) {
-        apply_prev<BLOCK, VALS>(a, chunk0, chunk1);
-        __syncthreads();
+        step_prev = *a.step_prev;
+        cprev = col_tile(a.col, a.jprev, chunk0, chunk1);
     }
-    load_column<BLOCK, TILE, VALS>(a, t0, chunk0, chunk1, s_x);
-
-    // ---- load the tile (vector loads when the tile is full)
     const int64_t base = t0 + (int64_t)tid * IPT;
-    const bool full = t0 + TILE <= a.n;
-    double ev[IPT];
-    double xv[IPT];
-    double wv[MODEL == SS_FINE_GRAY ? IPT : 1];
-    int dk[IPT];
+    const bool full = cnt == TILE;
     if (full) {
         const double2 *ep = reinterpret_cast<const double2 *>(a.e + base);
 #pragma unroll
@@ -276,20 +256,23 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
             ev[2 * q] = v.x;
             ev[2 * q + 1] = v.y;
         }
-        if (IPT >= 8) {
-            const uint64_t *dp = reinterpret_cast<const uint64_t *>(a.d8 + base);
+        if (WANT_D) {
+            if (IPT >= 8) {
+                const uint64_t *dp = reinterpret_cast<const uint64_t *>(a.d8 + base);
 #pragma unroll
-            for (int q = 0; q < IPT / 8; ++q) {
-                const uint64_t dd = dp[q];
+                for (int q = 0; q < IPT / 8; ++q) {
+                    const uint64_t dd = dp[q];
 #pragma unroll
-                for (int b = 0; b < 8; ++b) dk[8 * q + b] = (int)((dd >> (8 * b)) & 255u);
+                    for (int b = 0; b < 8; ++b)
+                        dk[(8 * q + b) % IPT] = (int)((dd >> (8 * b)) & 255u);
+                }
+            } else {
+                const uint32_t dd = *reinterpret_cast<const uint32_t *>(a.d8 + base);
+#pragma unroll
+                for (int b = 0; b < IPT; ++b) dk[b] = (int)((dd >> (8 * b)) & 255u);
             }
-        } else {
-            const uint32_t dd = *reinterpret_cast<const uint32_t *>(a.d8 + base);
-#pragma unroll
-            for (int b = 0; b < IPT; ++b) dk[b] = (int)((dd >> (8 * b)) & 255u);
         }
-        if (MODEL == SS_FINE_GRAY) {
+        if (WANT_W) {
             const double2 *wp = reinterpret_cast<const double2 *>(a.w_comp + base);
 #pragma unroll
             for (int q = 0; q < IPT / 2; ++q) {
@@ -304,14 +287,112 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
             const int64_t k = base + i;
             const bool ok = k < a.n;
             ev[i] = ok ? a.e[k] : 0.0;
-            dk[i] = ok ? (int)a.d8[k] : 0;
-            if (MODEL == SS_FINE_GRAY) wv[i] = ok ? a.w_comp[k] : 0.0;
+            if (WANT_D) dk[i] = ok ? (int)a.d8[k] : 0;
+            if (WANT_W) wv[i] = ok ? a.w_comp[k] : 0.0;
         }
     }
+    // a column with a non-zero at every position of a full tile is read
+    // straight into registers (no scatter)
+    const double *vdense = VALS ? a.col.vals + cj.cb + cj.lo + tid * IPT : nullptr;
+    const bool dense = VALS && full && (int64_t)(cj.hi - cj.lo) == cnt &&
+                       ((uintptr_t)(a.col.vals + cj.cb + cj.lo) & 15u) == 0;
+    if (!dense) {
+        for (int32_t o = cj.lo + tid; o < cj.hi; o += BLOCK) {
+            const int32_t r = (int32_t)(a.col.rows[cj.cb + o] - t0);
+            if (VALS) s_xv[r] = a.col.vals[cj.cb + o];
+            lds_flag_or(s_flag, r, kFlagX);
+        }
+    }
+    if (PREV && step_prev != 0.0) {
+        for (int32_t o = cprev.lo + tid; o < cprev.hi; o += BLOCK) {
+            const int32_t k = a.col.rows[cprev.cb + o];
+            const double x = VALS ? a.col.vals[cprev.cb + o] : 1.0;
+            const double et = a.eta[k] + x * step_prev;
+            const double en = exp(et);
+            a.eta[k] = et;
+            a.e[k] = en;
+            s_ep[k - t0] = en;
+            lds_flag_or(s_flag, (int32_t)(k - t0), kFlagPatch);
+        }
+    }
+    __syncthreads();
+    uint8_t fl[IPT];
+    lds_bytes<IPT>(s_flag + tid * IPT, fl);
+    if (dense) {
+        const double2 *vp = reinterpret_cast<const double2 *>(vdense);
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) xv[i] = s_x[tid * IPT + i];
+        for (int q = 0; q < IPT / 2; ++q) {
+            const double2 v = vp[q];
+            xv[2 * q] = v.x;
+            xv[2 * q + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            if (VALS) xv[i] = (fl[i] & kFlagX) ? s_xv[tid * IPT + i] : 0.0;
+            else xv[i] = (fl[i] & kFlagX) ? 1.0 : 0.0;
+        }
+    }
+    if (PREV) {
+#pragma unroll
+        for (int i = 0; i < IPT; ++i)
+            if (fl[i] & kFlagPatch) ev[i] = s_ep[tid * IPT + i];
+    }
+}
 
-    // ---- thread totals of the tuple
+// The fused scan -> transform -> reduce kernel (one coordinate).
+// MODEL: SS_COX (3 tuple components) or SS_FINE_GRAY (6).  PREV: apply the
+// pending step of column jprev to eta and e first (step (1) of Sec. 2.7).
+template <int BLOCK, int IPT, int MODEL, bool VALS, bool PREV>
+__global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
+                                                 int64_t ntiles)
+{
+    constexpr int TILE = BLOCK * IPT;
+    constexpr int NC = MODEL == SS_FINE_GRAY ? 6 : 3;
+    constexpr int NW = BLOCK / kWave;
+    static_assert(TILE % SS_CHUNK == 0, "tile must be whole chunks");
+
+    __shared__ __attribute__((aligned(16))) uint8_t s_flag[TILE];
+    __shared__ double s_xv[VALS ? TILE : 1];
+    __shared__ double s_ep[PREV ? TILE : 1];
+    __shared__ double s_wsum[NW][NC];
+    __shared__ double s_excl[NC];
+    __shared__ double s_red[NW * 4];
+    __shared__ uint64_t s_epoch;
+
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int w = tid / kWave;
+
+    // ---- 1. the tile is the workgroup index: workgroups start in index
+    // order on each XCD, so every predecessor a tile waits for has started
+    // (the waits are bounded all the same); clear the LDS flags meanwhile
+    SS_TRACE(ws, (int64_t)blockIdx.x, 0);
+    if (tid == 0) s_epoch = ld_relaxed_u64(&ws.hdr->epoch);
+    {
+        uint32_t *f32 = reinterpret_cast<uint32_t *>(s_flag);
+        for (int i = tid; i < TILE / 4; i += BLOCK) f32[i] = 0u;
+    }
+    __syncthreads();
+    const int64_t tile = blockIdx.x;
+    const uint64_t epoch = s_epoch;
+    const int64_t t0 = tile * TILE;
+    const int64_t nchunk = a.col.nchunk1 - 1;
+    const int64_t chunk0 = t0 / SS_CHUNK;
+    const int64_t chunk1 = min(chunk0 + TILE / SS_CHUNK, nchunk);
+    const int64_t cnt = min((int64_t)TILE, a.n - t0);
+
+    // ---- 2-4. tile data, column j and the pending update into registers
+    const int64_t base = t0 + (int64_t)tid * IPT;
+    double ev[IPT];
+    double xv[IPT];
+    double wv[MODEL == SS_FINE_GRAY ? IPT : 1];
+    int dk[IPT];
+    stage_tile<BLOCK, IPT, MODEL == SS_FINE_GRAY, VALS, PREV, true>(
+        a, t0, cnt, chunk0, chunk1, s_flag, s_xv, s_ep, ev, xv, wv, dk);
+    SS_TRACE(ws, tile, 1);
+
+    // ---- 5. thread totals of the tuple
     double run[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) run[c] = 0.0;
@@ -330,7 +411,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
         }
     }
 
-    // ---- block scan of the thread totals
+    // ---- 6. block scan of the thread totals
     double incl[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) incl[c] = run[c];
@@ -354,12 +435,13 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
         agg[c] = total;
     }
 
-    // ---- decoupled look-back for the tile's exclusive prefix
+    // ---- 7. decoupled look-back for the tile's exclusive prefix
+    SS_TRACE(ws, tile, 2);
     if (w == 0) {
         TileState *ts = ws.tiles + tile;
         if (tile == 0) {
-            if (lane == 0) publish<NC>(ts, agg, true, epoch);
             if (lane == 0) {
+                publish<NC>(ts, agg, true, epoch);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) s_excl[c] = 0.0;
             }
@@ -378,6 +460,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
         }
     }
     __syncthreads();
+    SS_TRACE(ws, tile, 3);
 #pragma unroll
     for (int c = 0; c < NC; ++c) texcl[c] += s_excl[c];
 
@@ -387,7 +470,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
         for (int c = 0; c < 3; ++c) tot[c] = ws.hdr->fg_tot[c];
     }
 
-    // ---- running prefix, transform at run ends, reduction
+    // ---- 8. running prefix, transform at run ends, reduction
     double acc[3] = {0.0, 0.0, 0.0};
     double S[NC];
 #pragma unroll
@@ -426,17 +509,11 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
         }
     }
     block_sum<3, BLOCK>(acc, s_red);
-    if (tid == 0) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) st_relaxed(ws.partials + 4 * tile + c, acc[c]);
-        order_release();
-        const uint32_t prev = fetch_add_relaxed(&ws.hdr->done, 1u);
-        s_last = prev == (uint32_t)(ntiles - 1);
-    }
-    __syncthreads();
-    if (s_last) {
-        order_acquire();
-        finish<BLOCK>(a, ws, ntiles, s_red);
+    if (tid == 0) publish_partial(ws.partials, ws.pflags, tile, acc, (epoch << 1) | 1u);
+    SS_TRACE(ws, tile, 4);
+    if (tile == ntiles - 1) {
+        finish<BLOCK>(a, ws, ntiles, epoch, s_red);
+        SS_TRACE(ws, tile, 5);
     }
 }
 
@@ -448,53 +525,48 @@ __global__ __launch_bounds__(BLOCK) void k_fg_totals(FusedCall a, WsView ws,
 {
     constexpr int TILE = BLOCK * IPT;
     constexpr int NW = BLOCK / kWave;
-    __shared__ double s_x[TILE];
+    __shared__ __attribute__((aligned(16))) uint8_t s_flag[TILE];
+    __shared__ double s_xv[VALS ? TILE : 1];
+    __shared__ double s_ep[PREV ? TILE : 1];
     __shared__ double s_red[NW * 4];
-    __shared__ int s_last;
+    __shared__ uint64_t s_epoch;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_epoch = ld_relaxed_u64(&ws.hdr->fg_epoch);
+    {
+        uint32_t *f32 = reinterpret_cast<uint32_t *>(s_flag);
+        for (int i = tid; i < TILE / 4; i += BLOCK) f32[i] = 0u;
+    }
+    __syncthreads();
+    const uint64_t epoch = s_epoch;
+    const uint64_t tag = (epoch << 1) | 1u;
     const int64_t tile = blockIdx.x;
     const int64_t t0 = tile * TILE;
     const int64_t nchunk = a.col.nchunk1 - 1;
     const int64_t chunk0 = t0 / SS_CHUNK;
     const int64_t chunk1 = min(chunk0 + TILE / SS_CHUNK, nchunk);
-    if (PREV) {
-        apply_prev<BLOCK, VALS>(a, chunk0, chunk1);
-        __syncthreads();
-    }
-    load_column<BLOCK, TILE, VALS>(a, t0, chunk0, chunk1, s_x);
+    const int64_t cnt = min((int64_t)TILE, a.n - t0);
+    double ev[IPT], xv[IPT], wv[IPT];
+    int dk[IPT];
+    stage_tile<BLOCK, IPT, true, VALS, PREV, false>(a, t0, cnt, chunk0, chunk1, s_flag, s_xv,
+                                                    s_ep, ev, xv, wv, dk);
     double acc[3] = {0.0, 0.0, 0.0};
-    const int64_t base = t0 + (int64_t)threadIdx.x * IPT;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const int64_t k = base + i;
-        if (k < a.n) {
-            const double ew = a.e[k] * a.w_comp[k];
-            const double xk = s_x[threadIdx.x * IPT + i];
-            acc[0] += ew;
-            acc[1] += ew * xk;
-            acc[2] += ew * xk * xk;
-        }
+        const double ew = ev[i] * wv[i];
+        acc[0] += ew;
+        acc[1] += ew * xv[i];
+        acc[2] += ew * xv[i] * xv[i];
     }
     block_sum<3, BLOCK>(acc, s_red);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) st_relaxed(ws.fg_partials + 4 * tile + c, acc[c]);
-        order_release();
-        const uint32_t prev = fetch_add_relaxed(&ws.hdr->fg_done, 1u);
-        s_last = prev == (uint32_t)(ntiles - 1);
-    }
-    __syncthreads();
-    if (s_last) {
-        order_acquire();
-        double t[3] = {0.0, 0.0, 0.0};
-        for (int64_t q = threadIdx.x; q < ntiles; q += BLOCK) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) t[c] += ld_relaxed(ws.fg_partials + 4 * q + c);
-        }
+    if (tid == 0) publish_partial(ws.fg_partials, ws.fg_pflags, tile, acc, tag);
+    if (tile == ntiles - 1) {
+        double t[3];
+        gather_partials<BLOCK>(ws.fg_partials, ws.fg_pflags, ntiles, tag, ws.hdr, t);
         block_sum<3, BLOCK>(t, s_red);
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) ws.hdr->fg_tot[c] = t[c];
-            st_relaxed_u32(&ws.hdr->fg_done, 0u);
+            st_relaxed_u64(&ws.hdr->fg_epoch, epoch + 1);
         }
     }
 }
@@ -570,6 +642,12 @@ size_t fused_ws_bytes(int64_t n)
     b = align_up(b + sizeof(TileState) * (size_t)tiles, 256);
     b = align_up(b + sizeof(double) * 4 * (size_t)tiles, 256);
     b = align_up(b + sizeof(double) * 4 * (size_t)tiles, 256);
+    b = align_up(b + sizeof(uint64_t) * (size_t)tiles, 256);
+    b = align_up(b + sizeof(uint64_t) * (size_t)tiles, 256);
+    b = align_up(b + sizeof(uint64_t) * (size_t)tiles, 256);
+#ifdef SS_TRACE_TIMES
+    b = align_up(b + sizeof(uint64_t) * 8 * (size_t)tiles, 256);
+#endif
     return b;
 }
 
@@ -585,6 +663,12 @@ bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v)
     v->partials = (double *)(p + off);
     off = align_up(off + sizeof(double) * 4 * (size_t)tiles, 256);
     v->fg_partials = (double *)(p + off);
+    off = align_up(off + sizeof(double) * 4 * (size_t)tiles, 256);
+    v->pflags = (uint64_t *)(p + off);
+    off = align_up(off + sizeof(uint64_t) * (size_t)tiles, 256);
+    v->fg_pflags = (uint64_t *)(p + off);
+    off = align_up(off + sizeof(uint64_t) * (size_t)tiles, 256);
+    v->sflags = (uint64_t *)(p + off);
     v->max_tiles = tiles;
     return true;
 }

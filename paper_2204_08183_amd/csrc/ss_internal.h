@@ -88,13 +88,13 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 // ------------------------------------------------------------ workspace
 // Layout of the fused-kernel workspace (all offsets 256-byte aligned):
 //   WsHeader | TileState[max_tiles] | partials[max_tiles][4] |
-//   fg_partials[max_tiles][4] | scratch scalars
+//   fg_partials[max_tiles][4] | pflags[max_tiles] | fg_pflags[max_tiles] |
+//   sflags[max_tiles]
 struct alignas(256) WsHeader {
-    uint32_t ticket;      // tile ticket of the running fused launch
-    uint32_t done;        // finished tiles of the running fused launch
     uint64_t epoch;       // number of completed fused launches
+    uint64_t fg_epoch;    // number of completed Fine-Gray totals passes
     uint32_t error;       // sticky: a bounded wait gave up
-    uint32_t fg_done;     // finished tiles of the Fine-Gray totals pass
+    uint32_t pad;
     double fg_tot[3];     // Fine-Gray totals sum_r e_r x_r^m w_r, m = 0..2
     double scratch_out[4];
 };
@@ -115,11 +115,19 @@ constexpr uint64_t kStateInc = 2;
 // an uncached load plus a short sleep, so this is on the order of a second).
 constexpr uint32_t kSpinLimit = 1u << 20;
 
+// Per-tile "partial ready" words hold the tag (epoch << 1) | 1 of the launch
+// that wrote the tile's partial sums; the last workgroup of the launch polls
+// them instead of counting finished tiles on one shared atomic counter
+// (same-address atomics from every workgroup serialise at the coherence
+// point, about 12 ns each on MI355X).
 struct WsView {
     WsHeader *hdr;
     TileState *tiles;
     double *partials;     // [max_tiles][4]
     double *fg_partials;  // [max_tiles][4]
+    uint64_t *pflags;     // [max_tiles]
+    uint64_t *fg_pflags;  // [max_tiles]
+    uint64_t *sflags;     // [max_tiles] step broadcast of the persistent sweep
     int64_t max_tiles;
 };
 
@@ -165,6 +173,32 @@ struct FusedCall {
 
 int32_t launch_fused(const FusedCall &call, const WsView &ws,
                      hipStream_t stream);
+
+// The whole sweep j_begin..j_end-1 as one cooperative launch; returns
+// SS_EUNSUPPORTED (launching nothing) when the problem does not fit on the
+// device at once, and the caller then launches per coordinate.
+struct SweepCall {
+    int32_t model;
+    int64_t n;
+    int32_t j_begin;
+    int32_t j_end;
+    double *eta;
+    double *e;
+    const uint8_t *d8;
+    const int32_t *d32;
+    const double *w_comp;
+    const double *g_end;
+    Column col;
+    const double *c;
+    double *beta;
+    double *delta;
+    double *steps;
+    double *g12_out;
+    int32_t penalty;
+    double lambda;
+};
+int32_t launch_sweep_persistent(const SweepCall &call, const WsView &ws,
+                                hipStream_t stream);
 int32_t launch_apply(int64_t n, int32_t j, const double *step, double *eta,
                      double *e, const Column &col, hipStream_t stream);
 int32_t launch_ccd_scalar(int32_t penalty, double lambda, int32_t j,

@@ -246,10 +246,22 @@ def oracle_sweeps(model, c, penalty, lam, sweeps):
     return beta, delta, eta, hist
 
 
+SWEEP_PATHS = ["persistent", "launch"]
+
+
+def _sweep_env(monkeypatch, path):
+    if path == "launch":
+        monkeypatch.setenv("SURVSCAN_SWEEP", "launch")
+    else:
+        monkeypatch.delenv("SURVSCAN_SWEEP", raising=False)
+
+
+@pytest.mark.parametrize("path", SWEEP_PATHS)
 @pytest.mark.parametrize("model", ["cox", "fg"])
 @pytest.mark.parametrize("penalty,lam", [(occd.PENALTY_L1, 2.0), (occd.PENALTY_L2, 1.0),
                                          (occd.PENALTY_NONE, 0.0)])
-def test_sweep_matches_oracle_ccd(model, penalty, lam):
+def test_sweep_matches_oracle_ccd(model, penalty, lam, path, monkeypatch):
+    _sweep_env(monkeypatch, path)
     c = make_case(model, 7000, 10, 60, 0, 0.2)
     c["eta"] = np.zeros(c["n"])
     prob = gpu_problem(model, c)
@@ -269,3 +281,55 @@ def test_sweep_matches_oracle_ccd(model, penalty, lam):
     np.testing.assert_allclose(prob.eta.cpu().numpy(), eta[order], rtol=1e-8, atol=1e-10)
     np.testing.assert_allclose(prob.e.cpu().numpy(), np.exp(eta[order]), rtol=1e-8)
     assert prob.workspace_error() == 0
+
+
+@pytest.mark.parametrize("path", SWEEP_PATHS)
+@pytest.mark.parametrize("model", ["cox", "fg"])
+@pytest.mark.parametrize("n,p,ties,valued", [
+    (1_000_000, 6, 0, False),     # the benchmark size: 489 segments of 2048
+    (2_500_003, 4, 0, True),      # segments of 8192, ragged last segment
+    (300_001, 5, 40, False),      # tie runs across segment boundaries
+    (4_300_000, 3, 0, False),     # above the persistent limit: launch per coordinate
+])
+def test_sweep_large(model, n, p, ties, valued, path, monkeypatch):
+    _sweep_env(monkeypatch, path)
+    c = make_case(model, n, p, 70, ties, 0.05, valued)
+    c["eta"] = np.zeros(n)
+    prob = gpu_problem(model, c)
+    lam = 1.0
+    g12 = torch.zeros(3 * p, dtype=torch.float64, device=DEV)
+    beta, delta, eta, hist = oracle_sweeps(model, c, occd.PENALTY_L1, lam, 1)
+    prob.sweep("l1", lam, g12_out=g12)
+    got = g12.cpu().numpy().reshape(-1, 3)
+    for j in range(p):
+        g1, g2, s1, s2 = hist[j]
+        assert abs(got[j, 0] - g1) <= 1e-10 * s1, (j, got[j, 0], g1)
+        assert abs(got[j, 1] - g2) <= 1e-10 * s2, (j, got[j, 1], g2)
+    np.testing.assert_allclose(prob.beta.cpu().numpy(), beta, rtol=1e-9, atol=1e-13)
+    order = prob.perm.cpu().numpy()
+    np.testing.assert_allclose(prob.eta.cpu().numpy(), eta[order], rtol=1e-9, atol=1e-12)
+    assert prob.workspace_error() == 0
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+def test_sweep_deterministic_and_consistent(model, monkeypatch):
+    """The persistent sweep adds every partial in a fixed order: two runs
+    from the same state agree bit for bit, and grad_hess afterwards sees the
+    e the sweep left behind."""
+    monkeypatch.delenv("SURVSCAN_SWEEP", raising=False)
+    c = make_case(model, 200_000, 8, 80, 0, 0.05)
+    c["eta"] = np.zeros(c["n"])
+    outs = []
+    for _ in range(2):
+        prob = gpu_problem(model, c)
+        g12 = torch.zeros(3 * c["p"], dtype=torch.float64, device=DEV)
+        prob.sweep("l1", 0.5, g12_out=g12)
+        prob.sweep("l1", 0.5, g12_out=g12)
+        outs.append((g12.cpu().numpy().copy(), prob.beta.cpu().numpy().copy(),
+                     prob.e.cpu().numpy().copy()))
+        # e is consistent with eta after the sweep
+        np.testing.assert_allclose(prob.e.cpu().numpy(), np.exp(prob.eta.cpu().numpy()),
+                                   rtol=1e-14)
+        assert prob.workspace_error() == 0
+    for a_, b_ in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a_, b_)
