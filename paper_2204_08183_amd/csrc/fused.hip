@@ -34,7 +34,7 @@ using namespace dev;
 #define SS_TRACE(ws, tile, slot)                                                   \
     do {                                                                           \
         if (threadIdx.x == 0)                                                      \
-            reinterpret_cast<uint64_t *>((ws).sflags + (ws).max_tiles)             \
+            reinterpret_cast<uint64_t *>((ws).sw_pre + 8 * (ws).max_tiles)         \
                 [(tile) * 8 + (slot)] = __builtin_amdgcn_s_memrealtime();          \
     } while (0)
 #else
@@ -645,8 +645,12 @@ size_t fused_ws_bytes(int64_t n)
     b = align_up(b + sizeof(uint64_t) * (size_t)tiles, 256);
     b = align_up(b + sizeof(uint64_t) * (size_t)tiles, 256);
     b = align_up(b + sizeof(uint64_t) * (size_t)tiles, 256);
+    b = align_up(b + 16 * 8 * (size_t)tiles, 256);
+    b = align_up(b + 16 * 4 * (size_t)tiles, 256);
+    b = align_up(b + 16 * (size_t)tiles, 256);
+    b = align_up(b + 16 * 8 * (size_t)tiles, 256);
 #ifdef SS_TRACE_TIMES
-    b = align_up(b + sizeof(uint64_t) * 8 * (size_t)tiles, 256);
+    b = align_up(b + sizeof(uint64_t) * 64 * (size_t)tiles, 256);
 #endif
     return b;
 }
@@ -669,6 +673,15 @@ bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v)
     v->fg_pflags = (uint64_t *)(p + off);
     off = align_up(off + sizeof(uint64_t) * (size_t)tiles, 256);
     v->sflags = (uint64_t *)(p + off);
+    typedef __attribute__((ext_vector_type(4))) unsigned int u4;
+    off = align_up(off + sizeof(uint64_t) * (size_t)tiles, 256);
+    v->sw_agg = (u4 *)(p + off);
+    off = align_up(off + 16 * 8 * (size_t)tiles, 256);
+    v->sw_part = (u4 *)(p + off);
+    off = align_up(off + 16 * 4 * (size_t)tiles, 256);
+    v->sw_step = (u4 *)(p + off);
+    off = align_up(off + 16 * (size_t)tiles, 256);
+    v->sw_pre = (u4 *)(p + off);
     v->max_tiles = tiles;
     return true;
 }

@@ -102,5 +102,113 @@ __device__ __forceinline__ ColTile col_tile(const Column &col, int32_t j, int64_
     return ct;
 }
 
+// ---------------------------------------------------------------- DPP
+// Wave64 scans and reductions of doubles on the VALU through DPP row shifts
+// and row broadcasts (gfx9 family), one 32-bit half at a time; lanes a
+// shift reads from outside the row, and rows the mask leaves out, add 0.
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ double dpp_double(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xF,
+                                               BOUND_ZERO);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF,
+                                               BOUND_ZERO);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Inclusive scan across the 64 lanes of a wave.
+__device__ __forceinline__ double dpp_incl_scan(double x)
+{
+    x += dpp_double<0x111, 0xF, true>(x);  // row_shr:1
+    x += dpp_double<0x112, 0xF, true>(x);  // row_shr:2
+    x += dpp_double<0x114, 0xF, true>(x);  // row_shr:4
+    x += dpp_double<0x118, 0xF, true>(x);  // row_shr:8
+    x += dpp_double<0x142, 0xA, false>(x); // row_bcast:15 into rows 1 and 3
+    x += dpp_double<0x143, 0xC, false>(x); // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+__device__ __forceinline__ double read_lane(double x, int lane)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the wave, returned in every lane.
+__device__ __forceinline__ double dpp_wave_sum(double x)
+{
+    return read_lane(dpp_incl_scan(x), kWave - 1);
+}
+
+// ---------------------------------------------------------------- pairs
+// A published value travels as a 16-byte (value, tag) pair written and read
+// with one agent-scope 16-byte access each, which the memory system performs
+// as a unit, so a reader that sees the expected tag also sees the value and
+// no separate flag or ordering wait is needed.  The tag carries the epoch of
+// the step that wrote it.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u32x4 make_pair(double v, uint64_t tag)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    u32x4 r;
+    r.x = (unsigned int)b;
+    r.y = (unsigned int)(b >> 32);
+    r.z = (unsigned int)tag;
+    r.w = (unsigned int)(tag >> 32);
+    return r;
+}
+__device__ __forceinline__ double pair_value(u32x4 r)
+{
+    return __longlong_as_double((long long)(((unsigned long long)r.y << 32) | r.x));
+}
+__device__ __forceinline__ uint64_t pair_tag(u32x4 r)
+{
+    return ((uint64_t)r.w << 32) | r.z;
+}
+
+// The s_nop after the store: a VMEM store of more than 64 bits must not have
+// its data VGPRs overwritten by the next VALU instructions before it has
+// read them (a GFX9-family hazard).  The compiler's hazard recognizer pads
+// the stores it emits itself, but not one inside inline assembly, so the
+// padding is part of the statement.
+__device__ __forceinline__ void st_pair(u32x4 *p, double v, uint64_t tag)
+{
+    const u32x4 val = make_pair(v, tag);
+    asm volatile("global_store_dwordx4 %0, %1, off sc1\n\ts_nop 4"
+                 : : "v"(p), "v"(val) : "memory");
+}
+
+// Loads NP consecutive pairs (NP in {1, 3, 6}) and waits for them.
+template <int NP>
+__device__ __forceinline__ void ld_pairs(const u32x4 *p, u32x4 (&r)[NP])
+{
+    if (NP == 1) {
+        asm volatile("global_load_dwordx4 %0, %1, off sc1\n\ts_waitcnt vmcnt(0)"
+                     : "=&v"(r[0]) : "v"(p) : "memory");
+    } else if (NP == 3) {
+        asm volatile("global_load_dwordx4 %0, %3, off sc1\n\t"
+                     "global_load_dwordx4 %1, %3, off offset:16 sc1\n\t"
+                     "global_load_dwordx4 %2, %3, off offset:32 sc1\n\t"
+                     "s_waitcnt vmcnt(0)"
+                     : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]) : "v"(p) : "memory");
+    } else {
+        asm volatile("global_load_dwordx4 %0, %6, off sc1\n\t"
+                     "global_load_dwordx4 %1, %6, off offset:16 sc1\n\t"
+                     "global_load_dwordx4 %2, %6, off offset:32 sc1\n\t"
+                     "global_load_dwordx4 %3, %6, off offset:48 sc1\n\t"
+                     "global_load_dwordx4 %4, %6, off offset:64 sc1\n\t"
+                     "global_load_dwordx4 %5, %6, off offset:80 sc1\n\t"
+                     "s_waitcnt vmcnt(0)"
+                     : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]),
+                       "=&v"(r[5])
+                     : "v"(p)
+                     : "memory");
+    }
+}
+
 }  // namespace dev
 }  // namespace ss

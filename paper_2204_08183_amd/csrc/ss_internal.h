@@ -127,7 +127,12 @@ struct WsView {
     double *fg_partials;  // [max_tiles][4]
     uint64_t *pflags;     // [max_tiles]
     uint64_t *fg_pflags;  // [max_tiles]
-    uint64_t *sflags;     // [max_tiles] step broadcast of the persistent sweep
+    uint64_t *sflags;     // [max_tiles] (trace base in analysis builds)
+    // persistent sweep: 16-byte (value, tag) pairs
+    __attribute__((ext_vector_type(4))) unsigned int *sw_agg;   // [max_tiles][8]
+    __attribute__((ext_vector_type(4))) unsigned int *sw_part;  // [max_tiles][4]
+    __attribute__((ext_vector_type(4))) unsigned int *sw_step;  // [max_tiles]
+    __attribute__((ext_vector_type(4))) unsigned int *sw_pre;   // [max_tiles][8]
     int64_t max_tiles;
 };
 

@@ -7,18 +7,20 @@
 // positions for the whole sweep; e (and, for Fine-Gray, w and G) of its
 // segment stay in registers, and only the rows that an update touches are
 // patched.  Per coordinate j the workgroups exchange data twice:
-//   1. all-to-all: each publishes the tuple aggregate of its segment, then
-//      sums the aggregates of the segments before it (its exclusive prefix
-//      of the tuple scan, Sec. 2.7) and, for Fine-Gray, of all segments (the
-//      totals that turn the inclusive prefix of e*w into the suffix sum of
-//      eq. fg_g) -- a fixed-order sum, so results are deterministic;
+//   1. all-to-one-to-all: each publishes the tuple aggregate of its
+//      segment; workgroup 0 scans them in segment order and hands every
+//      workgroup its exclusive prefix of the tuple scan (Sec. 2.7) -- and,
+//      for Fine-Gray, the weighted suffix sum that starts at the segment
+//      (eq. fg_g) -- a fixed-order computation, so results are
+//      deterministic;
 //   2. all-to-one-to-all: each publishes its partial sums of
 //      d*G, d*(H - G^2), d*log S0; workgroup 0 adds them in order, takes the
 //      coordinate update (Secs. 2.3-2.4) and broadcasts the step through one
 //      flag per workgroup.
-// All exchanged values go through agent-scope atomic loads/stores with
-// order-only fences (no L2 flush or invalidate), and every flag carries the
-// launch epoch of the coordinate, so nothing is cleared between steps.
+// Every exchanged value travels as a 16-byte (value, epoch tag) pair with
+// one agent-scope access (no L2 flush or invalidate, no separate flag), so
+// nothing is cleared between steps and O(segments) values move per
+// exchange.
 // Every wait is bounded; a timed-out wait sets the workspace error word and
 // every workgroup leaves at its next wait.
 #include "ss_device.h"
@@ -28,6 +30,20 @@ namespace ss {
 namespace {
 
 using namespace dev;
+
+// Phase timestamps of the first 8 coordinates per workgroup, for
+// performance-analysis builds only (-DSS_TRACE_TIMES).
+#ifdef SS_TRACE_TIMES
+#define SW_TRACE(a, b, jj, slot)                                                    \
+    do {                                                                            \
+        if (threadIdx.x == 0 && (jj) - (a).j_begin < 8)                             \
+            reinterpret_cast<uint64_t *>((a).ws.sw_pre + 8 * (a).ws.max_tiles)     \
+                [((b) * 8 + ((jj) - (a).j_begin)) * 8 + (slot)] =                   \
+                __builtin_amdgcn_s_memrealtime();                                   \
+    } while (0)
+#else
+#define SW_TRACE(a, b, jj, slot) do { } while (0)
+#endif
 
 struct SweepArgs {
     int64_t n;
@@ -52,12 +68,18 @@ struct SweepArgs {
     WsView ws;
 };
 
-// Waits (one thread) until *f == want.  Returns false if the wait gave up or
-// another workgroup already did.
-__device__ bool wait_flag(const uint64_t *f, uint64_t want, WsHeader *hdr)
+// Polls NP pairs until all carry `tag`.  Returns false if the wait gave up
+// or another workgroup already did.
+template <int NP>
+__device__ bool wait_pairs(const u32x4 *p, uint64_t tag, WsHeader *hdr, u32x4 (&r)[NP])
 {
     uint32_t spins = 0;
-    while (ld_flag(f) != want) {
+    for (;;) {
+        ld_pairs<NP>(p, r);
+        bool ok = true;
+#pragma unroll
+        for (int c = 0; c < NP; ++c) ok = ok && pair_tag(r[c]) == tag;
+        if (ok) return true;
         if ((++spins & 31u) == 0 && ld_relaxed_u32(&hdr->error)) return false;
         if (spins > kSpinLimit) {
             __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -65,8 +87,32 @@ __device__ bool wait_flag(const uint64_t *f, uint64_t want, WsHeader *hdr)
         }
         __builtin_amdgcn_s_sleep(1);
     }
-    return true;
 }
+
+// Applies `st` times column jc to eta and e inside the segment; with LDS
+// (s_ep, s_flag) also patches the registers of the owners.
+template <int BLOCK, bool VALS, bool PATCH_LDS>
+__device__ __forceinline__ void apply_step(const SweepArgs &a, int32_t jc, double st,
+                                           int64_t seg0, int64_t chunk0, int64_t chunk1,
+                                           double *s_ep, uint8_t *s_flag)
+{
+    const ColTile cp = col_tile(a.col, jc, chunk0, chunk1);
+    for (int32_t o = cp.lo + (int32_t)threadIdx.x; o < cp.hi; o += BLOCK) {
+        const int32_t k = a.col.rows[cp.cb + o];
+        const double x = VALS ? a.col.vals[cp.cb + o] : 1.0;
+        const double et = a.eta[k] + x * st;
+        const double en = exp(et);
+        a.eta[k] = et;
+        a.e[k] = en;
+        if (PATCH_LDS) {
+            s_ep[k - seg0] = en;
+            lds_flag_or(s_flag, (int32_t)(k - seg0), kFlagPatch);
+        }
+    }
+}
+
+// Upper bound on the number of workgroups (segments) of one sweep.
+constexpr int kMaxSweepBlocks = 512;
 
 template <int BLOCK, int IPT, int MODEL, bool VALS>
 __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
@@ -80,9 +126,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
     __shared__ __attribute__((aligned(16))) uint8_t s_flag[S];
     __shared__ double s_xv[VALS ? S : 1];
     __shared__ double s_ep[S];
+    __shared__ double s_g[FG ? S : 1];
     __shared__ double s_wsum[NW][NC];
-    __shared__ double s_red[NW * 8];
-    __shared__ double s_bc[8];
+    __shared__ double s_wred[NW][3];
+    __shared__ double s_bc[NC];
     __shared__ uint64_t s_ep0;
     __shared__ double s_step;
     __shared__ int s_abort;
@@ -105,11 +152,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
         s_abort = 0;
     }
 
-    // ---- the segment's data into registers for the whole sweep
+    // ---- the segment's data, kept for the whole sweep: e and w in
+    // registers, G(y) in LDS (read only at the ends of event runs)
     double ev[IPT];
     int dk[IPT];
     double wv[FG ? IPT : 1];
-    double gv[FG ? IPT : 1];
     if (cnt == S) {
         const double2 *ep = reinterpret_cast<const double2 *>(a.e + base);
 #pragma unroll
@@ -118,45 +165,39 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
             ev[2 * q] = v.x;
             ev[2 * q + 1] = v.y;
         }
-        uint8_t db[IPT];
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) db[i] = a.d8[base + i];
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) dk[i] = db[i];
         if (FG) {
             const double2 *wp = reinterpret_cast<const double2 *>(a.w_comp + base);
-            const double2 *gp = reinterpret_cast<const double2 *>(a.g_end + base);
 #pragma unroll
             for (int q = 0; q < IPT / 2; ++q) {
                 const double2 v = wp[q];
                 wv[2 * q] = v.x;
                 wv[2 * q + 1] = v.y;
-                const double2 u = gp[q];
-                gv[2 * q] = u.x;
-                gv[2 * q + 1] = u.y;
             }
         }
     } else {
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-            const int64_t k = base + i;
-            const bool ok = k < a.n;
-            ev[i] = ok ? a.e[k] : 0.0;
-            dk[i] = ok ? (int)a.d8[k] : 0;
-            if (FG) {
-                wv[i] = ok ? a.w_comp[k] : 0.0;
-                gv[i] = ok ? a.g_end[k] : 1.0;
-            }
+            const bool ok = base + i < a.n;
+            ev[i] = ok ? a.e[base + i] : 0.0;
+            if (FG) wv[i] = ok ? a.w_comp[base + i] : 0.0;
         }
     }
 #pragma unroll
-    for (int i = 0; i < IPT; ++i)
-        if (dk[i] == 255) dk[i] = a.d32[base + i];
+    for (int i = 0; i < IPT; ++i) {
+        const int64_t k = base + i;
+        const bool ok = k < a.n;
+        int d = ok ? (int)a.d8[k] : 0;
+        if (d == 255) d = a.d32[k];
+        dk[i] = d;
+        if (FG) s_g[tid * IPT + i] = ok ? a.g_end[k] : 1.0;
+    }
     __syncthreads();
     const uint64_t ep0 = s_ep0;
 
     for (int32_t j = a.j_begin; j < a.j_end; ++j) {
         const uint64_t ep = ep0 + (uint64_t)(j - a.j_begin);
+        const uint64_t tag = (ep << 1) | 1u;
+        SW_TRACE(a, b, j, 0);
 
         // ---- column j and the pending step of column j-1 into LDS
         {
@@ -164,39 +205,31 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
             for (int i = tid; i < S / 4; i += BLOCK) f32[i] = 0u;
         }
         __syncthreads();
-        const ColTile cj = col_tile(a.col, j, chunk0, chunk1);
-        for (int32_t o = cj.lo + tid; o < cj.hi; o += BLOCK) {
-            const int32_t r = (int32_t)(a.col.rows[cj.cb + o] - seg0);
-            if (VALS) s_xv[r] = a.col.vals[cj.cb + o];
-            lds_flag_or(s_flag, r, kFlagX);
+        {
+            const ColTile cj = col_tile(a.col, j, chunk0, chunk1);
+            for (int32_t o = cj.lo + tid; o < cj.hi; o += BLOCK) {
+                const int32_t r = (int32_t)(a.col.rows[cj.cb + o] - seg0);
+                if (VALS) s_xv[r] = a.col.vals[cj.cb + o];
+                lds_flag_or(s_flag, r, kFlagX);
+            }
         }
         if (j > a.j_begin) {
             if (tid == 0) {
-                if (wait_flag(a.ws.sflags + b, ((ep - 1) << 1) | 1u, hdr)) {
-                    order_acquire();
-                    s_step = ld_relaxed(a.steps + (j - 1));
-                } else {
+                u32x4 r[1];
+                if (wait_pairs<1>(a.ws.sw_step + b, ((ep - 1) << 1) | 1u, hdr, r))
+                    s_step = pair_value(r[0]);
+                else
                     s_abort = 1;
-                }
             }
             __syncthreads();
+            SW_TRACE(a, b, j, 1);
             if (s_abort) return;
             const double st = s_step;
-            if (st != 0.0) {
-                const ColTile cp = col_tile(a.col, j - 1, chunk0, chunk1);
-                for (int32_t o = cp.lo + tid; o < cp.hi; o += BLOCK) {
-                    const int32_t k = a.col.rows[cp.cb + o];
-                    const double x = VALS ? a.col.vals[cp.cb + o] : 1.0;
-                    const double et = a.eta[k] + x * st;
-                    const double en = exp(et);
-                    a.eta[k] = et;
-                    a.e[k] = en;
-                    s_ep[k - seg0] = en;
-                    lds_flag_or(s_flag, (int32_t)(k - seg0), kFlagPatch);
-                }
-            }
+            if (st != 0.0)
+                apply_step<BLOCK, VALS, true>(a, j - 1, st, seg0, chunk0, chunk1, s_ep, s_flag);
         }
         __syncthreads();
+        SW_TRACE(a, b, j, 2);
         double xv[IPT];
         {
             uint8_t fl[IPT];
@@ -209,175 +242,250 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
             }
         }
 
-        // ---- tuple totals of the thread, block scan, segment aggregate
-        double run[NC];
+        // ---- thread totals, wave scans (DPP), segment aggregate
+        double texcl[NC];
+        {
+            double run[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) run[c] = 0.0;
+            for (int c = 0; c < NC; ++c) run[c] = 0.0;
 #pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            const double ex = ev[i] * xv[i];
-            run[0] += ev[i];
-            run[1] += ex;
-            run[2] += ex * xv[i];
-            if (FG) {
-                const double ew = ev[i] * wv[i];
-                const double exw = ew * xv[i];
-                run[3] += ew;
-                run[4] += exw;
-                run[5] += exw * xv[i];
+            for (int i = 0; i < IPT; ++i) {
+                const double ex = ev[i] * xv[i];
+                run[0] += ev[i];
+                run[1] += ex;
+                run[2] += ex * xv[i];
+                if (FG) {
+                    const double ew = ev[i] * wv[i];
+                    const double exw = ew * xv[i];
+                    run[3] += ew;
+                    run[4] += exw;
+                    run[5] += exw * xv[i];
+                }
             }
-        }
-        double incl[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) incl[c] = run[c];
-        wave_inclusive_scan<NC>(incl);
-        if (lane == kWave - 1) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) s_wsum[w][c] = incl[c];
+            for (int c = 0; c < NC; ++c) {
+                const double inc = dpp_incl_scan(run[c]);
+                texcl[c] = inc - run[c];
+                if (lane == kWave - 1) s_wsum[w][c] = inc;
+            }
         }
         __syncthreads();
-        double texcl[NC];
-        double agg[NC];
+        if (tid == 0) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) t += s_wsum[q][c];
+                st_pair(a.ws.sw_agg + b * 8 + c, t, tag);
+            }
+        }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            double before = 0.0, total = 0.0;
+            double before = 0.0;
 #pragma unroll
-            for (int q = 0; q < NW; ++q) {
+            for (int q = 0; q < NW; ++q)
                 if (q < w) before += s_wsum[q][c];
-                total += s_wsum[q][c];
-            }
-            texcl[c] = before + incl[c] - run[c];
-            agg[c] = total;
+            texcl[c] += before;
         }
+        SW_TRACE(a, b, j, 3);
 
-        // ---- exchange 1: every segment aggregate to every workgroup
-        if (tid == 0) {
-            TileState *ts = a.ws.tiles + b;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) st_relaxed(ts->agg + c, agg[c]);
-            order_release();
-            st_flag(&ts->flag, (ep << 2) | kStateAgg);
-        }
-        double pre[NC];
-        double tot[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int c = 0; c < NC; ++c) pre[c] = 0.0;
-        int bad = 0;
-        for (int q = tid; q < G; q += BLOCK) {
-            const TileState *ts = a.ws.tiles + q;
-            if (!wait_flag(&ts->flag, (ep << 2) | kStateAgg, hdr)) {
-                bad = 1;
-                break;
-            }
-            order_acquire();
-            double v[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) v[c] = ld_relaxed(ts->agg + c);
-            if (q < b) {
-#pragma unroll
-                for (int c = 0; c < NC; ++c) pre[c] += v[c];
-            }
-            if (FG) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) tot[c] += v[3 + c];
-            }
-        }
-        if (__syncthreads_or(bad)) return;
-        {
-            double red[NC + 3];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) red[c] = pre[c];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) red[NC + c] = tot[c];
-            block_sum<NC + 3, BLOCK>(red, s_red);
-            if (tid == 0) {
-#pragma unroll
-                for (int c = 0; c < NC + 3; ++c) s_bc[c] = red[c];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int c = 0; c < NC; ++c) texcl[c] += s_bc[c];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) tot[c] = s_bc[NC + c];
-        }
-
-        // ---- running prefix, transform at run ends, reduction
-        double acc[3] = {0.0, 0.0, 0.0};
-        double Sr[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) Sr[c] = texcl[c];
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            const double ex = ev[i] * xv[i];
-            Sr[0] += ev[i];
-            Sr[1] += ex;
-            Sr[2] += ex * xv[i];
-            if (FG) {
-                const double ew = ev[i] * wv[i];
-                const double exw = ew * xv[i];
-                Sr[3] += ew;
-                Sr[4] += exw;
-                Sr[5] += exw * xv[i];
-            }
-            const int d = dk[i];
-            if (d != 0) {
-                double S0 = Sr[0], S1 = Sr[1], S2 = Sr[2];
-                if (FG) {
-                    const double g = gv[i];
-                    S0 += g * (tot[0] - Sr[3]);
-                    S1 += g * (tot[1] - Sr[4]);
-                    S2 += g * (tot[2] - Sr[5]);
-                }
-                const double r = 1.0 / S0;
-                const double Gk = S1 * r;
-                const double Hk = S2 * r;
-                const double dd = (double)d;
-                acc[0] += dd * Gk;
-                acc[1] += dd * (Hk - Gk * Gk);
-                if (a.want_log) acc[2] += dd * log(S0);
-            }
-        }
-        block_sum<3, BLOCK>(acc, s_red);
-
-        // ---- exchange 2: partials to workgroup 0, step back to everyone
-        const uint64_t ptag = (ep << 1) | 1u;
-        if (tid == 0) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) st_relaxed(a.ws.partials + 4 * b + c, acc[c]);
-            order_release();
-            st_flag(a.ws.pflags + b, ptag);
-        }
+        // ---- exchange 1: workgroup 0 gathers every segment aggregate, scans
+        // them in segment order and hands each workgroup its exclusive
+        // prefix; for Fine-Gray the weighted components are handed over as
+        // total minus exclusive prefix (the suffix sum that starts at the
+        // segment).
         if (b == 0) {
-            double sum[3] = {0.0, 0.0, 0.0};
-            bad = 0;
-            for (int q = tid; q < G; q += BLOCK) {
-                if (!wait_flag(a.ws.pflags + q, ptag, hdr)) {
-                    bad = 1;
-                    break;
-                }
-                order_acquire();
+            constexpr int K = (kMaxSweepBlocks + BLOCK - 1) / BLOCK;
+            double v[K][NC];
+            bool bad = false;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) sum[c] += ld_relaxed(a.ws.partials + 4 * q + c);
+            for (int k = 0; k < K; ++k) {
+                const int q = tid * K + k;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) v[k][c] = 0.0;
+                if (q < G && !bad) {
+                    u32x4 r[NC];
+                    if (wait_pairs<NC>(a.ws.sw_agg + (int64_t)q * 8, tag, hdr, r)) {
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) v[k][c] = pair_value(r[c]);
+                    } else {
+                        bad = true;
+                    }
+                }
             }
             if (__syncthreads_or(bad)) return;
-            block_sum<3, BLOCK>(sum, s_red);
+            // exclusive scan over q = tid*K + k: thread-serial, DPP across
+            // lanes, LDS across waves
+            double tsum[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) t += v[k][c];
+                tsum[c] = t;
+                const double inc = dpp_incl_scan(t);
+                tsum[c] = inc - t;  // exclusive within the wave
+                if (lane == kWave - 1) s_wsum[w][c] = inc;
+            }
+            __syncthreads();
+            double tot3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double before = 0.0, all = 0.0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    if (q < w) before += s_wsum[q][c];
+                    all += s_wsum[q][c];
+                }
+                tsum[c] += before;
+                if (FG && c >= 3) tot3[c - 3] = all;
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int q = tid * K + k;
+                if (q < G) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const double out = (FG && c >= 3) ? tot3[c - 3] - tsum[c] : tsum[c];
+                        st_pair(a.ws.sw_pre + (int64_t)q * 8 + c, out, tag);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NC; ++c) tsum[c] += v[k][c];
+            }
+        }
+        if (tid == 0) {
+            u32x4 r[NC];
+            if (wait_pairs<NC>(a.ws.sw_pre + b * 8, tag, hdr, r)) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) s_bc[c] = pair_value(r[c]);
+            } else {
+                s_abort = 1;
+            }
+        }
+        __syncthreads();
+        SW_TRACE(a, b, j, 4);
+        if (s_abort) return;
+
+        // ---- running prefix, transform at run ends, reduction.  For
+        // Fine-Gray R holds the weighted sums over the positions after the
+        // current one (suffix sums, exclusive).
+        double acc[3] = {0.0, 0.0, 0.0};
+        {
+            double Sr[3];
+            double R[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Sr[c] = texcl[c] + s_bc[c];
+            if (FG) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) R[c] = s_bc[3 + c] - texcl[3 + c];
+            }
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const double ex = ev[i] * xv[i];
+                Sr[0] += ev[i];
+                Sr[1] += ex;
+                Sr[2] += ex * xv[i];
+                if (FG) {
+                    const double ew = ev[i] * wv[i];
+                    const double exw = ew * xv[i];
+                    R[0] -= ew;
+                    R[1] -= exw;
+                    R[2] -= exw * xv[i];
+                }
+                const int d = dk[i];
+                if (d != 0) {
+                    double S0 = Sr[0], S1 = Sr[1], S2 = Sr[2];
+                    if (FG) {
+                        const double g = s_g[tid * IPT + i];
+                        S0 += g * R[0];
+                        S1 += g * R[1];
+                        S2 += g * R[2];
+                    }
+                    const double r = 1.0 / S0;
+                    const double Gk = S1 * r;
+                    const double Hk = S2 * r;
+                    const double dd = (double)d;
+                    acc[0] += dd * Gk;
+                    acc[1] += dd * (Hk - Gk * Gk);
+                    if (a.want_log) acc[2] += dd * log(S0);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[c] = dpp_wave_sum(acc[c]);
+            if (lane == 0) s_wred[w][c] = acc[c];
+        }
+        __syncthreads();
+
+        // ---- exchange 2: partials to workgroup 0, step back to everyone
+        if (tid == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) t += s_wred[q][c];
+                st_pair(a.ws.sw_part + b * 4 + c, t, tag);
+            }
+        }
+        SW_TRACE(a, b, j, 5);
+        if (b == 0) {
+            constexpr int K = (kMaxSweepBlocks + BLOCK - 1) / BLOCK;
+            double sum[3] = {0.0, 0.0, 0.0};
+            bool bad = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int q = tid * K + k;
+                if (q < G && !bad) {
+                    u32x4 r[3];
+                    if (wait_pairs<3>(a.ws.sw_part + (int64_t)q * 4, tag, hdr, r)) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) sum[c] += pair_value(r[c]);
+                    } else {
+                        bad = true;
+                    }
+                }
+            }
+            if (__syncthreads_or(bad)) return;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                sum[c] = dpp_wave_sum(sum[c]);
+                if (lane == 0) s_wred[w][c] = sum[c];
+            }
+            __syncthreads();
             if (tid == 0) {
-                const double g1 = a.c[j] - sum[0];
-                const double g2 = -sum[1];
+                double tot[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) t += s_wred[q][c];
+                    tot[c] = t;
+                }
+                const double g1 = a.c[j] - tot[0];
+                const double g2 = -tot[1];
                 double bj = a.beta[j], dj = a.delta[j], st = 0.0;
                 ccd_apply(g1, g2, a.penalty, a.lambda, &bj, &dj, &st);
                 a.beta[j] = bj;
                 a.delta[j] = dj;
-                st_relaxed(a.steps + j, st);
+                a.steps[j] = st;
                 if (a.g12_out) {
                     a.g12_out[3 * j] = g1;
                     a.g12_out[3 * j + 1] = g2;
-                    a.g12_out[3 * j + 2] = sum[2];
+                    a.g12_out[3 * j + 2] = tot[2];
                 }
-                order_release();
+                s_step = st;
             }
             __syncthreads();
-            for (int q = tid; q < G; q += BLOCK) st_flag(a.ws.sflags + q, ptag);
+            SW_TRACE(a, b, j, 6);
+            const double st = s_step;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int q = tid * K + k;
+                if (q < G) st_pair(a.ws.sw_step + q, st, tag);
+            }
+            SW_TRACE(a, b, j, 7);
         }
     }
 
@@ -385,26 +493,16 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
     const int32_t jl = a.j_end - 1;
     const uint64_t ep_last = ep0 + (uint64_t)(jl - a.j_begin);
     if (tid == 0) {
-        if (wait_flag(a.ws.sflags + b, (ep_last << 1) | 1u, hdr)) {
-            order_acquire();
-            s_step = ld_relaxed(a.steps + jl);
-        } else {
+        u32x4 r[1];
+        if (wait_pairs<1>(a.ws.sw_step + b, (ep_last << 1) | 1u, hdr, r))
+            s_step = pair_value(r[0]);
+        else
             s_abort = 1;
-        }
     }
     __syncthreads();
     if (s_abort) return;
-    const double st = s_step;
-    if (st != 0.0) {
-        const ColTile cp = col_tile(a.col, jl, chunk0, chunk1);
-        for (int32_t o = cp.lo + tid; o < cp.hi; o += BLOCK) {
-            const int32_t k = a.col.rows[cp.cb + o];
-            const double x = VALS ? a.col.vals[cp.cb + o] : 1.0;
-            const double et = a.eta[k] + x * st;
-            a.eta[k] = et;
-            a.e[k] = exp(et);
-        }
-    }
+    if (s_step != 0.0)
+        apply_step<BLOCK, VALS, false>(a, jl, s_step, seg0, chunk0, chunk1, s_ep, s_flag);
     // every workgroup read the epoch before exchange 1 of the first
     // coordinate, which workgroup 0 waited for
     if (b == 0 && tid == 0)
@@ -435,9 +533,12 @@ void *pick_kernel(int model, bool vals)
 
 void *kernel_for(int block, int ipt, int model, bool vals)
 {
-    if (block == 512 && ipt == 4) return pick_kernel<512, 4>(model, vals);
+    if (block == 256 && ipt == 8) return pick_kernel<256, 8>(model, vals);
+    if (block == 256 && ipt == 16) return pick_kernel<256, 16>(model, vals);
     if (block == 512 && ipt == 8) return pick_kernel<512, 8>(model, vals);
-    if (block == 512 && ipt == 16) return pick_kernel<512, 16>(model, vals);
+    // 8192-position segments: Cox only (Fine-Gray's extra LDS does not fit)
+    if (block == 512 && ipt == 16 && model == SS_COX)
+        return vals ? kernel_ptr<512, 16, SS_COX, true>() : kernel_ptr<512, 16, SS_COX, false>();
     return nullptr;
 }
 
@@ -445,9 +546,9 @@ void *kernel_for(int block, int ipt, int model, bool vals)
 
 int32_t launch_sweep_persistent(const SweepCall &call, const WsView &ws, hipStream_t s)
 {
-    // segments of 2048, 4096 or 8192 positions; LDS holds a segment's flags,
-    // column values and patched e (8192 positions: 136 KB of 160 KB)
-    static const Shape shapes[] = {{512, 4}, {512, 8}, {512, 16}};
+    // segments of 2048 to 8192 positions; LDS holds a segment's flags,
+    // column values, patched e and (Fine-Gray) G(y)
+    static const Shape shapes[] = {{256, 8}, {256, 16}, {512, 8}, {512, 16}};
     int dev = 0;
     SS_HIP_CHECK(hipGetDevice(&dev));
     int cus = 0, coop = 0;
@@ -460,7 +561,7 @@ int32_t launch_sweep_persistent(const SweepCall &call, const WsView &ws, hipStre
         const int64_t G = ceil_div(call.n, seg);
         // a few hundred segments at most: the all-to-all exchange reads G
         // aggregates per workgroup
-        if (G > 512 || G > ws.max_tiles) continue;
+        if (G > kMaxSweepBlocks || G > ws.max_tiles) continue;
         void *k = kernel_for(sh.block, sh.ipt, call.model, vals);
         if (!k) continue;
         int per_cu = 0;
