@@ -99,13 +99,30 @@ def roofline(torch, ss, gen, n, reps):
         if t.get("kernel_sha") == kernel_hash() and t.get("n") == n:
             traffic = t.get("bytes_per_launch")
     err = prob.workspace_error()
+    copy_gbs = copy_peak_gbs(torch)
+    ipt = 4 if n <= 4 << 20 else 8 if n <= 32 << 20 else 16  # tile shape the library picks
     del prob
     torch.cuda.empty_cache()
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_fused<256,8,cox,vals>", "n": n, "nnz": nnz,
+            "kernel": "k_fused<256,%d,cox,vals>" % ipt, "n": n, "nnz": nnz,
             "algo_bytes_per_launch": algo, "avg_us": round(us, 2), "reps": reps,
+            "copy_peak_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
             "wait_errors": err}
+
+
+def copy_peak_gbs(torch):
+    """Measured device-to-device copy rate (read + write bytes), 1 GiB each way."""
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    us = event_time_us(torch, lambda: b.copy_(a), 10)
+    nbytes = 2 * a.numel() * 8
+    del a, b
+    torch.cuda.empty_cache()
+    return nbytes / (us * 1e-6) / 1e9
 
 
 def context(torch, ss, gen):

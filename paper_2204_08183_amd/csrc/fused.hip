@@ -34,48 +34,70 @@ using namespace dev;
 #define SS_TRACE(ws, tile, slot)                                                   \
     do {                                                                           \
         if (threadIdx.x == 0)                                                      \
-            reinterpret_cast<uint64_t *>((ws).sw_pre + 8 * (ws).max_tiles)         \
+            reinterpret_cast<uint64_t *>((ws).sw_bc + 8 * (ws).max_tiles)          \
                 [(tile) * 8 + (slot)] = __builtin_amdgcn_s_memrealtime();          \
     } while (0)
 #else
 #define SS_TRACE(ws, tile, slot) do { } while (0)
 #endif
 
-template <int NC>
-struct Vec {
-    double v[NC];
+// ---------------------------------------------------------------- look-back
+// Decoupled look-back (single-pass chained scan, Sec. 2.6).  A tile's slot
+// holds a flag word (epoch << 2) | state (1: aggregate published, 2:
+// inclusive prefix published) and the two payloads; a payload is written
+// before its flag (release order) and read after it (acquire order).
+//
+// Wave 0 of the tile inspects its predecessors kLbK * 64 at a time (kLbK
+// flags per lane, all in flight together) and stops at the nearest
+// inclusive prefix; payloads are loaded only for the predecessors needed.
+// Polling by one wave keeps the flag traffic of the tiles waiting at once
+// small next to the data stream (all four waves polling was measured
+// slower).  Every predecessor started earlier (workgroups start in index
+// order on each XCD) and publishes its aggregate without waiting on anyone,
+// so the wait ends; it is bounded all the same.
+struct alignas(128) LbSlot {
+    uint64_t flag;
+    double agg[kMaxComp];
+    double inc[kMaxComp];
 };
 
-// Decoupled look-back (single-pass chained scan, Sec. 2.6): wave 0 of tile
-// `tile` inspects its predecessors kLbK*64 at a time (kLbK flags per lane,
-// all in flight together) and stops at the nearest inclusive prefix.
-// Returns the tile's exclusive prefix in every lane of wave 0.  Every
-// predecessor started earlier (workgroups start in index order on each
-// XCD) and publishes its aggregate without waiting on anyone, so the wait
-// ends; it is bounded all the same.
-constexpr int kLbK = 4;
-
+// Wave 0, lane 0: payload, then flag.
 template <int NC>
-__device__ void look_back(const TileState *tiles, int64_t tile, uint64_t epoch,
-                          WsHeader *hdr, double (&excl)[NC])
+__device__ __forceinline__ void publish_lb(LbSlot *slot, const double (&v)[NC], bool inclusive,
+                                           uint64_t epoch)
 {
+    double *dst = inclusive ? slot->inc : slot->agg;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) st_relaxed(dst + c, v[c]);
+    order_release();
+    st_flag(&slot->flag, (epoch << 2) | (inclusive ? kStateInc : kStateAgg));
+}
+
+// Wave 0 only; the exclusive prefix is returned in every lane.  Returns
+// false if the wait gave up (the error word is then set).
+template <int NC>
+__device__ bool look_back(const LbSlot *lb, int64_t tile, uint64_t epoch, WsHeader *hdr,
+                          double (&excl)[NC])
+{
+    constexpr int kLbK = NC > 3 ? 2 : 4;  // Fine-Gray: twice the payload
     const int lane = lane_id();
 #pragma unroll
     for (int c = 0; c < NC; ++c) excl[c] = 0.0;
-    int64_t top = tile - 1;
+    // tile indices fit in 32 bits (n < 2^31, tiles of at least 1024)
+    int32_t top = (int32_t)tile - 1;
     uint32_t spins = 0;
     while (top >= 0) {
-        uint64_t st[kLbK];
-        int found = -1;  // sub-window holding the nearest inclusive prefix
+        int st[kLbK];
+        int found = -1;  // window holding the nearest inclusive prefix
         // every lane runs the same iterations, so the loop stays wave-uniform
         for (;;) {
 #pragma unroll
             for (int q = 0; q < kLbK; ++q) {
-                const int64_t t = top - lane - (int64_t)kWave * q;
-                st[q] = kStateInc;  // before tile 0: an empty inclusive prefix
+                const int32_t t = top - lane - kWave * q;
+                st[q] = (int)kStateInc;  // before tile 0: an empty inclusive prefix
                 if (t >= 0) {
-                    const uint64_t f = ld_flag(&tiles[t].flag);
-                    st[q] = (f >> 2) == epoch ? (f & 3u) : 0u;
+                    const uint64_t f = ld_flag(&lb[t].flag);
+                    st[q] = (f >> 2) == epoch ? (int)(f & 3u) : 0;
                 }
             }
             bool ready = true;
@@ -84,14 +106,15 @@ __device__ void look_back(const TileState *tiles, int64_t tile, uint64_t epoch,
             for (int q = 0; q < kLbK; ++q) {
                 if (ready && found < 0) {
                     if (__any(st[q] == 0)) ready = false;
-                    else if (__any(st[q] == kStateInc)) found = q;
+                    else if (__any(st[q] == (int)kStateInc)) found = q;
                 }
             }
             if (ready) break;
             if (++spins > kSpinLimit) {
-                if (lane == 0) __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-                return;
+                if (lane == 0)
+                    __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                return false;
             }
             __builtin_amdgcn_s_sleep(1);
         }
@@ -100,14 +123,14 @@ __device__ void look_back(const TileState *tiles, int64_t tile, uint64_t epoch,
         double pay[kLbK][NC];
 #pragma unroll
         for (int q = 0; q < kLbK; ++q) {
-            const int64_t t = top - lane - (int64_t)kWave * q;
+            const int32_t t = top - lane - kWave * q;
             bool take = q <= qmax && t >= 0;
             if (q == found) {
-                const uint64_t m = __ballot(st[q] == kStateInc);
+                const uint64_t m = __ballot(st[q] == (int)kStateInc);
                 take = take && lane <= __ffsll((unsigned long long)m) - 1;
             }
-            const double *src = st[q] == kStateInc ? tiles[take ? t : 0].inc
-                                                   : tiles[take ? t : 0].agg;
+            const LbSlot *sl = lb + (take ? t : 0);
+            const double *src = st[q] == (int)kStateInc ? sl->inc : sl->agg;
 #pragma unroll
             for (int c = 0; c < NC; ++c) pay[q][c] = take ? ld_relaxed(src + c) : 0.0;
         }
@@ -119,94 +142,128 @@ __device__ void look_back(const TileState *tiles, int64_t tile, uint64_t epoch,
             excl[c] += wave_sum(v);
         }
         if (found >= 0) break;
-        top -= (int64_t)kWave * kLbK;
+        top -= kWave * kLbK;
     }
+    return true;
 }
 
+// Lanes 0 .. NC-1 of the calling wave store one pair each.
 template <int NC>
-__device__ __forceinline__ void publish(TileState *ts, const double (&val)[NC],
-                                        bool inclusive, uint64_t epoch)
+__device__ __forceinline__ void publish_pairs(u32x4 *slot, const double (&v)[NC],
+                                              uint64_t tag)
 {
-    double *dst = inclusive ? ts->inc : ts->agg;
+    const int lane = lane_id();
+    double x = v[0];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) st_relaxed(dst + c, val[c]);
-    order_release();  // the payload is at the coherence point before the flag
-    st_flag(&ts->flag, (epoch << 2) | (inclusive ? kStateInc : kStateAgg));
+    for (int c = 1; c < NC; ++c)
+        if (lane == c) x = v[c];
+    if (lane < NC) st_pair(slot + lane, x, tag);
 }
 
-// The last workgroup of a launch waits until every tile has published its
-// partial sums (flag == tag), U flags in flight per thread, then adds the
-// partials in tile order (deterministic for given partials).  Returns false
-// if a bounded wait gave up.
-template <int BLOCK>
-__device__ bool gather_partials(const double *partials, const uint64_t *pflags,
-                                int64_t ntiles, uint64_t tag, WsHeader *hdr, double (&acc)[3])
+// Polls three pairs until all carry `tag`; false if the wait gave up (then
+// the error word is set) or another wait already did.
+__device__ __forceinline__ bool poll_pairs3(const u32x4 *p, uint64_t tag, WsHeader *hdr,
+                                            u32x4 (&r)[3])
 {
-    constexpr int U = 8;
-    bool ok = true;
-    acc[0] = acc[1] = acc[2] = 0.0;
-    for (int64_t t0 = threadIdx.x; t0 < ntiles; t0 += (int64_t)BLOCK * U) {
-        uint32_t spins = 0;
-        for (;;) {
-            bool ready = true;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t t = t0 + (int64_t)u * BLOCK;
-                if (t < ntiles && ld_flag(pflags + t) != tag) ready = false;
-            }
-            if (ready) break;
-            if (++spins > kSpinLimit) {
-                __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = false;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
+    uint32_t spins = 0;
+    for (;;) {
+        ld_pairs<3>(p, r);
+        if (pair_tag(r[0]) == tag && pair_tag(r[1]) == tag && pair_tag(r[2]) == tag)
+            return true;
+        if (++spins > kSpinLimit || ((spins & 31u) == 0 && ld_relaxed_u32(&hdr->error))) {
+            __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
         }
-        order_acquire();
-        double v[U][3];
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// ------------------------------------------------------ partial sums
+// Two-level reduction of the per-tile partial sums, in a fixed order (so
+// the result does not depend on timing): every tile publishes its three
+// sums as pairs; the last tile of each group of kGroup tiles waits for its
+// group (wave 0, one tile per lane) and publishes the group's sums; the
+// last tile of the launch waits for the groups and adds them.  Only tiles
+// with smaller indices are ever waited for.
+//
+// tile_sum: the calling tile's sums (valid in every thread).  In the last
+// tile, `total` (thread 0) receives the launch total; a wait that gives up
+// sets the error word and leaves its share out.
+template <int BLOCK>
+__device__ void reduce_partials(u32x4 *part, u32x4 *gpart, int64_t tile, int64_t ntiles,
+                                uint64_t tag, WsHeader *hdr, const double (&tile_sum)[3],
+                                double (&total)[3], double *s_red)
+{
+    const int lane = lane_id();
+    const int tid = threadIdx.x;
+    const bool last = tile == ntiles - 1;
+    const bool leader = last || (tile % kGroup) == kGroup - 1;
+    if (tid < kWave) {
+        if (!leader) {
+            publish_pairs<3>(part + tile * 4, tile_sum, tag);
+        } else {
+            // wave 0 of a group leader: tiles g0 .. tile, this tile's own
+            // sums from registers
+            const int64_t g0 = tile - tile % kGroup;
+            const int64_t t = g0 + lane;
+            double v[3] = {0.0, 0.0, 0.0};
+            if (t < tile) {
+                u32x4 r[3];
+                if (poll_pairs3(part + t * 4, tag, hdr, r)) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t t = t0 + (int64_t)u * BLOCK;
+                    for (int c = 0; c < 3; ++c) v[c] = pair_value(r[c]);
+                }
+            } else if (t == tile) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) v[u][c] = t < ntiles ? ld_relaxed(partials + 4 * t + c) : 0.0;
-        }
+                for (int c = 0; c < 3; ++c) v[c] = tile_sum[c];
+            }
+            double g[3];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+            for (int c = 0; c < 3; ++c) g[c] = dpp_wave_sum(v[c]);
+            if (!last) publish_pairs<3>(gpart + (tile / kGroup) * 4, g, tag);
+            if (lane == 0) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc[c] += v[u][c];
+                for (int c = 0; c < 3; ++c) s_red[c] = g[c];
+            }
         }
     }
-    return ok;
-}
-
-// Publishes one tile's partial sums (thread 0).
-__device__ __forceinline__ void publish_partial(double *partials, uint64_t *pflags, int64_t tile,
-                                                const double (&acc)[3], uint64_t tag)
-{
+    if (!last) return;
+    __syncthreads();
+    // the last tile: groups 0 .. ngroups-2 from memory, its own from LDS
+    const int64_t ngroups = tile / kGroup + 1;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t q = tid; q < ngroups - 1; q += BLOCK) {
+        u32x4 r[3];
+        if (!poll_pairs3(gpart + q * 4, tag, hdr, r)) break;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) st_relaxed(partials + 4 * tile + c, acc[c]);
-    order_release();
-    st_flag(pflags + tile, tag);
+        for (int c = 0; c < 3; ++c) acc[c] += pair_value(r[c]);
+    }
+    double own[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) own[c] = s_red[c];
+    block_sum<3, BLOCK>(acc, s_red + 4);
+    if (tid == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) total[c] = acc[c] + own[c];
+    }
 }
 
-// Last tile: sum of the per-tile partials, then g', g'', the likelihood or
-// the coordinate update, then the launch epoch moves on.
+// Last tile: g', g'', the likelihood or the coordinate update from the
+// launch totals (thread 0), then the launch epoch moves on.
 template <int BLOCK>
-__device__ void finish(const FusedCall &a, const WsView &ws, int64_t ntiles, uint64_t epoch,
-                       double *s_red)
+__device__ void finish(const FusedCall &a, const WsView &ws, uint64_t epoch,
+                       const double (&tot)[3], double *s_red)
 {
-    double acc[3];
-    gather_partials<BLOCK>(ws.partials, ws.pflags, ntiles, (epoch << 1) | 1u, ws.hdr, acc);
     double btc = 0.0;
     if (a.beta_ll) {
         for (int64_t q = threadIdx.x; q < a.p; q += BLOCK) btc += a.beta_ll[q] * a.c[q];
     }
-    double all[4] = {acc[0], acc[1], acc[2], btc};
-    block_sum<4, BLOCK>(all, s_red);
+    double all[1] = {btc};
+    block_sum<1, BLOCK>(all, s_red);
     if (threadIdx.x == 0) {
-        const double A = all[0], B = all[1], L = all[2];
+        const double A = tot[0], B = tot[1], L = tot[2];
         if (a.beta_ll) {
-            a.out[0] = all[3] - L;
+            a.out[0] = all[0] - L;
         } else {
             const double g1 = a.c[a.j] - A;
             const double g2 = -B;
@@ -223,19 +280,24 @@ __device__ void finish(const FusedCall &a, const WsView &ws, int64_t ntiles, uin
     }
 }
 
-// Stages one tile (positions [t0, t0+cnt)) in registers: e (patched by the
-// pending step of column jprev, which is also written back to eta and e),
-// the weights w (Fine-Gray), the event counts d, and x of column j.  All
-// independent loads are issued together; the column and the patch travel
-// through LDS flag bytes.  s_flag must be zero and visible on entry; ends
-// with the tile's data in registers after one workgroup barrier.
+// Stages one tile (positions [t0, t0+cnt)): e (patched by the pending step
+// of column jprev, which is also written back to eta and e), the weights w
+// (Fine-Gray) and the event counts d (one byte each) go to registers; of
+// column j only a bit per position stays in a register (returned: bit i for
+// position base + i) and, with VALS, the value sits in LDS at
+// s_xv[i * BLOCK + tid] (lane-consecutive, so reading it back is free of
+// bank conflicts).  All independent loads are issued together; the sparse
+// column and the patch travel through LDS flag bytes.  s_flag must be zero
+// and visible on entry; ends after one workgroup barrier.
 template <int BLOCK, int IPT, bool WANT_W, bool VALS, bool PREV, bool WANT_D>
-__device__ __forceinline__ void stage_tile(const FusedCall &a, int64_t t0, int64_t cnt,
-                                           int64_t chunk0, int64_t chunk1, uint8_t *s_flag,
-                                           double *s_xv, double *s_ep, double (&ev)[IPT],
-                                           double (&xv)[IPT],
-                                           double (&wv)[WANT_W ? IPT : 1], int (&dk)[IPT])
+__device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, int64_t cnt,
+                                               int64_t chunk0, int64_t chunk1,
+                                               uint8_t *s_flag, double *s_xv, double *s_ep,
+                                               double (&ev)[IPT],
+                                               double (&wv)[WANT_W ? IPT : 1],
+                                               uint32_t (&dw)[(IPT + 3) / 4])
 {
+    static_assert(IPT <= 32 && (IPT & (IPT - 1)) == 0, "IPT: a power of two up to 32");
     constexpr int TILE = BLOCK * IPT;
     const int tid = threadIdx.x;
     ColTile cj = {0, 0, 0};
@@ -258,18 +320,15 @@ __device__ __forceinline__ void stage_tile(const FusedCall &a, int64_t t0, int64
         }
         if (WANT_D) {
             if (IPT >= 8) {
-                const uint64_t *dp = reinterpret_cast<const uint64_t *>(a.d8 + base);
+                const uint2 *dp = reinterpret_cast<const uint2 *>(a.d8 + base);
 #pragma unroll
                 for (int q = 0; q < IPT / 8; ++q) {
-                    const uint64_t dd = dp[q];
-#pragma unroll
-                    for (int b = 0; b < 8; ++b)
-                        dk[(8 * q + b) % IPT] = (int)((dd >> (8 * b)) & 255u);
+                    const uint2 dd = dp[q];
+                    dw[2 * q] = dd.x;
+                    dw[2 * q + 1] = dd.y;
                 }
             } else {
-                const uint32_t dd = *reinterpret_cast<const uint32_t *>(a.d8 + base);
-#pragma unroll
-                for (int b = 0; b < IPT; ++b) dk[b] = (int)((dd >> (8 * b)) & 255u);
+                dw[0] = *reinterpret_cast<const uint32_t *>(a.d8 + base);
             }
         }
         if (WANT_W) {
@@ -283,23 +342,35 @@ __device__ __forceinline__ void stage_tile(const FusedCall &a, int64_t t0, int64
         }
     } else {
 #pragma unroll
+        for (int q = 0; q < (IPT + 3) / 4; ++q) dw[q] = 0u;
+#pragma unroll
         for (int i = 0; i < IPT; ++i) {
             const int64_t k = base + i;
             const bool ok = k < a.n;
             ev[i] = ok ? a.e[k] : 0.0;
-            if (WANT_D) dk[i] = ok ? (int)a.d8[k] : 0;
+            if (WANT_D && ok) dw[i / 4] |= (uint32_t)a.d8[k] << (8 * (i % 4));
             if (WANT_W) wv[i] = ok ? a.w_comp[k] : 0.0;
         }
     }
     // a column with a non-zero at every position of a full tile is read
-    // straight into registers (no scatter)
-    const double *vdense = VALS ? a.col.vals + cj.cb + cj.lo + tid * IPT : nullptr;
-    const bool dense = VALS && full && (int64_t)(cj.hi - cj.lo) == cnt &&
-                       ((uintptr_t)(a.col.vals + cj.cb + cj.lo) & 15u) == 0;
-    if (!dense) {
+    // straight from its value array (no scatter, no flags)
+    const bool dense = full && (int64_t)(cj.hi - cj.lo) == cnt &&
+                       (!VALS || ((uintptr_t)(a.col.vals + cj.cb + cj.lo) & 15u) == 0);
+    if (dense) {
+        if (VALS) {
+            const double2 *vp =
+                reinterpret_cast<const double2 *>(a.col.vals + cj.cb + cj.lo + tid * IPT);
+#pragma unroll
+            for (int q = 0; q < IPT / 2; ++q) {
+                const double2 v = vp[q];
+                s_xv[(2 * q) * BLOCK + tid] = v.x;
+                s_xv[(2 * q + 1) * BLOCK + tid] = v.y;
+            }
+        }
+    } else {
         for (int32_t o = cj.lo + tid; o < cj.hi; o += BLOCK) {
             const int32_t r = (int32_t)(a.col.rows[cj.cb + o] - t0);
-            if (VALS) s_xv[r] = a.col.vals[cj.cb + o];
+            if (VALS) s_xv[(r % IPT) * BLOCK + r / IPT] = a.col.vals[cj.cb + o];
             lds_flag_or(s_flag, r, kFlagX);
         }
     }
@@ -318,26 +389,25 @@ __device__ __forceinline__ void stage_tile(const FusedCall &a, int64_t t0, int64
     __syncthreads();
     uint8_t fl[IPT];
     lds_bytes<IPT>(s_flag + tid * IPT, fl);
-    if (dense) {
-        const double2 *vp = reinterpret_cast<const double2 *>(vdense);
+    uint32_t xbits = 0u;
 #pragma unroll
-        for (int q = 0; q < IPT / 2; ++q) {
-            const double2 v = vp[q];
-            xv[2 * q] = v.x;
-            xv[2 * q + 1] = v.y;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            if (VALS) xv[i] = (fl[i] & kFlagX) ? s_xv[tid * IPT + i] : 0.0;
-            else xv[i] = (fl[i] & kFlagX) ? 1.0 : 0.0;
-        }
-    }
+    for (int i = 0; i < IPT; ++i) xbits |= (uint32_t)(fl[i] & kFlagX) << i;
+    if (dense) xbits = IPT == 32 ? ~0u : (1u << IPT) - 1u;
     if (PREV) {
 #pragma unroll
         for (int i = 0; i < IPT; ++i)
             if (fl[i] & kFlagPatch) ev[i] = s_ep[tid * IPT + i];
     }
+    return xbits;
+}
+
+// x of column j at position base + i of this thread (see stage_tile).
+template <int BLOCK, bool VALS>
+__device__ __forceinline__ double x_at(uint32_t xbits, int i, const double *s_xv)
+{
+    const bool nz = (xbits >> i) & 1u;
+    if (VALS) return nz ? s_xv[i * BLOCK + threadIdx.x] : 0.0;
+    return nz ? 1.0 : 0.0;
 }
 
 // The fused scan -> transform -> reduce kernel (one coordinate).
@@ -358,6 +428,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
     __shared__ double s_wsum[NW][NC];
     __shared__ double s_excl[NC];
     __shared__ double s_red[NW * 4];
+    __shared__ double s_tsum[3];
     __shared__ uint64_t s_epoch;
 
     const int tid = threadIdx.x;
@@ -385,11 +456,10 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
     // ---- 2-4. tile data, column j and the pending update into registers
     const int64_t base = t0 + (int64_t)tid * IPT;
     double ev[IPT];
-    double xv[IPT];
     double wv[MODEL == SS_FINE_GRAY ? IPT : 1];
-    int dk[IPT];
-    stage_tile<BLOCK, IPT, MODEL == SS_FINE_GRAY, VALS, PREV, true>(
-        a, t0, cnt, chunk0, chunk1, s_flag, s_xv, s_ep, ev, xv, wv, dk);
+    uint32_t dw[(IPT + 3) / 4];  // event counts, one byte per position
+    const uint32_t xbits = stage_tile<BLOCK, IPT, MODEL == SS_FINE_GRAY, VALS, PREV, true>(
+        a, t0, cnt, chunk0, chunk1, s_flag, s_xv, s_ep, ev, wv, dw);
     SS_TRACE(ws, tile, 1);
 
     // ---- 5. thread totals of the tuple
@@ -398,16 +468,17 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
     for (int c = 0; c < NC; ++c) run[c] = 0.0;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const double ex = ev[i] * xv[i];
+        const double x = x_at<BLOCK, VALS>(xbits, i, s_xv);
+        const double ex = ev[i] * x;
         run[0] += ev[i];
         run[1] += ex;
-        run[2] += ex * xv[i];
+        run[2] += ex * x;
         if (MODEL == SS_FINE_GRAY) {
             const double ew = ev[i] * wv[i];
-            const double exw = ew * xv[i];
+            const double exw = ew * x;
             run[3] += ew;
             run[4] += exw;
-            run[5] += exw * xv[i];
+            run[5] += exw * x;
         }
     }
 
@@ -438,31 +509,41 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
     // ---- 7. decoupled look-back for the tile's exclusive prefix
     SS_TRACE(ws, tile, 2);
     if (w == 0) {
-        TileState *ts = ws.tiles + tile;
+        LbSlot *lb = reinterpret_cast<LbSlot *>(ws.lb);
+        double ex[NC];
         if (tile == 0) {
-            if (lane == 0) {
-                publish<NC>(ts, agg, true, epoch);
+            if (lane == 0) publish_lb<NC>(lb, agg, true, epoch);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) s_excl[c] = 0.0;
-            }
+            for (int c = 0; c < NC; ++c) ex[c] = 0.0;
         } else {
-            if (lane == 0) publish<NC>(ts, agg, false, epoch);
-            double ex[NC];
-            look_back<NC>(ws.tiles, tile, epoch, ws.hdr, ex);
+            if (lane == 0) publish_lb<NC>(lb + tile, agg, false, epoch);
+            // a wait that gives up has set the error word; the launch still
+            // runs to its end
+            (void)look_back<NC>(lb, tile, epoch, ws.hdr, ex);
             if (lane == 0) {
                 double inc[NC];
 #pragma unroll
                 for (int c = 0; c < NC; ++c) inc[c] = ex[c] + agg[c];
-                publish<NC>(ts, inc, true, epoch);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) s_excl[c] = ex[c];
+                publish_lb<NC>(lb + tile, inc, true, epoch);
             }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) s_excl[c] = ex[c];
         }
     }
     __syncthreads();
     SS_TRACE(ws, tile, 3);
 #pragma unroll
     for (int c = 0; c < NC; ++c) texcl[c] += s_excl[c];
+    // the products of step 5 are recomputed below rather than kept live
+    // across the look-back (registers bound how many tiles a CU holds)
+    uint32_t xb = xbits;
+    asm volatile("" : "+v"(xb));
+    if (MODEL == SS_FINE_GRAY) {
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) asm volatile("" : "+v"(wv[i]));
+    }
 
     double tot[3] = {0.0, 0.0, 0.0};
     if (MODEL == SS_FINE_GRAY) {
@@ -472,23 +553,25 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
 
     // ---- 8. running prefix, transform at run ends, reduction
     double acc[3] = {0.0, 0.0, 0.0};
+    LogSum lsum;
     double S[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) S[c] = texcl[c];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const double ex = ev[i] * xv[i];
+        const double x = x_at<BLOCK, VALS>(xb, i, s_xv);
+        const double ex = ev[i] * x;
         S[0] += ev[i];
         S[1] += ex;
-        S[2] += ex * xv[i];
+        S[2] += ex * x;
         if (MODEL == SS_FINE_GRAY) {
             const double ew = ev[i] * wv[i];
-            const double exw = ew * xv[i];
+            const double exw = ew * x;
             S[3] += ew;
             S[4] += exw;
-            S[5] += exw * xv[i];
+            S[5] += exw * x;
         }
-        int d = dk[i];
+        int d = (int)((dw[i / 4] >> (8 * (i % 4))) & 255u);
         if (d != 0) {
             const int64_t k = base + i;
             if (d == 255) d = a.d32[k];
@@ -505,14 +588,23 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
             const double dd = (double)d;
             acc[0] += dd * G;
             acc[1] += dd * (H - G * G);
-            if (a.want_log) acc[2] += dd * log(S0);
+            if (a.want_log) lsum.add(S0, d);
         }
     }
+    if (a.want_log) acc[2] = lsum.value();
     block_sum<3, BLOCK>(acc, s_red);
-    if (tid == 0) publish_partial(ws.partials, ws.pflags, tile, acc, (epoch << 1) | 1u);
+    if (tid == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s_tsum[c] = acc[c];
+    }
+    __syncthreads();
+    const double tsum[3] = {s_tsum[0], s_tsum[1], s_tsum[2]};
+    double total[3];
+    reduce_partials<BLOCK>(ws.part, ws.gpart, tile, ntiles, (epoch << 1) | 1u, ws.hdr, tsum,
+                           total, s_red);
     SS_TRACE(ws, tile, 4);
     if (tile == ntiles - 1) {
-        finish<BLOCK>(a, ws, ntiles, epoch, s_red);
+        finish<BLOCK>(a, ws, epoch, total, s_red);
         SS_TRACE(ws, tile, 5);
     }
 }
@@ -529,6 +621,7 @@ __global__ __launch_bounds__(BLOCK) void k_fg_totals(FusedCall a, WsView ws,
     __shared__ double s_xv[VALS ? TILE : 1];
     __shared__ double s_ep[PREV ? TILE : 1];
     __shared__ double s_red[NW * 4];
+    __shared__ double s_tsum[3];
     __shared__ uint64_t s_epoch;
     const int tid = threadIdx.x;
     if (tid == 0) s_epoch = ld_relaxed_u64(&ws.hdr->fg_epoch);
@@ -545,24 +638,29 @@ __global__ __launch_bounds__(BLOCK) void k_fg_totals(FusedCall a, WsView ws,
     const int64_t chunk0 = t0 / SS_CHUNK;
     const int64_t chunk1 = min(chunk0 + TILE / SS_CHUNK, nchunk);
     const int64_t cnt = min((int64_t)TILE, a.n - t0);
-    double ev[IPT], xv[IPT], wv[IPT];
-    int dk[IPT];
-    stage_tile<BLOCK, IPT, true, VALS, PREV, false>(a, t0, cnt, chunk0, chunk1, s_flag, s_xv,
-                                                    s_ep, ev, xv, wv, dk);
+    double ev[IPT], wv[IPT];
+    uint32_t dw[(IPT + 3) / 4];
+    const uint32_t xbits = stage_tile<BLOCK, IPT, true, VALS, PREV, false>(
+        a, t0, cnt, chunk0, chunk1, s_flag, s_xv, s_ep, ev, wv, dw);
     double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
+        const double x = x_at<BLOCK, VALS>(xbits, i, s_xv);
         const double ew = ev[i] * wv[i];
         acc[0] += ew;
-        acc[1] += ew * xv[i];
-        acc[2] += ew * xv[i] * xv[i];
+        acc[1] += ew * x;
+        acc[2] += ew * x * x;
     }
     block_sum<3, BLOCK>(acc, s_red);
-    if (tid == 0) publish_partial(ws.fg_partials, ws.fg_pflags, tile, acc, tag);
+    if (tid == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s_tsum[c] = acc[c];
+    }
+    __syncthreads();
+    const double tsum[3] = {s_tsum[0], s_tsum[1], s_tsum[2]};
+    double t[3];
+    reduce_partials<BLOCK>(ws.fg_part, ws.fg_gpart, tile, ntiles, tag, ws.hdr, tsum, t, s_red);
     if (tile == ntiles - 1) {
-        double t[3];
-        gather_partials<BLOCK>(ws.fg_partials, ws.fg_pflags, ntiles, tag, ws.hdr, t);
-        block_sum<3, BLOCK>(t, s_red);
         if (tid == 0) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) ws.hdr->fg_tot[c] = t[c];
@@ -638,17 +736,19 @@ int grid_for(int64_t work, int per_block, int cap)
 size_t fused_ws_bytes(int64_t n)
 {
     const int64_t tiles = ceil_div(n, SS_CHUNK) + 1;
+    const int64_t groups = ceil_div(tiles, kGroup) + 1;
     size_t b = sizeof(WsHeader);
-    b = align_up(b + sizeof(TileState) * (size_t)tiles, 256);
-    b = align_up(b + sizeof(double) * 4 * (size_t)tiles, 256);
-    b = align_up(b + sizeof(double) * 4 * (size_t)tiles, 256);
-    b = align_up(b + sizeof(uint64_t) * (size_t)tiles, 256);
-    b = align_up(b + sizeof(uint64_t) * (size_t)tiles, 256);
-    b = align_up(b + sizeof(uint64_t) * (size_t)tiles, 256);
-    b = align_up(b + 16 * 8 * (size_t)tiles, 256);
-    b = align_up(b + 16 * 4 * (size_t)tiles, 256);
-    b = align_up(b + 16 * (size_t)tiles, 256);
-    b = align_up(b + 16 * 8 * (size_t)tiles, 256);
+    b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // lb
+    b = align_up(b + 16 * 4 * (size_t)tiles, 256);   // part
+    b = align_up(b + 16 * 4 * (size_t)tiles, 256);   // fg_part
+    b = align_up(b + 16 * 4 * (size_t)groups, 256);  // gpart
+    b = align_up(b + 16 * 4 * (size_t)groups, 256);  // fg_gpart
+    b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // sw_agg
+    b = align_up(b + 16 * 4 * (size_t)tiles, 256);   // sw_part
+    b = align_up(b + 16 * (size_t)tiles, 256);       // sw_step
+    b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // sw_pre
+    b = align_up(b + 16 * 16 * (size_t)tiles, 256);  // sw_pub
+    b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // sw_bc
 #ifdef SS_TRACE_TIMES
     b = align_up(b + sizeof(uint64_t) * 64 * (size_t)tiles, 256);
 #endif
@@ -659,29 +759,27 @@ bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v)
 {
     if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < fused_ws_bytes(n)) return false;
     const int64_t tiles = ceil_div(n, SS_CHUNK) + 1;
+    const int64_t groups = ceil_div(tiles, kGroup) + 1;
     char *p = (char *)ws;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        u32x4 *r = (u32x4 *)(p + off);
+        off = align_up(off + bytes, 256);
+        return r;
+    };
     v->hdr = (WsHeader *)p;
-    size_t off = sizeof(WsHeader);
-    v->tiles = (TileState *)(p + off);
-    off = align_up(off + sizeof(TileState) * (size_t)tiles, 256);
-    v->partials = (double *)(p + off);
-    off = align_up(off + sizeof(double) * 4 * (size_t)tiles, 256);
-    v->fg_partials = (double *)(p + off);
-    off = align_up(off + sizeof(double) * 4 * (size_t)tiles, 256);
-    v->pflags = (uint64_t *)(p + off);
-    off = align_up(off + sizeof(uint64_t) * (size_t)tiles, 256);
-    v->fg_pflags = (uint64_t *)(p + off);
-    off = align_up(off + sizeof(uint64_t) * (size_t)tiles, 256);
-    v->sflags = (uint64_t *)(p + off);
-    typedef __attribute__((ext_vector_type(4))) unsigned int u4;
-    off = align_up(off + sizeof(uint64_t) * (size_t)tiles, 256);
-    v->sw_agg = (u4 *)(p + off);
-    off = align_up(off + 16 * 8 * (size_t)tiles, 256);
-    v->sw_part = (u4 *)(p + off);
-    off = align_up(off + 16 * 4 * (size_t)tiles, 256);
-    v->sw_step = (u4 *)(p + off);
-    off = align_up(off + 16 * (size_t)tiles, 256);
-    v->sw_pre = (u4 *)(p + off);
+    off = sizeof(WsHeader);
+    v->lb = take(16 * 8 * (size_t)tiles);
+    v->part = take(16 * 4 * (size_t)tiles);
+    v->fg_part = take(16 * 4 * (size_t)tiles);
+    v->gpart = take(16 * 4 * (size_t)groups);
+    v->fg_gpart = take(16 * 4 * (size_t)groups);
+    v->sw_agg = take(16 * 8 * (size_t)tiles);
+    v->sw_part = take(16 * 4 * (size_t)tiles);
+    v->sw_step = take(16 * (size_t)tiles);
+    v->sw_pre = take(16 * 8 * (size_t)tiles);
+    v->sw_pub = take(16 * 16 * (size_t)tiles);
+    v->sw_bc = take(16 * 8 * (size_t)tiles);
     v->max_tiles = tiles;
     return true;
 }

@@ -7,27 +7,56 @@
 namespace ss {
 namespace dev {
 
-// Inclusive wave-wide scan of NC doubles (wave64 shuffles).
+// ---------------------------------------------------------------- DPP
+// Wave64 scans and reductions of doubles on the VALU through DPP row shifts
+// and row broadcasts (gfx9 family), one 32-bit half at a time; lanes a
+// shift reads from outside the row, and rows the mask leaves out, add 0.
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ double dpp_double(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xF,
+                                               BOUND_ZERO);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF,
+                                               BOUND_ZERO);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Inclusive scan across the 64 lanes of a wave.
+__device__ __forceinline__ double dpp_incl_scan(double x)
+{
+    x += dpp_double<0x111, 0xF, true>(x);  // row_shr:1
+    x += dpp_double<0x112, 0xF, true>(x);  // row_shr:2
+    x += dpp_double<0x114, 0xF, true>(x);  // row_shr:4
+    x += dpp_double<0x118, 0xF, true>(x);  // row_shr:8
+    x += dpp_double<0x142, 0xA, false>(x); // row_bcast:15 into rows 1 and 3
+    x += dpp_double<0x143, 0xC, false>(x); // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+__device__ __forceinline__ double read_lane(double x, int lane)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the wave, returned in every lane.
+__device__ __forceinline__ double dpp_wave_sum(double x)
+{
+    return read_lane(dpp_incl_scan(x), kWave - 1);
+}
+
+// Inclusive wave-wide scan of NC doubles.
 template <int NC>
 __device__ __forceinline__ void wave_inclusive_scan(double (&x)[NC])
 {
-    const int lane = lane_id();
 #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            double y = __shfl_up(x[c], off, kWave);
-            if (lane >= off) x[c] += y;
-        }
-    }
+    for (int c = 0; c < NC; ++c) x[c] = dpp_incl_scan(x[c]);
 }
 
-__device__ __forceinline__ double wave_sum(double x)
-{
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
-    return x;
-}
+__device__ __forceinline__ double wave_sum(double x) { return dpp_wave_sum(x); }
 
 // Block-wide sum of NC doubles in a fixed order; result valid in thread 0.
 template <int NC, int BLOCK>
@@ -53,6 +82,30 @@ __device__ __forceinline__ void block_sum(double (&x)[NC], double *s_red)
         }
     }
 }
+
+// Sum of d log(s) over the events of one thread: for d = 1 (almost every
+// event) the mantissa of s multiplies a running product and its binary
+// exponent adds to an integer, so the sum is log(m) + k ln 2 with a single
+// logarithm at the end; other d take their logarithm directly.  Mantissas
+// lie in [1/2, 1), so up to 1000 factors cannot underflow.
+struct LogSum {
+    double m = 1.0;
+    int k = 0;
+    double rest = 0.0;
+    __device__ __forceinline__ void add(double s, int d)
+    {
+        if (d == 1) {
+            m *= __builtin_amdgcn_frexp_mant(s);
+            k += __builtin_amdgcn_frexp_exp(s);
+        } else {
+            rest += (double)d * log(s);
+        }
+    }
+    __device__ __forceinline__ double value() const
+    {
+        return rest + ((double)k * 0.69314718055994530942 + log(m));
+    }
+};
 
 // Loads IPT consecutive bytes of LDS (IPT in {4, 8, 16}) with one access.
 template <int IPT>
@@ -102,54 +155,12 @@ __device__ __forceinline__ ColTile col_tile(const Column &col, int32_t j, int64_
     return ct;
 }
 
-// ---------------------------------------------------------------- DPP
-// Wave64 scans and reductions of doubles on the VALU through DPP row shifts
-// and row broadcasts (gfx9 family), one 32-bit half at a time; lanes a
-// shift reads from outside the row, and rows the mask leaves out, add 0.
-template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
-__device__ __forceinline__ double dpp_double(double x)
-{
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xF,
-                                               BOUND_ZERO);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF,
-                                               BOUND_ZERO);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Inclusive scan across the 64 lanes of a wave.
-__device__ __forceinline__ double dpp_incl_scan(double x)
-{
-    x += dpp_double<0x111, 0xF, true>(x);  // row_shr:1
-    x += dpp_double<0x112, 0xF, true>(x);  // row_shr:2
-    x += dpp_double<0x114, 0xF, true>(x);  // row_shr:4
-    x += dpp_double<0x118, 0xF, true>(x);  // row_shr:8
-    x += dpp_double<0x142, 0xA, false>(x); // row_bcast:15 into rows 1 and 3
-    x += dpp_double<0x143, 0xC, false>(x); // row_bcast:31 into rows 2 and 3
-    return x;
-}
-
-__device__ __forceinline__ double read_lane(double x, int lane)
-{
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Sum over the wave, returned in every lane.
-__device__ __forceinline__ double dpp_wave_sum(double x)
-{
-    return read_lane(dpp_incl_scan(x), kWave - 1);
-}
-
 // ---------------------------------------------------------------- pairs
 // A published value travels as a 16-byte (value, tag) pair written and read
 // with one agent-scope 16-byte access each, which the memory system performs
 // as a unit, so a reader that sees the expected tag also sees the value and
 // no separate flag or ordering wait is needed.  The tag carries the epoch of
 // the step that wrote it.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ u32x4 make_pair(double v, uint64_t tag)
 {
@@ -182,33 +193,289 @@ __device__ __forceinline__ void st_pair(u32x4 *p, double v, uint64_t tag)
                  : : "v"(p), "v"(val) : "memory");
 }
 
-// Loads NP consecutive pairs (NP in {1, 3, 6}) and waits for them.
+// Loads NP consecutive pairs and waits for them (one statement, so the
+// compiler cannot touch the destination registers before the wait).
 template <int NP>
-__device__ __forceinline__ void ld_pairs(const u32x4 *p, u32x4 (&r)[NP])
+__device__ __forceinline__ void ld_pairs(const u32x4 *p, u32x4 (&r)[NP]);
+
+template <>
+__device__ __forceinline__ void ld_pairs<1>(const u32x4 *p, u32x4 (&r)[1])
 {
-    if (NP == 1) {
-        asm volatile("global_load_dwordx4 %0, %1, off sc1\n\ts_waitcnt vmcnt(0)"
-                     : "=&v"(r[0]) : "v"(p) : "memory");
-    } else if (NP == 3) {
-        asm volatile("global_load_dwordx4 %0, %3, off sc1\n\t"
-                     "global_load_dwordx4 %1, %3, off offset:16 sc1\n\t"
-                     "global_load_dwordx4 %2, %3, off offset:32 sc1\n\t"
-                     "s_waitcnt vmcnt(0)"
-                     : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]) : "v"(p) : "memory");
-    } else {
-        asm volatile("global_load_dwordx4 %0, %6, off sc1\n\t"
-                     "global_load_dwordx4 %1, %6, off offset:16 sc1\n\t"
-                     "global_load_dwordx4 %2, %6, off offset:32 sc1\n\t"
-                     "global_load_dwordx4 %3, %6, off offset:48 sc1\n\t"
-                     "global_load_dwordx4 %4, %6, off offset:64 sc1\n\t"
-                     "global_load_dwordx4 %5, %6, off offset:80 sc1\n\t"
-                     "s_waitcnt vmcnt(0)"
-                     : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]),
-                       "=&v"(r[5])
-                     : "v"(p)
-                     : "memory");
-    }
+    asm volatile("global_load_dwordx4 %0, %1, off sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0])
+                 : "v"(p)
+                 : "memory");
 }
+
+template <>
+__device__ __forceinline__ void ld_pairs<3>(const u32x4 *p, u32x4 (&r)[3])
+{
+    asm volatile("global_load_dwordx4 %0, %3, off sc1\n\t"
+                 "global_load_dwordx4 %1, %3, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %3, off offset:32 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs<4>(const u32x4 *p, u32x4 (&r)[4])
+{
+    asm volatile("global_load_dwordx4 %0, %4, off sc1\n\t"
+                 "global_load_dwordx4 %1, %4, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %4, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %4, off offset:48 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs<6>(const u32x4 *p, u32x4 (&r)[6])
+{
+    asm volatile("global_load_dwordx4 %0, %6, off sc1\n\t"
+                 "global_load_dwordx4 %1, %6, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %6, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %6, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %6, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %6, off offset:80 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs<7>(const u32x4 *p, u32x4 (&r)[7])
+{
+    asm volatile("global_load_dwordx4 %0, %7, off sc1\n\t"
+                 "global_load_dwordx4 %1, %7, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %7, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %7, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %7, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %7, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %7, off offset:96 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs<9>(const u32x4 *p, u32x4 (&r)[9])
+{
+    asm volatile("global_load_dwordx4 %0, %9, off sc1\n\t"
+                 "global_load_dwordx4 %1, %9, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %9, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %9, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %9, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %9, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %9, off offset:96 sc1\n\t"
+                 "global_load_dwordx4 %7, %9, off offset:112 sc1\n\t"
+                 "global_load_dwordx4 %8, %9, off offset:128 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]), "=&v"(r[7]), "=&v"(r[8])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs<15>(const u32x4 *p, u32x4 (&r)[15])
+{
+    asm volatile("global_load_dwordx4 %0, %15, off sc1\n\t"
+                 "global_load_dwordx4 %1, %15, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %15, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %15, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %15, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %15, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %15, off offset:96 sc1\n\t"
+                 "global_load_dwordx4 %7, %15, off offset:112 sc1\n\t"
+                 "global_load_dwordx4 %8, %15, off offset:128 sc1\n\t"
+                 "global_load_dwordx4 %9, %15, off offset:144 sc1\n\t"
+                 "global_load_dwordx4 %10, %15, off offset:160 sc1\n\t"
+                 "global_load_dwordx4 %11, %15, off offset:176 sc1\n\t"
+                 "global_load_dwordx4 %12, %15, off offset:192 sc1\n\t"
+                 "global_load_dwordx4 %13, %15, off offset:208 sc1\n\t"
+                 "global_load_dwordx4 %14, %15, off offset:224 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]), "=&v"(r[7]), "=&v"(r[8]), "=&v"(r[9]), "=&v"(r[10]), "=&v"(r[11]), "=&v"(r[12]), "=&v"(r[13]), "=&v"(r[14])
+                 : "v"(p)
+                 : "memory");
+}
+
+
+template <>
+__device__ __forceinline__ void ld_pairs<5>(const u32x4 *p, u32x4 (&r)[5])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %5, off sc1\n\t"
+                 "global_load_dwordx4 %1, %5, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %5, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %5, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %5, off offset:64 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs<11>(const u32x4 *p, u32x4 (&r)[11])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %11, off sc1\n\t"
+                 "global_load_dwordx4 %1, %11, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %11, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %11, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %11, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %11, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %11, off offset:96 sc1\n\t"
+                 "global_load_dwordx4 %7, %11, off offset:112 sc1\n\t"
+                 "global_load_dwordx4 %8, %11, off offset:128 sc1\n\t"
+                 "global_load_dwordx4 %9, %11, off offset:144 sc1\n\t"
+                 "global_load_dwordx4 %10, %11, off offset:160 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]), "=&v"(r[7]), "=&v"(r[8]), "=&v"(r[9]), "=&v"(r[10])
+                 : "v"(p)
+                 : "memory");
+}
+
+// Loads NP pairs at p and NP pairs 256 bytes further (two consecutive
+// 16-pair slots) and waits for all of them.
+template <int NP>
+__device__ __forceinline__ void ld_pairs2(const u32x4 *p, u32x4 (&r0)[NP], u32x4 (&r1)[NP]);
+
+template <>
+__device__ __forceinline__ void ld_pairs2<9>(const u32x4 *p, u32x4 (&r0)[9],
+                                               u32x4 (&r1)[9])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %18, off sc1\n\t"
+                 "global_load_dwordx4 %1, %18, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %18, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %18, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %18, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %18, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %18, off offset:96 sc1\n\t"
+                 "global_load_dwordx4 %7, %18, off offset:112 sc1\n\t"
+                 "global_load_dwordx4 %8, %18, off offset:128 sc1\n\t"
+                 "global_load_dwordx4 %9, %18, off offset:256 sc1\n\t"
+                 "global_load_dwordx4 %10, %18, off offset:272 sc1\n\t"
+                 "global_load_dwordx4 %11, %18, off offset:288 sc1\n\t"
+                 "global_load_dwordx4 %12, %18, off offset:304 sc1\n\t"
+                 "global_load_dwordx4 %13, %18, off offset:320 sc1\n\t"
+                 "global_load_dwordx4 %14, %18, off offset:336 sc1\n\t"
+                 "global_load_dwordx4 %15, %18, off offset:352 sc1\n\t"
+                 "global_load_dwordx4 %16, %18, off offset:368 sc1\n\t"
+                 "global_load_dwordx4 %17, %18, off offset:384 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r0[0]), "=&v"(r0[1]), "=&v"(r0[2]), "=&v"(r0[3]), "=&v"(r0[4]), "=&v"(r0[5]), "=&v"(r0[6]), "=&v"(r0[7]), "=&v"(r0[8]), "=&v"(r1[0]), "=&v"(r1[1]), "=&v"(r1[2]), "=&v"(r1[3]), "=&v"(r1[4]), "=&v"(r1[5]), "=&v"(r1[6]), "=&v"(r1[7]), "=&v"(r1[8])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs2<15>(const u32x4 *p, u32x4 (&r0)[15],
+                                               u32x4 (&r1)[15])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %30, off sc1\n\t"
+                 "global_load_dwordx4 %1, %30, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %30, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %30, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %30, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %30, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %30, off offset:96 sc1\n\t"
+                 "global_load_dwordx4 %7, %30, off offset:112 sc1\n\t"
+                 "global_load_dwordx4 %8, %30, off offset:128 sc1\n\t"
+                 "global_load_dwordx4 %9, %30, off offset:144 sc1\n\t"
+                 "global_load_dwordx4 %10, %30, off offset:160 sc1\n\t"
+                 "global_load_dwordx4 %11, %30, off offset:176 sc1\n\t"
+                 "global_load_dwordx4 %12, %30, off offset:192 sc1\n\t"
+                 "global_load_dwordx4 %13, %30, off offset:208 sc1\n\t"
+                 "global_load_dwordx4 %14, %30, off offset:224 sc1\n\t"
+                 "global_load_dwordx4 %15, %30, off offset:256 sc1\n\t"
+                 "global_load_dwordx4 %16, %30, off offset:272 sc1\n\t"
+                 "global_load_dwordx4 %17, %30, off offset:288 sc1\n\t"
+                 "global_load_dwordx4 %18, %30, off offset:304 sc1\n\t"
+                 "global_load_dwordx4 %19, %30, off offset:320 sc1\n\t"
+                 "global_load_dwordx4 %20, %30, off offset:336 sc1\n\t"
+                 "global_load_dwordx4 %21, %30, off offset:352 sc1\n\t"
+                 "global_load_dwordx4 %22, %30, off offset:368 sc1\n\t"
+                 "global_load_dwordx4 %23, %30, off offset:384 sc1\n\t"
+                 "global_load_dwordx4 %24, %30, off offset:400 sc1\n\t"
+                 "global_load_dwordx4 %25, %30, off offset:416 sc1\n\t"
+                 "global_load_dwordx4 %26, %30, off offset:432 sc1\n\t"
+                 "global_load_dwordx4 %27, %30, off offset:448 sc1\n\t"
+                 "global_load_dwordx4 %28, %30, off offset:464 sc1\n\t"
+                 "global_load_dwordx4 %29, %30, off offset:480 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r0[0]), "=&v"(r0[1]), "=&v"(r0[2]), "=&v"(r0[3]), "=&v"(r0[4]), "=&v"(r0[5]), "=&v"(r0[6]), "=&v"(r0[7]), "=&v"(r0[8]), "=&v"(r0[9]), "=&v"(r0[10]), "=&v"(r0[11]), "=&v"(r0[12]), "=&v"(r0[13]), "=&v"(r0[14]), "=&v"(r1[0]), "=&v"(r1[1]), "=&v"(r1[2]), "=&v"(r1[3]), "=&v"(r1[4]), "=&v"(r1[5]), "=&v"(r1[6]), "=&v"(r1[7]), "=&v"(r1[8]), "=&v"(r1[9]), "=&v"(r1[10]), "=&v"(r1[11]), "=&v"(r1[12]), "=&v"(r1[13]), "=&v"(r1[14])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs2<7>(const u32x4 *p, u32x4 (&r0)[7],
+                                               u32x4 (&r1)[7])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %14, off sc1\n\t"
+                 "global_load_dwordx4 %1, %14, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %14, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %14, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %14, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %14, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %14, off offset:96 sc1\n\t"
+                 "global_load_dwordx4 %7, %14, off offset:256 sc1\n\t"
+                 "global_load_dwordx4 %8, %14, off offset:272 sc1\n\t"
+                 "global_load_dwordx4 %9, %14, off offset:288 sc1\n\t"
+                 "global_load_dwordx4 %10, %14, off offset:304 sc1\n\t"
+                 "global_load_dwordx4 %11, %14, off offset:320 sc1\n\t"
+                 "global_load_dwordx4 %12, %14, off offset:336 sc1\n\t"
+                 "global_load_dwordx4 %13, %14, off offset:352 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r0[0]), "=&v"(r0[1]), "=&v"(r0[2]), "=&v"(r0[3]), "=&v"(r0[4]), "=&v"(r0[5]), "=&v"(r0[6]), "=&v"(r1[0]), "=&v"(r1[1]), "=&v"(r1[2]), "=&v"(r1[3]), "=&v"(r1[4]), "=&v"(r1[5]), "=&v"(r1[6])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs2<11>(const u32x4 *p, u32x4 (&r0)[11],
+                                               u32x4 (&r1)[11])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %22, off sc1\n\t"
+                 "global_load_dwordx4 %1, %22, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %22, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %22, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %22, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %22, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %22, off offset:96 sc1\n\t"
+                 "global_load_dwordx4 %7, %22, off offset:112 sc1\n\t"
+                 "global_load_dwordx4 %8, %22, off offset:128 sc1\n\t"
+                 "global_load_dwordx4 %9, %22, off offset:144 sc1\n\t"
+                 "global_load_dwordx4 %10, %22, off offset:160 sc1\n\t"
+                 "global_load_dwordx4 %11, %22, off offset:256 sc1\n\t"
+                 "global_load_dwordx4 %12, %22, off offset:272 sc1\n\t"
+                 "global_load_dwordx4 %13, %22, off offset:288 sc1\n\t"
+                 "global_load_dwordx4 %14, %22, off offset:304 sc1\n\t"
+                 "global_load_dwordx4 %15, %22, off offset:320 sc1\n\t"
+                 "global_load_dwordx4 %16, %22, off offset:336 sc1\n\t"
+                 "global_load_dwordx4 %17, %22, off offset:352 sc1\n\t"
+                 "global_load_dwordx4 %18, %22, off offset:368 sc1\n\t"
+                 "global_load_dwordx4 %19, %22, off offset:384 sc1\n\t"
+                 "global_load_dwordx4 %20, %22, off offset:400 sc1\n\t"
+                 "global_load_dwordx4 %21, %22, off offset:416 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r0[0]), "=&v"(r0[1]), "=&v"(r0[2]), "=&v"(r0[3]), "=&v"(r0[4]), "=&v"(r0[5]), "=&v"(r0[6]), "=&v"(r0[7]), "=&v"(r0[8]), "=&v"(r0[9]), "=&v"(r0[10]), "=&v"(r1[0]), "=&v"(r1[1]), "=&v"(r1[2]), "=&v"(r1[3]), "=&v"(r1[4]), "=&v"(r1[5]), "=&v"(r1[6]), "=&v"(r1[7]), "=&v"(r1[8]), "=&v"(r1[9]), "=&v"(r1[10])
+                 : "v"(p)
+                 : "memory");
+}
+
 
 }  // namespace dev
 }  // namespace ss

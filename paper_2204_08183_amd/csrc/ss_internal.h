@@ -86,10 +86,15 @@ __device__ __forceinline__ uint32_t fetch_add_relaxed(uint32_t *p, uint32_t v)
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 // ------------------------------------------------------------ workspace
-// Layout of the fused-kernel workspace (all offsets 256-byte aligned):
-//   WsHeader | TileState[max_tiles] | partials[max_tiles][4] |
-//   fg_partials[max_tiles][4] | pflags[max_tiles] | fg_pflags[max_tiles] |
-//   sflags[max_tiles]
+// Values that cross workgroups travel as 16-byte (value, tag) pairs, each
+// written and read with one 16-byte agent-scope access (ss_device.h).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Layout of the workspace (every region 256-byte aligned), T = max_tiles
+// and U = ceil(T / kGroup) + 1 tile groups:
+//   WsHeader | lb[T][8] | part[T][4] | fg_part[T][4] | gpart[U][4] |
+//   fg_gpart[U][4] | sw_agg[T][8] | sw_part[T][4] | sw_step[T] |
+//   sw_pre[T][8] | sw_pub[T][16] | sw_bc[T][8]
 struct alignas(256) WsHeader {
     uint64_t epoch;       // number of completed fused launches
     uint64_t fg_epoch;    // number of completed Fine-Gray totals passes
@@ -99,40 +104,34 @@ struct alignas(256) WsHeader {
     double scratch_out[4];
 };
 
-// Per-tile look-back state: the flag word is (epoch << 2) | state with
-// state 0 = nothing published, 1 = tile aggregate, 2 = inclusive prefix.
+// Look-back pairs of a tile carry the tag (epoch << 2) | state with state
+// 1 = tile aggregate, 2 = inclusive prefix (anything else: not published in
+// this launch).  Partial-sum pairs carry (epoch << 1) | 1.
 constexpr int kMaxComp = 6;
-struct alignas(128) TileState {
-    uint64_t flag;
-    double agg[kMaxComp];
-    double inc[kMaxComp];
-};
-
 constexpr uint64_t kStateAgg = 1;
 constexpr uint64_t kStateInc = 2;
+
+// Tiles per group of the two-level reduction of the per-tile partial sums.
+constexpr int kGroup = 64;
 
 // Upper bound on polls of one bounded wait before it gives up (each poll is
 // an uncached load plus a short sleep, so this is on the order of a second).
 constexpr uint32_t kSpinLimit = 1u << 20;
 
-// Per-tile "partial ready" words hold the tag (epoch << 1) | 1 of the launch
-// that wrote the tile's partial sums; the last workgroup of the launch polls
-// them instead of counting finished tiles on one shared atomic counter
-// (same-address atomics from every workgroup serialise at the coherence
-// point, about 12 ns each on MI355X).
 struct WsView {
     WsHeader *hdr;
-    TileState *tiles;
-    double *partials;     // [max_tiles][4]
-    double *fg_partials;  // [max_tiles][4]
-    uint64_t *pflags;     // [max_tiles]
-    uint64_t *fg_pflags;  // [max_tiles]
-    uint64_t *sflags;     // [max_tiles] (trace base in analysis builds)
-    // persistent sweep: 16-byte (value, tag) pairs
-    __attribute__((ext_vector_type(4))) unsigned int *sw_agg;   // [max_tiles][8]
-    __attribute__((ext_vector_type(4))) unsigned int *sw_part;  // [max_tiles][4]
-    __attribute__((ext_vector_type(4))) unsigned int *sw_step;  // [max_tiles]
-    __attribute__((ext_vector_type(4))) unsigned int *sw_pre;   // [max_tiles][8]
+    u32x4 *lb;        // [max_tiles][8]  look-back (aggregate / inclusive prefix)
+    u32x4 *part;      // [max_tiles][4]  per-tile partial sums
+    u32x4 *fg_part;   // [max_tiles][4]  Fine-Gray totals pass, per tile
+    u32x4 *gpart;     // [groups][4]     per-group partial sums
+    u32x4 *fg_gpart;  // [groups][4]
+    // persistent sweep
+    u32x4 *sw_agg;    // [max_tiles][8]
+    u32x4 *sw_part;   // [max_tiles][4]
+    u32x4 *sw_step;   // [max_tiles]
+    u32x4 *sw_pre;    // [max_tiles][8]
+    u32x4 *sw_pub;    // [max_tiles][16]
+    u32x4 *sw_bc;     // [max_tiles][8]
     int64_t max_tiles;
 };
 

@@ -37,7 +37,7 @@ using namespace dev;
 #define SW_TRACE(a, b, jj, slot)                                                    \
     do {                                                                            \
         if (threadIdx.x == 0 && (jj) - (a).j_begin < 8)                             \
-            reinterpret_cast<uint64_t *>((a).ws.sw_pre + 8 * (a).ws.max_tiles)     \
+            reinterpret_cast<uint64_t *>((a).ws.sw_bc + 8 * (a).ws.max_tiles)      \
                 [((b) * 8 + ((jj) - (a).j_begin)) * 8 + (slot)] =                   \
                 __builtin_amdgcn_s_memrealtime();                                   \
     } while (0)
@@ -509,6 +509,503 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
         st_relaxed_u64(&hdr->epoch, ep0 + (uint64_t)(a.j_end - a.j_begin));
 }
 
+// ------------------------------------------------------------------------
+// One exchange per coordinate, for 0/1 (indicator) designs.
+//
+// With x in {0, 1}, the update of column j multiplies e by exp(s_j) at the
+// rows of column j, so a segment's tuple aggregate for the next coordinate
+// is  A + expm1(s_j) D  with  A = sum e (1, x_{j+1}, x_{j+1}^2)  over the
+// segment and  D  the same sum over the rows of column j -- both known
+// before s_j is.  Every workgroup therefore publishes, in one go, its
+// partial sums for coordinate j together with A and D for coordinate j+1;
+// workgroup 0 adds the partials, takes the coordinate update, forms every
+// segment's aggregate for j+1, scans them in segment order and broadcasts
+// (s_j, exclusive prefix) to each workgroup: one round trip per coordinate.
+//
+// Between receiving the broadcast and publishing, a workgroup touches no
+// global memory: eta of its segment lives in LDS and e in registers, the
+// update of the previous column is applied in place (eta += s, e *= exp(s)),
+// and the rows of column j+2 are scattered into LDS while the workgroup
+// waits for the broadcast.  Column c's rows live in bit (c mod 3) of the
+// LDS flag bytes, so the previous column, the current one and the next one
+// are all at hand.  eta and e = exp(eta) go back to global memory once, at
+// the end of the sweep.
+template <int BLOCK, int IPT, int MODEL>
+__global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
+{
+    constexpr int S = BLOCK * IPT;
+    constexpr bool FG = MODEL == SS_FINE_GRAY;
+    // With x in {0, 1}, e x^2 = e x: the tuple is (e, e x) for Cox and
+    // (e, e x, e w, e w x) for Fine-Gray.
+    constexpr int NT = FG ? 4 : 2;
+    constexpr int NW = BLOCK / kWave;
+    constexpr int NPUB = 3 + 2 * NT;  // partial sums, A, D
+    constexpr int NBC = 1 + NT;       // step, prefix (Fine-Gray: suffix starts)
+    constexpr int NLEAD = 3 + 2 * NT; // per-wave totals in the leader round
+    constexpr int K = (kMaxSweepBlocks + BLOCK - 1) / BLOCK;
+    static_assert(K <= 2, "the leader takes at most two segments per thread");
+    static_assert(S % SS_CHUNK == 0, "segment must be whole chunks");
+
+    __shared__ __attribute__((aligned(16))) uint8_t s_flag[S];
+    __shared__ double s_eta[S];          // [i * BLOCK + tid]
+    __shared__ double s_g[FG ? S : 1];   // G(y) at each position, same layout
+    __shared__ double s_wsum[NW][NT];
+    __shared__ double s_wred[NW][NPUB];
+    __shared__ double s_lead[NW][NLEAD];  // leader round only
+    __shared__ double s_bc[NBC];
+    __shared__ uint64_t s_ep0;
+    __shared__ double s_step;
+    __shared__ int s_abort;
+
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int w = tid / kWave;
+    const int64_t b = blockIdx.x;
+    const int G = a.nblk;
+    WsHeader *hdr = a.ws.hdr;
+    const int64_t seg0 = b * S;
+    const int64_t cnt = min((int64_t)S, a.n - seg0);
+    const int64_t nchunk = a.col.nchunk1 - 1;
+    const int64_t chunk0 = seg0 / SS_CHUNK;
+    const int64_t chunk1 = min(chunk0 + S / SS_CHUNK, nchunk);
+    const int64_t base = seg0 + (int64_t)tid * IPT;
+    const int32_t jb = a.j_begin, je = a.j_end;
+
+    if (tid == 0) {
+        s_ep0 = ld_relaxed_u64(&hdr->epoch);
+        s_abort = 0;
+    }
+    // ---- the segment's data for the whole sweep
+    double ev[IPT];
+    int dk[IPT];
+    double wv[FG ? IPT : 1];
+    if (cnt == S) {
+        const double2 *ep = reinterpret_cast<const double2 *>(a.e + base);
+        const double2 *hp = reinterpret_cast<const double2 *>(a.eta + base);
+#pragma unroll
+        for (int q = 0; q < IPT / 2; ++q) {
+            const double2 v = ep[q];
+            const double2 h = hp[q];
+            ev[2 * q] = v.x;
+            ev[2 * q + 1] = v.y;
+            s_eta[(2 * q) * BLOCK + tid] = h.x;
+            s_eta[(2 * q + 1) * BLOCK + tid] = h.y;
+        }
+        if (FG) {
+            const double2 *wp = reinterpret_cast<const double2 *>(a.w_comp + base);
+#pragma unroll
+            for (int q = 0; q < IPT / 2; ++q) {
+                const double2 v = wp[q];
+                wv[2 * q] = v.x;
+                wv[2 * q + 1] = v.y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const bool ok = base + i < a.n;
+            ev[i] = ok ? a.e[base + i] : 0.0;
+            s_eta[i * BLOCK + tid] = ok ? a.eta[base + i] : 0.0;
+            if (FG) wv[i] = ok ? a.w_comp[base + i] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int64_t k = base + i;
+        const bool ok = k < a.n;
+        int d = ok ? (int)a.d8[k] : 0;
+        if (d == 255) d = a.d32[k];
+        dk[i] = d;
+        if (FG) s_g[i * BLOCK + tid] = ok ? a.g_end[k] : 1.0;
+    }
+    {
+        uint32_t *f32 = reinterpret_cast<uint32_t *>(s_flag);
+        for (int i = tid; i < S / 4; i += BLOCK) f32[i] = 0u;
+    }
+    __syncthreads();
+    const uint64_t ep0 = s_ep0;
+
+    // Adds column jc's rows of this segment as bit (jc mod 3), spread over
+    // threads first .. BLOCK-1.
+    auto scatter = [&](int32_t jc, int first) {
+        const ColTile ct = col_tile(a.col, jc, chunk0, chunk1);
+        const uint8_t bit = (uint8_t)(1u << (jc % 3));
+        for (int32_t o = ct.lo + tid - first; o < ct.hi; o += BLOCK - first)
+            lds_flag_or(s_flag, (int32_t)(a.col.rows[ct.cb + o] - seg0), bit);
+    };
+    // Clears bit (jc mod 3) in the bytes this thread owns.
+    auto clear_bit = [&](int32_t jc) {
+        const uint32_t keep = ~(0x01010101u << (jc % 3));
+        uint32_t *f32 = reinterpret_cast<uint32_t *>(s_flag + tid * IPT);
+#pragma unroll
+        for (int q = 0; q < IPT / 4; ++q) f32[q] &= keep;
+    };
+    // Block sums of NPUB values, published by thread 0 as pairs.
+    auto publish = [&](double (&v)[NPUB], uint64_t tag) {
+#pragma unroll
+        for (int c = 0; c < NPUB; ++c) {
+            const double t = dpp_wave_sum(v[c]);
+            if (lane == 0) s_wred[w][c] = t;
+        }
+        __syncthreads();
+        if (tid == 0) {
+#pragma unroll
+            for (int c = 0; c < NPUB; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) t += s_wred[q][c];
+                st_pair(a.ws.sw_pub + b * 16 + c, t, tag);
+            }
+        }
+    };
+    // Workgroup 0: gathers every workgroup's (partials, A, D), takes the
+    // update of column jc (none when jc < 0), and broadcasts (step, prefix).
+    // The exclusive scans of A and D over the segments run alongside the
+    // sum of the partials; the prefix of each segment is then
+    // scan(A) + expm1(s) scan(D).
+    auto leader_round = [&](int32_t jc, uint64_t tag) -> bool {
+        double cj = 0.0, bj = 0.0, dj = 0.0;
+        if (tid == 0 && jc >= 0) {  // in flight while the partials arrive
+            cj = a.c[jc];
+            bj = a.beta[jc];
+            dj = a.delta[jc];
+        }
+        double v[K][NPUB];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < NPUB; ++c) v[k][c] = 0.0;
+        bool bad = false;
+        const int q0 = tid * K;
+        if (K == 2 && q0 + 1 < G) {
+            u32x4 r0[NPUB], r1[NPUB];
+            uint32_t spins = 0;
+            for (;;) {
+                ld_pairs2<NPUB>(a.ws.sw_pub + (int64_t)q0 * 16, r0, r1);
+                bool ok = true;
+#pragma unroll
+                for (int c = 0; c < NPUB; ++c)
+                    ok = ok && pair_tag(r0[c]) == tag && pair_tag(r1[c]) == tag;
+                if (ok) break;
+                if (((++spins & 31u) == 0 && ld_relaxed_u32(&hdr->error)) ||
+                    spins > kSpinLimit) {
+                    __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    bad = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (!bad) {
+#pragma unroll
+                for (int c = 0; c < NPUB; ++c) {
+                    v[0][c] = pair_value(r0[c]);
+                    v[K - 1][c] = pair_value(r1[c]);
+                }
+            }
+        } else if (q0 < G) {
+            u32x4 r[NPUB];
+            if (wait_pairs<NPUB>(a.ws.sw_pub + (int64_t)q0 * 16, tag, hdr, r)) {
+#pragma unroll
+                for (int c = 0; c < NPUB; ++c) v[0][c] = pair_value(r[c]);
+            } else {
+                bad = true;
+            }
+        }
+        // thread totals: partial sums, and A, D for the scans
+        double ps[3], tA[NT], tD[NT];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) t += v[k][c];
+            ps[c] = dpp_wave_sum(t);
+        }
+        double iA[NT], iD[NT];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            double ta = 0.0, td = 0.0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                ta += v[k][3 + c];
+                td += v[k][3 + NT + c];
+            }
+            tA[c] = ta;
+            tD[c] = td;
+            iA[c] = dpp_incl_scan(ta);
+            iD[c] = dpp_incl_scan(td);
+        }
+        if (lane == kWave - 1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s_lead[w][c] = ps[c];
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                s_lead[w][3 + c] = iA[c];
+                s_lead[w][3 + NT + c] = iD[c];
+            }
+        }
+        if (jc >= 0) SW_TRACE(a, b, jc, 6);
+        if (__syncthreads_or(bad)) return false;
+        if (tid == 0) {
+            double st = 0.0;
+            if (jc >= 0) {
+                double tot[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) t += s_lead[q][c];
+                    tot[c] = t;
+                }
+                const double g1 = cj - tot[0];
+                const double g2 = -tot[1];
+                ccd_apply(g1, g2, a.penalty, a.lambda, &bj, &dj, &st);
+                a.beta[jc] = bj;
+                a.delta[jc] = dj;
+                a.steps[jc] = st;
+                if (a.g12_out) {
+                    a.g12_out[3 * jc] = g1;
+                    a.g12_out[3 * jc + 1] = g2;
+                    a.g12_out[3 * jc + 2] = tot[2];
+                }
+            }
+            s_step = st;
+        }
+        // exclusive scans of A and D up to this thread's first segment
+        double eA[NT], eD[NT], allA[NT], allD[NT];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            double bA = 0.0, bD = 0.0, sA = 0.0, sD = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                const double xa = s_lead[q][3 + c], xd = s_lead[q][3 + NT + c];
+                if (q < w) {
+                    bA += xa;
+                    bD += xd;
+                }
+                sA += xa;
+                sD += xd;
+            }
+            eA[c] = bA + iA[c] - tA[c];
+            eD[c] = bD + iD[c] - tD[c];
+            allA[c] = sA;
+            allD[c] = sD;
+        }
+        __syncthreads();
+        if (jc >= 0) SW_TRACE(a, b, jc, 7);
+        const double st = s_step;
+        const double f = expm1(st);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int q = q0 + k;
+            if (q < G) {
+                st_pair(a.ws.sw_bc + (int64_t)q * 8, st, tag);
+#pragma unroll
+                for (int c = 0; c < NT; ++c) {
+                    const double pre = eA[c] + f * eD[c];
+                    const double out = (FG && c >= 2) ? (allA[c] + f * allD[c]) - pre : pre;
+                    st_pair(a.ws.sw_bc + (int64_t)q * 8 + 1 + c, out, tag);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                eA[c] += v[k][3 + c];
+                eD[c] += v[k][3 + NT + c];
+            }
+        }
+        return true;
+    };
+    // Thread 0 waits for this workgroup's broadcast; all threads get it.
+    auto receive = [&](uint64_t tag) -> bool {
+        if (tid == 0) {
+            u32x4 r[NBC];
+            if (wait_pairs<NBC>(a.ws.sw_bc + b * 8, tag, hdr, r)) {
+#pragma unroll
+                for (int c = 0; c < NBC; ++c) s_bc[c] = pair_value(r[c]);
+            } else {
+                s_abort = 1;
+            }
+        }
+        __syncthreads();
+        return !s_abort;
+    };
+
+    // ---- round 0: aggregates of coordinate jb; rows of jb and jb+1
+    scatter(jb, 0);
+    if (jb + 1 < je) scatter(jb + 1, 0);
+    __syncthreads();
+    {
+        double v[NPUB];
+#pragma unroll
+        for (int c = 0; c < NPUB; ++c) v[c] = 0.0;
+        uint8_t fl[IPT];
+        lds_bytes<IPT>(s_flag + tid * IPT, fl);
+        const uint8_t bj = (uint8_t)(1u << (jb % 3));
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            v[3] += ev[i];
+            v[4] += (fl[i] & bj) ? ev[i] : 0.0;
+            if (FG) {
+                const double ew = ev[i] * wv[i];
+                v[5] += ew;
+                v[6] += (fl[i] & bj) ? ew : 0.0;
+            }
+        }
+        publish(v, (ep0 << 1) | 1u);
+    }
+    if (b == 0 && !leader_round(-1, (ep0 << 1) | 1u)) return;
+    if (!receive((ep0 << 1) | 1u)) return;
+
+    for (int32_t j = jb; j < je; ++j) {
+        const uint64_t r = (uint64_t)(j - jb) + 1;  // exchange round of coordinate j
+        const uint64_t tag = ((ep0 + r) << 1) | 1u;
+        SW_TRACE(a, b, j, 0);
+        // ---- s_{j-1} and the prefix of coordinate j arrived in round r-1
+        const double st_prev = s_bc[0];
+        double pre[NT];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) pre[c] = s_bc[1 + c];
+        uint8_t fl[IPT];
+        lds_bytes<IPT>(s_flag + tid * IPT, fl);
+        const uint8_t bcur = (uint8_t)(1u << (j % 3));
+        const uint8_t bnext = (uint8_t)(1u << ((j + 1) % 3));
+        const uint8_t bprev = (uint8_t)(1u << ((j + 2) % 3));
+        // ---- the update of column j-1, in place
+        if (j > jb && st_prev != 0.0) {
+            const double fe = exp(st_prev);
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                if (fl[i] & bprev) {
+                    s_eta[i * BLOCK + tid] += st_prev;
+                    ev[i] *= fe;
+                }
+            }
+        }
+        SW_TRACE(a, b, j, 1);
+        // ---- in-segment scan of the tuple of coordinate j
+        double texcl[NT];
+        {
+            double run[NT];
+#pragma unroll
+            for (int c = 0; c < NT; ++c) run[c] = 0.0;
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                run[0] += ev[i];
+                run[1] += (fl[i] & bcur) ? ev[i] : 0.0;
+                if (FG) {
+                    const double ew = ev[i] * wv[i];
+                    run[2] += ew;
+                    run[3] += (fl[i] & bcur) ? ew : 0.0;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                const double inc = dpp_incl_scan(run[c]);
+                texcl[c] = inc - run[c];
+                if (lane == kWave - 1) s_wsum[w][c] = inc;
+            }
+        }
+        __syncthreads();
+        // every thread has read its flags: column j-1's bit is free
+        clear_bit(j + 2);
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            double before = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q)
+                if (q < w) before += s_wsum[q][c];
+            texcl[c] += before;
+        }
+        SW_TRACE(a, b, j, 2);
+        // ---- transform and reduction of coordinate j; A and D of j+1
+        double v[NPUB];
+#pragma unroll
+        for (int c = 0; c < NPUB; ++c) v[c] = 0.0;
+        {
+            double Sr[2], R[2] = {0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 2; ++c) Sr[c] = pre[c] + texcl[c];
+            if (FG) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c) R[c] = pre[2 + c] - texcl[2 + c];
+            }
+            const bool has_next = j + 1 < je;
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const bool xc = fl[i] & bcur;
+                const bool xn = has_next && (fl[i] & bnext);
+                const double ex = xc ? ev[i] : 0.0;
+                Sr[0] += ev[i];
+                Sr[1] += ex;
+                double ew = 0.0, ewx = 0.0;
+                if (FG) {
+                    ew = ev[i] * wv[i];
+                    ewx = xc ? ew : 0.0;
+                    R[0] -= ew;
+                    R[1] -= ewx;
+                }
+                const int d = dk[i];
+                if (d != 0) {
+                    double S0 = Sr[0], S1 = Sr[1];
+                    if (FG) {
+                        const double g = s_g[i * BLOCK + tid];
+                        S0 += g * R[0];
+                        S1 += g * R[1];
+                    }
+                    // indicator design: S2 = S1, so H = G
+                    const double Gk = S1 / S0;
+                    const double dd = (double)d;
+                    v[0] += dd * Gk;
+                    v[1] += dd * (Gk - Gk * Gk);
+                    if (a.want_log) v[2] += dd * log(S0);
+                }
+                // A (all positions) and D (rows of column j) for j+1
+                v[3] += ev[i];
+                v[4] += xn ? ev[i] : 0.0;
+                v[3 + NT] += ex;
+                v[4 + NT] += xn ? ex : 0.0;
+                if (FG) {
+                    v[5] += ew;
+                    v[6] += xn ? ew : 0.0;
+                    v[5 + NT] += ewx;
+                    v[6 + NT] += xn ? ewx : 0.0;
+                }
+            }
+        }
+        publish(v, tag);
+        SW_TRACE(a, b, j, 3);
+        if (b == 0) {
+            if (!leader_round(j, tag)) return;
+            SW_TRACE(a, b, j, 4);
+        }
+        // ---- rows of column j+2 while the broadcast is on its way (wave 0
+        // stays free to poll)
+        if (j + 2 < je && w > 0) scatter(j + 2, kWave);
+        if (!receive(tag)) return;
+        SW_TRACE(a, b, j, 5);
+    }
+
+    // ---- the last coordinate's update, then eta and e back to memory
+    const double st = s_bc[0];
+    {
+        uint8_t fl[IPT];
+        lds_bytes<IPT>(s_flag + tid * IPT, fl);
+        const uint8_t blast = (uint8_t)(1u << ((je - 1) % 3));
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const int64_t k = base + i;
+            if (k < a.n) {
+                double h = s_eta[i * BLOCK + tid];
+                if (st != 0.0 && (fl[i] & blast)) h += st;
+                a.eta[k] = h;
+                a.e[k] = exp(h);
+            }
+        }
+    }
+    if (b == 0 && tid == 0)
+        st_relaxed_u64(&hdr->epoch, ep0 + (uint64_t)(je - jb) + 1);
+}
+
 // Shapes tried in order: the first whose workgroups all fit on the device at
 // once (a cooperative launch requires it) is used.
 struct Shape {
@@ -522,13 +1019,20 @@ void *kernel_ptr()
     return reinterpret_cast<void *>(&k_sweep<BLOCK, IPT, MODEL, VALS>);
 }
 
+template <int BLOCK, int IPT, int MODEL>
+void *kernel1_ptr()
+{
+    return reinterpret_cast<void *>(&k_sweep1<BLOCK, IPT, MODEL>);
+}
+
+// Indicator designs take the one-exchange kernel, valued ones the general.
 template <int BLOCK, int IPT>
 void *pick_kernel(int model, bool vals)
 {
     if (model == SS_FINE_GRAY)
         return vals ? kernel_ptr<BLOCK, IPT, SS_FINE_GRAY, true>()
-                    : kernel_ptr<BLOCK, IPT, SS_FINE_GRAY, false>();
-    return vals ? kernel_ptr<BLOCK, IPT, SS_COX, true>() : kernel_ptr<BLOCK, IPT, SS_COX, false>();
+                    : kernel1_ptr<BLOCK, IPT, SS_FINE_GRAY>();
+    return vals ? kernel_ptr<BLOCK, IPT, SS_COX, true>() : kernel1_ptr<BLOCK, IPT, SS_COX>();
 }
 
 void *kernel_for(int block, int ipt, int model, bool vals)
@@ -538,7 +1042,7 @@ void *kernel_for(int block, int ipt, int model, bool vals)
     if (block == 512 && ipt == 8) return pick_kernel<512, 8>(model, vals);
     // 8192-position segments: Cox only (Fine-Gray's extra LDS does not fit)
     if (block == 512 && ipt == 16 && model == SS_COX)
-        return vals ? kernel_ptr<512, 16, SS_COX, true>() : kernel_ptr<512, 16, SS_COX, false>();
+        return vals ? kernel_ptr<512, 16, SS_COX, true>() : kernel1_ptr<512, 16, SS_COX>();
     return nullptr;
 }
 
