@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--density", type=float, default=0.05)
     ap.add_argument("--roof-n", type=int, default=1 << 27)
     ap.add_argument("--roof-reps", type=int, default=20)
-    ap.add_argument("--cpu-coords", type=int, default=150,
+    ap.add_argument("--cpu-coords", type=int, default=400,
                     help="coordinates per model in the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
