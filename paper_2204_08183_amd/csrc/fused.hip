@@ -47,12 +47,10 @@ using namespace dev;
 // inclusive prefix published) and the two payloads; a payload is written
 // before its flag (release order) and read after it (acquire order).
 //
-// Wave 0 of the tile inspects its predecessors kLbK * 64 at a time (kLbK
-// flags per lane, all in flight together) and stops at the nearest
-// inclusive prefix; payloads are loaded only for the predecessors needed.
-// Polling by one wave keeps the flag traffic of the tiles waiting at once
-// small next to the data stream (all four waves polling was measured
-// slower).  Every predecessor started earlier (workgroups start in index
+// Wave 0 of the tile does the look-back (see look_back below).  Polling by
+// one wave, and re-polling only what is missing, keeps the flag traffic of
+// the tiles waiting at once small next to the data stream (all four waves
+// polling whole windows was measured slower).  Every predecessor started earlier (workgroups start in index
 // order on each XCD) and publishes its aggregate without waiting on anyone,
 // so the wait ends; it is bounded all the same.
 struct alignas(128) LbSlot {
@@ -75,75 +73,115 @@ __device__ __forceinline__ void publish_lb(LbSlot *slot, const double (&v)[NC], 
 
 // Wave 0 only; the exclusive prefix is returned in every lane.  Returns
 // false if the wait gave up (the error word is then set).
+//
+// One round covers 64 * kLbW predecessors: their flags are read once (one
+// round trip), the nearest inclusive prefix among them fixes which ones are
+// needed, only the needed ones that had not published yet are polled again,
+// and each needed payload is loaded once (aggregate, or the inclusive prefix
+// at the nearest one).  The states stay packed, two bits per predecessor.
 template <int NC>
 __device__ bool look_back(const LbSlot *lb, int64_t tile, uint64_t epoch, WsHeader *hdr,
-                          double (&excl)[NC])
+                          double (&excl)[NC], uint64_t *lb_stats = nullptr)
 {
-    constexpr int kLbK = NC > 3 ? 2 : 4;  // Fine-Gray: twice the payload
+    constexpr int kLbW = 4;  // windows of 64 per round (8 measured slower: registers)
+    constexpr int kBatch = NC > 3 ? 2 : 4;  // payload windows in flight per lane
     const int lane = lane_id();
 #pragma unroll
     for (int c = 0; c < NC; ++c) excl[c] = 0.0;
     // tile indices fit in 32 bits (n < 2^31, tiles of at least 1024)
     int32_t top = (int32_t)tile - 1;
     uint32_t spins = 0;
+    // uniform base plus a 32-bit byte offset: one VGPR per address
+    const char *lbase = reinterpret_cast<const char *>(lb);
+    auto state_of = [&](int32_t t) -> uint32_t {
+        if (t < 0) return (uint32_t)kStateInc;  // before tile 0: an empty prefix
+        const uint32_t off = (uint32_t)t * (uint32_t)sizeof(LbSlot);
+        const uint64_t f = ld_flag(reinterpret_cast<const uint64_t *>(lbase + off));
+        return (f >> 2) == epoch ? (uint32_t)(f & 3u) : 0u;
+    };
+    uint32_t rounds = 0, waits = 0;
     while (top >= 0) {
-        int st[kLbK];
-        int found = -1;  // window holding the nearest inclusive prefix
-        // every lane runs the same iterations, so the loop stays wave-uniform
+        ++rounds;
+        uint32_t stb = 0;  // bits 2q, 2q+1: state of predecessor top - lane - 64 q
+#pragma unroll
+        for (int q = 0; q < kLbW; ++q) stb |= state_of(top - lane - kWave * q) << (2 * q);
+        // nearest inclusive prefix: first window holding one, lowest lane in it
+        int fq = -1, fl = 0;
+        auto nearest_inclusive = [&]() {
+            fq = -1;
+            fl = 0;
+#pragma unroll
+            for (int q = 0; q < kLbW; ++q) {
+                const uint64_t m = __ballot(((stb >> (2 * q)) & 3u) == kStateInc);
+                if (fq < 0 && m) {
+                    fq = q;
+                    fl = __ffsll((unsigned long long)m) - 1;
+                }
+            }
+        };
+        nearest_inclusive();
+        auto needed = [&](int q) {
+            return fq < 0 || q < fq || (q == fq && lane <= fl);
+        };
+        // wait for the needed predecessors that had not published
         for (;;) {
+            bool pend = false;
 #pragma unroll
-            for (int q = 0; q < kLbK; ++q) {
-                const int32_t t = top - lane - kWave * q;
-                st[q] = (int)kStateInc;  // before tile 0: an empty inclusive prefix
-                if (t >= 0) {
-                    const uint64_t f = ld_flag(&lb[t].flag);
-                    st[q] = (f >> 2) == epoch ? (int)(f & 3u) : 0;
+            for (int q = 0; q < kLbW; ++q) {
+                if (needed(q) && ((stb >> (2 * q)) & 3u) == 0u) {
+                    const uint32_t s2 = state_of(top - lane - kWave * q);
+                    stb |= s2 << (2 * q);
+                    pend = pend || s2 == 0u;
                 }
             }
-            bool ready = true;
-            found = -1;
-#pragma unroll
-            for (int q = 0; q < kLbK; ++q) {
-                if (ready && found < 0) {
-                    if (__any(st[q] == 0)) ready = false;
-                    else if (__any(st[q] == (int)kStateInc)) found = q;
-                }
-            }
-            if (ready) break;
+            if (!__any(pend)) break;
+            ++waits;
             if (++spins > kSpinLimit) {
                 if (lane == 0)
                     __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                 return false;
             }
-            __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_s_sleep(2);
         }
+        // a predecessor polled again may have published its inclusive prefix
+        // meanwhile: the nearest one can only have moved closer, and every
+        // position before it is ready (tile 0 publishes no aggregate, so its
+        // inclusive prefix must be read when it is the nearest)
+        nearest_inclusive();
         order_acquire();  // payload loads stay after the flag loads
-        const int qmax = found < 0 ? kLbK - 1 : found;
-        double pay[kLbK][NC];
+        double sum[NC];
 #pragma unroll
-        for (int q = 0; q < kLbK; ++q) {
-            const int32_t t = top - lane - kWave * q;
-            bool take = q <= qmax && t >= 0;
-            if (q == found) {
-                const uint64_t m = __ballot(st[q] == (int)kStateInc);
-                take = take && lane <= __ffsll((unsigned long long)m) - 1;
+        for (int c = 0; c < NC; ++c) sum[c] = 0.0;
+#pragma unroll
+        for (int q0 = 0; q0 < kLbW; q0 += kBatch) {
+            if (fq >= 0 && q0 > fq) break;  // wave-uniform: nothing needed beyond
+            // one batch of loads in flight at a time (bounds the registers)
+            asm volatile("" ::: "memory");
+            double pay[kBatch][NC];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int q = q0 + k;
+                const int32_t t = top - lane - kWave * q;
+                const bool take = needed(q) && t >= 0;
+                const uint32_t off = (uint32_t)(take ? t : 0) * (uint32_t)sizeof(LbSlot) +
+                                     ((q == fq && lane == fl) ? (uint32_t)offsetof(LbSlot, inc)
+                                                              : (uint32_t)offsetof(LbSlot, agg));
+                const double *src = reinterpret_cast<const double *>(lbase + off);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) pay[k][c] = take ? ld_relaxed(src + c) : 0.0;
             }
-            const LbSlot *sl = lb + (take ? t : 0);
-            const double *src = st[q] == (int)kStateInc ? sl->inc : sl->agg;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) pay[q][c] = take ? ld_relaxed(src + c) : 0.0;
+            for (int k = 0; k < kBatch; ++k)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) sum[c] += pay[k][c];
         }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            double v = 0.0;
-#pragma unroll
-            for (int q = 0; q < kLbK; ++q) v += pay[q][c];
-            excl[c] += wave_sum(v);
-        }
-        if (found >= 0) break;
-        top -= kWave * kLbK;
+        for (int c = 0; c < NC; ++c) excl[c] += wave_sum(sum[c]);
+        if (fq >= 0) break;
+        top -= kWave * kLbW;
     }
+    if (lb_stats && lane == 0) *lb_stats = ((uint64_t)rounds << 32) | waits;
     return true;
 }
 
@@ -280,15 +318,49 @@ __device__ void finish(const FusedCall &a, const WsView &ws, uint64_t epoch,
     }
 }
 
+// Position map of a tile (BLOCK threads, IPT elements each): the tile is
+// R = IPT / CONSEC rows of BLOCK * CONSEC positions, and in every row a
+// thread holds CONSEC consecutive positions.  Element i = q * CONSEC + k of
+// thread tid sits at position
+//   q * BLOCK * CONSEC + tid * CONSEC + k.
+// Streaming alone, 8 doubles per thread per row (a wave's 16-byte loads then
+// cover whole 128-byte lines) reads at 6.5 TB/s against 4.6 TB/s for 16;
+// in this kernel, though, the second row costs registers (3 workgroups per
+// CU instead of 4) and the tile waits on its look-back far longer than on
+// its loads, so one row of 16 measured faster (0.89 ms against 0.93 ms at
+// N = 2^27).  kConsecMax keeps the choice in one place.
+constexpr int kConsecMax = 16;
+template <int IPT>
+struct TileMap {
+    static constexpr int CONSEC = IPT < kConsecMax ? IPT : kConsecMax;
+    static constexpr int R = IPT / CONSEC;
+};
+
+template <int BLOCK, int IPT>
+__device__ __forceinline__ int32_t tile_pos(int i, int t)
+{
+    constexpr int C = TileMap<IPT>::CONSEC;
+    return (i / C) * (BLOCK * C) + t * C + (i % C);
+}
+
+// Lane-major LDS slot of tile position r: [i * BLOCK + owner thread].
+template <int BLOCK, int IPT>
+__device__ __forceinline__ int32_t lds_slot(int32_t r)
+{
+    constexpr int C = TileMap<IPT>::CONSEC;
+    const int32_t q = r / (BLOCK * C), rem = r % (BLOCK * C);
+    return (q * C + rem % C) * BLOCK + rem / C;
+}
+
 // Stages one tile (positions [t0, t0+cnt)): e (patched by the pending step
 // of column jprev, which is also written back to eta and e), the weights w
-// (Fine-Gray) and the event counts d (one byte each) go to registers; of
-// column j only a bit per position stays in a register (returned: bit i for
-// position base + i) and, with VALS, the value sits in LDS at
-// s_xv[i * BLOCK + tid] (lane-consecutive, so reading it back is free of
-// bank conflicts).  All independent loads are issued together; the sparse
-// column and the patch travel through LDS flag bytes.  s_flag must be zero
-// and visible on entry; ends after one workgroup barrier.
+// (Fine-Gray) and the event counts d (one byte each, element i in byte i%4
+// of word i/4) go to registers; of column j only a bit per element stays in
+// a register (returned: bit i for element i) and, with VALS, the value sits
+// in LDS at s_xv[i * BLOCK + tid] (lane-major, free of bank conflicts).  All
+// independent loads are issued together; the sparse column and the patch
+// travel through LDS flag bytes (position order).  s_flag must be zero and
+// visible on entry; ends after one workgroup barrier.
 template <int BLOCK, int IPT, bool WANT_W, bool VALS, bool PREV, bool WANT_D>
 __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, int64_t cnt,
                                                int64_t chunk0, int64_t chunk1,
@@ -297,8 +369,11 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
                                                double (&wv)[WANT_W ? IPT : 1],
                                                uint32_t (&dw)[(IPT + 3) / 4])
 {
-    static_assert(IPT <= 32 && (IPT & (IPT - 1)) == 0, "IPT: a power of two up to 32");
+    static_assert(IPT <= 32 && (IPT & (IPT - 1)) == 0 && IPT >= 4,
+                  "IPT: a power of two from 4 to 32");
     constexpr int TILE = BLOCK * IPT;
+    constexpr int C = TileMap<IPT>::CONSEC;
+    constexpr int R = TileMap<IPT>::R;
     const int tid = threadIdx.x;
     ColTile cj = {0, 0, 0};
     if (a.j >= 0) cj = col_tile(a.col, a.j, chunk0, chunk1);
@@ -308,36 +383,39 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
         step_prev = *a.step_prev;
         cprev = col_tile(a.col, a.jprev, chunk0, chunk1);
     }
-    const int64_t base = t0 + (int64_t)tid * IPT;
     const bool full = cnt == TILE;
     if (full) {
-        const double2 *ep = reinterpret_cast<const double2 *>(a.e + base);
 #pragma unroll
-        for (int q = 0; q < IPT / 2; ++q) {
-            const double2 v = ep[q];
-            ev[2 * q] = v.x;
-            ev[2 * q + 1] = v.y;
-        }
-        if (WANT_D) {
-            if (IPT >= 8) {
-                const uint2 *dp = reinterpret_cast<const uint2 *>(a.d8 + base);
+        for (int q = 0; q < R; ++q) {
+            const int64_t rb = t0 + (int64_t)q * BLOCK * C + (int64_t)tid * C;
+            const double2 *ep = reinterpret_cast<const double2 *>(a.e + rb);
 #pragma unroll
-                for (int q = 0; q < IPT / 8; ++q) {
-                    const uint2 dd = dp[q];
-                    dw[2 * q] = dd.x;
-                    dw[2 * q + 1] = dd.y;
-                }
-            } else {
-                dw[0] = *reinterpret_cast<const uint32_t *>(a.d8 + base);
+            for (int h = 0; h < C / 2; ++h) {
+                const double2 v = ep[h];
+                ev[q * C + 2 * h] = v.x;
+                ev[q * C + 2 * h + 1] = v.y;
             }
-        }
-        if (WANT_W) {
-            const double2 *wp = reinterpret_cast<const double2 *>(a.w_comp + base);
+            if (WANT_D) {
+                if (C >= 8) {
+                    const uint2 *dp = reinterpret_cast<const uint2 *>(a.d8 + rb);
 #pragma unroll
-            for (int q = 0; q < IPT / 2; ++q) {
-                const double2 v = wp[q];
-                wv[2 * q] = v.x;
-                wv[2 * q + 1] = v.y;
+                    for (int h = 0; h < C / 8; ++h) {
+                        const uint2 dd = dp[h];
+                        dw[q * (C / 4) + 2 * h] = dd.x;
+                        dw[q * (C / 4) + 2 * h + 1] = dd.y;
+                    }
+                } else {
+                    dw[q] = *reinterpret_cast<const uint32_t *>(a.d8 + rb);
+                }
+            }
+            if (WANT_W) {
+                const double2 *wp = reinterpret_cast<const double2 *>(a.w_comp + rb);
+#pragma unroll
+                for (int h = 0; h < C / 2; ++h) {
+                    const double2 v = wp[h];
+                    wv[q * C + 2 * h] = v.x;
+                    wv[q * C + 2 * h + 1] = v.y;
+                }
             }
         }
     } else {
@@ -345,7 +423,7 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
         for (int q = 0; q < (IPT + 3) / 4; ++q) dw[q] = 0u;
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-            const int64_t k = base + i;
+            const int64_t k = t0 + tile_pos<BLOCK, IPT>(i, tid);
             const bool ok = k < a.n;
             ev[i] = ok ? a.e[k] : 0.0;
             if (WANT_D && ok) dw[i / 4] |= (uint32_t)a.d8[k] << (8 * (i % 4));
@@ -358,19 +436,22 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
                        (!VALS || ((uintptr_t)(a.col.vals + cj.cb + cj.lo) & 15u) == 0);
     if (dense) {
         if (VALS) {
-            const double2 *vp =
-                reinterpret_cast<const double2 *>(a.col.vals + cj.cb + cj.lo + tid * IPT);
 #pragma unroll
-            for (int q = 0; q < IPT / 2; ++q) {
-                const double2 v = vp[q];
-                s_xv[(2 * q) * BLOCK + tid] = v.x;
-                s_xv[(2 * q + 1) * BLOCK + tid] = v.y;
+            for (int q = 0; q < R; ++q) {
+                const double2 *vp = reinterpret_cast<const double2 *>(
+                    a.col.vals + cj.cb + cj.lo + q * BLOCK * C + tid * C);
+#pragma unroll
+                for (int h = 0; h < C / 2; ++h) {
+                    const double2 v = vp[h];
+                    s_xv[(q * C + 2 * h) * BLOCK + tid] = v.x;
+                    s_xv[(q * C + 2 * h + 1) * BLOCK + tid] = v.y;
+                }
             }
         }
     } else {
         for (int32_t o = cj.lo + tid; o < cj.hi; o += BLOCK) {
             const int32_t r = (int32_t)(a.col.rows[cj.cb + o] - t0);
-            if (VALS) s_xv[(r % IPT) * BLOCK + r / IPT] = a.col.vals[cj.cb + o];
+            if (VALS) s_xv[lds_slot<BLOCK, IPT>(r)] = a.col.vals[cj.cb + o];
             lds_flag_or(s_flag, r, kFlagX);
         }
     }
@@ -387,21 +468,28 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
         }
     }
     __syncthreads();
-    uint8_t fl[IPT];
-    lds_bytes<IPT>(s_flag + tid * IPT, fl);
     uint32_t xbits = 0u;
+    uint32_t pbits = 0u;
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) xbits |= (uint32_t)(fl[i] & kFlagX) << i;
+    for (int q = 0; q < R; ++q) {
+        uint8_t fl[C];
+        lds_bytes<C>(s_flag + q * BLOCK * C + tid * C, fl);
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            xbits |= (uint32_t)(fl[k] & kFlagX) << (q * C + k);
+            pbits |= (uint32_t)((fl[k] & kFlagPatch) ? 1u : 0u) << (q * C + k);
+        }
+    }
     if (dense) xbits = IPT == 32 ? ~0u : (1u << IPT) - 1u;
     if (PREV) {
 #pragma unroll
         for (int i = 0; i < IPT; ++i)
-            if (fl[i] & kFlagPatch) ev[i] = s_ep[tid * IPT + i];
+            if ((pbits >> i) & 1u) ev[i] = s_ep[tile_pos<BLOCK, IPT>(i, tid)];
     }
     return xbits;
 }
 
-// x of column j at position base + i of this thread (see stage_tile).
+// x of column j at element i of this thread (see stage_tile).
 template <int BLOCK, bool VALS>
 __device__ __forceinline__ double x_at(uint32_t xbits, int i, const double *s_xv)
 {
@@ -414,8 +502,7 @@ __device__ __forceinline__ double x_at(uint32_t xbits, int i, const double *s_xv
 // MODEL: SS_COX (3 tuple components) or SS_FINE_GRAY (6).  PREV: apply the
 // pending step of column jprev to eta and e first (step (1) of Sec. 2.7).
 template <int BLOCK, int IPT, int MODEL, bool VALS, bool PREV>
-__global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
-                                                 int64_t ntiles)
+__global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t ntiles)
 {
     constexpr int TILE = BLOCK * IPT;
     constexpr int NC = MODEL == SS_FINE_GRAY ? 6 : 3;
@@ -425,7 +512,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
     __shared__ __attribute__((aligned(16))) uint8_t s_flag[TILE];
     __shared__ double s_xv[VALS ? TILE : 1];
     __shared__ double s_ep[PREV ? TILE : 1];
-    __shared__ double s_wsum[NW][NC];
+    __shared__ double s_wsum[TileMap<IPT>::R][NW][NC];
     __shared__ double s_excl[NC];
     __shared__ double s_red[NW * 4];
     __shared__ double s_tsum[3];
@@ -454,59 +541,54 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
     const int64_t cnt = min((int64_t)TILE, a.n - t0);
 
     // ---- 2-4. tile data, column j and the pending update into registers
-    const int64_t base = t0 + (int64_t)tid * IPT;
+    constexpr int C = TileMap<IPT>::CONSEC;
+    constexpr int R = TileMap<IPT>::R;
     double ev[IPT];
     double wv[MODEL == SS_FINE_GRAY ? IPT : 1];
-    uint32_t dw[(IPT + 3) / 4];  // event counts, one byte per position
+    uint32_t dw[(IPT + 3) / 4];  // event counts, one byte per element
     const uint32_t xbits = stage_tile<BLOCK, IPT, MODEL == SS_FINE_GRAY, VALS, PREV, true>(
         a, t0, cnt, chunk0, chunk1, s_flag, s_xv, s_ep, ev, wv, dw);
     SS_TRACE(ws, tile, 1);
 
-    // ---- 5. thread totals of the tuple
-    double run[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) run[c] = 0.0;
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        const double x = x_at<BLOCK, VALS>(xbits, i, s_xv);
-        const double ex = ev[i] * x;
-        run[0] += ev[i];
-        run[1] += ex;
-        run[2] += ex * x;
-        if (MODEL == SS_FINE_GRAY) {
-            const double ew = ev[i] * wv[i];
-            const double exw = ew * x;
-            run[3] += ew;
-            run[4] += exw;
-            run[5] += exw * x;
-        }
-    }
-
-    // ---- 6. block scan of the thread totals
-    double incl[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) incl[c] = run[c];
-    wave_inclusive_scan<NC>(incl);
-    if (lane == kWave - 1) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) s_wsum[w][c] = incl[c];
-    }
-    __syncthreads();
-    double texcl[NC];  // exclusive prefix of this thread inside the tile
+    // ---- 5. the tile's aggregate: thread totals, then a block sum (the
+    // scan inside the tile waits until after the look-back, so that no
+    // per-row prefixes are held while the tile waits)
     double agg[NC];
+    {
+        double run[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        double before = 0.0, total = 0.0;
+        for (int c = 0; c < NC; ++c) run[c] = 0.0;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) {
-            if (q < w) before += s_wsum[q][c];
-            total += s_wsum[q][c];
+        for (int i = 0; i < IPT; ++i) {
+            const double x = x_at<BLOCK, VALS>(xbits, i, s_xv);
+            const double ex = ev[i] * x;
+            run[0] += ev[i];
+            run[1] += ex;
+            run[2] += ex * x;
+            if (MODEL == SS_FINE_GRAY) {
+                const double ew = ev[i] * wv[i];
+                const double exw = ew * x;
+                run[3] += ew;
+                run[4] += exw;
+                run[5] += exw * x;
+            }
         }
-        texcl[c] = before + incl[c] - run[c];
-        agg[c] = total;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double t = dpp_wave_sum(run[c]);
+            if (lane == 0) s_wsum[0][w][c] = t;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) t += s_wsum[0][v][c];
+            agg[c] = t;
+        }
     }
 
-    // ---- 7. decoupled look-back for the tile's exclusive prefix
+    // ---- 6. decoupled look-back for the tile's exclusive prefix
     SS_TRACE(ws, tile, 2);
     if (w == 0) {
         LbSlot *lb = reinterpret_cast<LbSlot *>(ws.lb);
@@ -517,9 +599,17 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
             for (int c = 0; c < NC; ++c) ex[c] = 0.0;
         } else {
             if (lane == 0) publish_lb<NC>(lb + tile, agg, false, epoch);
+            SS_TRACE(ws, tile, 6);
             // a wait that gives up has set the error word; the launch still
             // runs to its end
+#ifdef SS_TRACE_TIMES
+            uint64_t *lbs = tile == ntiles - 1 ? nullptr
+                : reinterpret_cast<uint64_t *>(ws.sw_bc + 8 * ws.max_tiles) + tile * 8 + 5;
+            (void)look_back<NC>(lb, tile, epoch, ws.hdr, ex, lbs);
+#else
             (void)look_back<NC>(lb, tile, epoch, ws.hdr, ex);
+#endif
+            SS_TRACE(ws, tile, 7);
             if (lane == 0) {
                 double inc[NC];
 #pragma unroll
@@ -534,8 +624,6 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
     }
     __syncthreads();
     SS_TRACE(ws, tile, 3);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) texcl[c] += s_excl[c];
     // the products of step 5 are recomputed below rather than kept live
     // across the look-back (registers bound how many tiles a CU holds)
     uint32_t xb = xbits;
@@ -545,50 +633,104 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws,
         for (int i = 0; i < IPT; ++i) asm volatile("" : "+v"(wv[i]));
     }
 
+    // ---- 7. scan inside the tile, row by row: thread-serial over the row
+    // segment, DPP across the wave, one barrier across the waves
+    double texcl[R][NC];  // exclusive prefix of this thread's segment of row q
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        double run[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) run[c] = 0.0;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int i = q * C + k;
+            const double x = x_at<BLOCK, VALS>(xb, i, s_xv);
+            const double ex = ev[i] * x;
+            run[0] += ev[i];
+            run[1] += ex;
+            run[2] += ex * x;
+            if (MODEL == SS_FINE_GRAY) {
+                const double ew = ev[i] * wv[i];
+                const double exw = ew * x;
+                run[3] += ew;
+                run[4] += exw;
+                run[5] += exw * x;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double inc = dpp_incl_scan(run[c]);
+            texcl[q][c] = inc - run[c];
+            if (lane == kWave - 1) s_wsum[q][w][c] = inc;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double done = s_excl[c];  // the tile's prefix plus rows before q
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            double before = 0.0, row = 0.0;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) {
+                if (v < w) before += s_wsum[q][v][c];
+                row += s_wsum[q][v][c];
+            }
+            texcl[q][c] += done + before;
+            done += row;
+        }
+    }
+
     double tot[3] = {0.0, 0.0, 0.0};
     if (MODEL == SS_FINE_GRAY) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) tot[c] = ws.hdr->fg_tot[c];
     }
 
-    // ---- 8. running prefix, transform at run ends, reduction
+    // ---- 8. running prefix, transform at run ends, reduction (the
+    // products are formed again, not kept from step 7)
+    asm volatile("" : "+v"(xb));
     double acc[3] = {0.0, 0.0, 0.0};
     LogSum lsum;
-    double S[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) S[c] = texcl[c];
+    for (int q = 0; q < R; ++q) {
+        double S[NC];
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        const double x = x_at<BLOCK, VALS>(xb, i, s_xv);
-        const double ex = ev[i] * x;
-        S[0] += ev[i];
-        S[1] += ex;
-        S[2] += ex * x;
-        if (MODEL == SS_FINE_GRAY) {
-            const double ew = ev[i] * wv[i];
-            const double exw = ew * x;
-            S[3] += ew;
-            S[4] += exw;
-            S[5] += exw * x;
-        }
-        int d = (int)((dw[i / 4] >> (8 * (i % 4))) & 255u);
-        if (d != 0) {
-            const int64_t k = base + i;
-            if (d == 255) d = a.d32[k];
-            double S0 = S[0], S1 = S[1], S2 = S[2];
+        for (int c = 0; c < NC; ++c) S[c] = texcl[q][c];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int i = q * C + k;
+            const double x = x_at<BLOCK, VALS>(xb, i, s_xv);
+            const double ex = ev[i] * x;
+            S[0] += ev[i];
+            S[1] += ex;
+            S[2] += ex * x;
             if (MODEL == SS_FINE_GRAY) {
-                const double g = a.g_end[k];
-                S0 += g * (tot[0] - S[3]);
-                S1 += g * (tot[1] - S[4]);
-                S2 += g * (tot[2] - S[5]);
+                const double ew = ev[i] * wv[i];
+                const double exw = ew * x;
+                S[3] += ew;
+                S[4] += exw;
+                S[5] += exw * x;
             }
-            const double r = 1.0 / S0;
-            const double G = S1 * r;
-            const double H = S2 * r;
-            const double dd = (double)d;
-            acc[0] += dd * G;
-            acc[1] += dd * (H - G * G);
-            if (a.want_log) lsum.add(S0, d);
+            int d = (int)((dw[i / 4] >> (8 * (i % 4))) & 255u);
+            if (d != 0) {
+                const int64_t kk = t0 + tile_pos<BLOCK, IPT>(i, tid);
+                if (d == 255) d = a.d32[kk];
+                double S0 = S[0], S1 = S[1], S2 = S[2];
+                if (MODEL == SS_FINE_GRAY) {
+                    const double g = a.g_end[kk];
+                    S0 += g * (tot[0] - S[3]);
+                    S1 += g * (tot[1] - S[4]);
+                    S2 += g * (tot[2] - S[5]);
+                }
+                const double r = 1.0 / S0;
+                const double G = S1 * r;
+                const double H = S2 * r;
+                const double dd = (double)d;
+                acc[0] += dd * G;
+                acc[1] += dd * (H - G * G);
+                if (a.want_log) lsum.add(S0, d);
+            }
         }
     }
     if (a.want_log) acc[2] = lsum.value();

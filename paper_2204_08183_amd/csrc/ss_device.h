@@ -83,27 +83,46 @@ __device__ __forceinline__ void block_sum(double (&x)[NC], double *s_red)
     }
 }
 
-// Sum of d log(s) over the events of one thread: for d = 1 (almost every
-// event) the mantissa of s multiplies a running product and its binary
-// exponent adds to an integer, so the sum is log(m) + k ln 2 with a single
-// logarithm at the end; other d take their logarithm directly.  Mantissas
-// lie in [1/2, 1), so up to 1000 factors cannot underflow.
+// Sum of d log(s) over the events of one thread, kept as log(m) + k ln 2:
+// s = f 2^e with f in [1/2, 1) contributes f^d to the product m and d e to
+// the integer k, so a thread takes a single logarithm at the end.  f^d is
+// formed by binary powering with the product renormalised after every
+// multiplication (d = 1, almost every event, is one multiplication); m
+// stays in [1/2, 1) between calls.
 struct LogSum {
     double m = 1.0;
-    int k = 0;
-    double rest = 0.0;
+    int64_t k = 0;
+    __device__ __forceinline__ void renorm(double &x, int64_t &kx)
+    {
+        kx += __builtin_amdgcn_frexp_exp(x);
+        x = __builtin_amdgcn_frexp_mant(x);
+    }
     __device__ __forceinline__ void add(double s, int d)
     {
+        double f = __builtin_amdgcn_frexp_mant(s);
+        k += (int64_t)__builtin_amdgcn_frexp_exp(s) * d;
         if (d == 1) {
-            m *= __builtin_amdgcn_frexp_mant(s);
-            k += __builtin_amdgcn_frexp_exp(s);
+            m *= f;
         } else {
-            rest += (double)d * log(s);
+            int64_t kf = 0;  // the base is f 2^kf
+            for (uint32_t e = (uint32_t)d; e != 0u; e >>= 1) {
+                if (e & 1u) {
+                    m *= f;
+                    k += kf;
+                    renorm(m, k);
+                }
+                if (e > 1u) {
+                    f *= f;
+                    kf *= 2;
+                    renorm(f, kf);
+                }
+            }
         }
+        renorm(m, k);
     }
     __device__ __forceinline__ double value() const
     {
-        return rest + ((double)k * 0.69314718055994530942 + log(m));
+        return (double)k * 0.69314718055994530942 + log(m);
     }
 };
 
@@ -476,6 +495,112 @@ __device__ __forceinline__ void ld_pairs2<11>(const u32x4 *p, u32x4 (&r0)[11],
                  : "memory");
 }
 
+
+
+// Loads NC consecutive pairs at each of KQ addresses and waits for all of
+// them (the look-back's predecessor windows).
+template <int KQ, int NC>
+__device__ __forceinline__ void ld_lb(const u32x4 *const (&p)[KQ], u32x4 (&r)[KQ][NC]);
+
+template <>
+__device__ __forceinline__ void ld_lb<4, 3>(const u32x4 *const (&p)[4],
+                                               u32x4 (&r)[4][3])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %12, off sc1\n\t"
+                 "global_load_dwordx4 %1, %12, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %12, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %13, off sc1\n\t"
+                 "global_load_dwordx4 %4, %13, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %5, %13, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %6, %14, off sc1\n\t"
+                 "global_load_dwordx4 %7, %14, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %8, %14, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %9, %15, off sc1\n\t"
+                 "global_load_dwordx4 %10, %15, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %11, %15, off offset:32 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0][0]), "=&v"(r[0][1]), "=&v"(r[0][2]), "=&v"(r[1][0]), "=&v"(r[1][1]), "=&v"(r[1][2]), "=&v"(r[2][0]), "=&v"(r[2][1]), "=&v"(r[2][2]), "=&v"(r[3][0]), "=&v"(r[3][1]), "=&v"(r[3][2])
+                 : "v"(p[0]), "v"(p[1]), "v"(p[2]), "v"(p[3])
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_lb<3, 3>(const u32x4 *const (&p)[3],
+                                               u32x4 (&r)[3][3])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %9, off sc1\n\t"
+                 "global_load_dwordx4 %1, %9, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %9, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %10, off sc1\n\t"
+                 "global_load_dwordx4 %4, %10, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %5, %10, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %6, %11, off sc1\n\t"
+                 "global_load_dwordx4 %7, %11, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %8, %11, off offset:32 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0][0]), "=&v"(r[0][1]), "=&v"(r[0][2]), "=&v"(r[1][0]), "=&v"(r[1][1]), "=&v"(r[1][2]), "=&v"(r[2][0]), "=&v"(r[2][1]), "=&v"(r[2][2])
+                 : "v"(p[0]), "v"(p[1]), "v"(p[2])
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_lb<2, 3>(const u32x4 *const (&p)[2],
+                                               u32x4 (&r)[2][3])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %6, off sc1\n\t"
+                 "global_load_dwordx4 %1, %6, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %6, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %7, off sc1\n\t"
+                 "global_load_dwordx4 %4, %7, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %5, %7, off offset:32 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0][0]), "=&v"(r[0][1]), "=&v"(r[0][2]), "=&v"(r[1][0]), "=&v"(r[1][1]), "=&v"(r[1][2])
+                 : "v"(p[0]), "v"(p[1])
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_lb<2, 6>(const u32x4 *const (&p)[2],
+                                               u32x4 (&r)[2][6])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %12, off sc1\n\t"
+                 "global_load_dwordx4 %1, %12, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %12, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %12, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %12, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %12, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %13, off sc1\n\t"
+                 "global_load_dwordx4 %7, %13, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %8, %13, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %9, %13, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %10, %13, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %11, %13, off offset:80 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0][0]), "=&v"(r[0][1]), "=&v"(r[0][2]), "=&v"(r[0][3]), "=&v"(r[0][4]), "=&v"(r[0][5]), "=&v"(r[1][0]), "=&v"(r[1][1]), "=&v"(r[1][2]), "=&v"(r[1][3]), "=&v"(r[1][4]), "=&v"(r[1][5])
+                 : "v"(p[0]), "v"(p[1])
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_lb<1, 6>(const u32x4 *const (&p)[1],
+                                               u32x4 (&r)[1][6])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %6, off sc1\n\t"
+                 "global_load_dwordx4 %1, %6, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %6, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %6, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %6, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %6, off offset:80 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0][0]), "=&v"(r[0][1]), "=&v"(r[0][2]), "=&v"(r[0][3]), "=&v"(r[0][4]), "=&v"(r[0][5])
+                 : "v"(p[0])
+                 : "memory");
+}
 
 }  // namespace dev
 }  // namespace ss
