@@ -42,22 +42,168 @@ using namespace dev;
 #endif
 
 // ---------------------------------------------------------------- look-back
-// Decoupled look-back (single-pass chained scan, Sec. 2.6).  A tile's slot
-// holds a flag word (epoch << 2) | state (1: aggregate published, 2:
-// inclusive prefix published) and the two payloads; a payload is written
-// before its flag (release order) and read after it (acquire order).
+// Decoupled look-back (single-pass chained scan, Sec. 2.6), in two
+// variants; a launch uses one of them throughout (chosen by tile size).
 //
-// Wave 0 of the tile does the look-back (see look_back below).  Polling by
-// one wave, and re-polling only what is missing, keeps the flag traffic of
-// the tiles waiting at once small next to the data stream (all four waves
-// polling whole windows was measured slower).  Every predecessor started earlier (workgroups start in index
-// order on each XCD) and publishes its aggregate without waiting on anyone,
-// so the wait ends; it is bounded all the same.
+// Pairs (large tiles, large N): a tile's slot holds its NC values as
+// 16-byte (value, tag) pairs, tag = (epoch << 2) | state with state 1 = tile
+// aggregate and 2 = inclusive prefix; the inclusive prefix overwrites the
+// aggregate in place.  Each pair is written and read as one 16-byte access,
+// so a reader that sees all NC tags equal has a consistent snapshot (mixed
+// tags: the slot is being overwritten, not ready yet), and one load brings a
+// predecessor's state and value together: no flag word, no ordering wait on
+// either side.  While the data stream saturates memory a round trip through
+// the coherence point takes ~5 us, and one round trip instead of two (flags,
+// then payloads) took the look-back from 11 to 5 us per tile at N = 2^27.
+//
+// Flags (small tiles, small N): an 8-byte flag per tile and separate
+// payloads.  When every tile of a launch is resident at once (N up to a few
+// million) all of them look back together, and polling 48 bytes per
+// predecessor instead of 8 made those launches slower.
+//
+// In both, wave 0 looks back over windows of 64 predecessors per round: one
+// load round trip for a round, the nearest inclusive prefix fixes which
+// predecessors are needed, and only the needed ones that were not ready are
+// polled again.  Every predecessor started earlier (workgroups start in
+// index order on each XCD) and publishes its aggregate without waiting on
+// anyone, so the wait ends; it is bounded all the same.
+constexpr int kLbSlot = 8;  // pairs per tile slot (128 bytes)
+
+// Lanes 0 .. NC-1 of the calling wave store one pair each.
+template <int NC>
+__device__ __forceinline__ void publish_pairs(u32x4 *slot, const double (&v)[NC],
+                                              uint64_t tag)
+{
+    const int lane = lane_id();
+    double x = v[0];
+#pragma unroll
+    for (int c = 1; c < NC; ++c)
+        if (lane == c) x = v[c];
+    if (lane < NC) st_pair(slot + lane, x, tag);
+}
+
+// Wave 0 only; the exclusive prefix is returned in every lane.  Returns
+// false if the wait gave up (the error word is then set).
+template <int NC>
+__device__ bool look_back_pairs(const u32x4 *lb, int64_t tile, uint64_t epoch, WsHeader *hdr,
+                          double (&excl)[NC], uint64_t *lb_stats = nullptr)
+{
+    constexpr int kLbW = NC > 3 ? 2 : 4;  // windows of 64 per round
+    const int lane = lane_id();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) excl[c] = 0.0;
+    // tile indices fit in 32 bits (n < 2^31, tiles of at least 1024)
+    int32_t top = (int32_t)tile - 1;
+    uint32_t spins = 0;
+    uint32_t rounds = 0, waits = 0;
+    // state of a snapshot: all tags equal and of this launch, else 0
+    auto state_of = [&](const u32x4 (&r)[NC]) -> uint32_t {
+        const uint64_t t0 = pair_tag(r[0]);
+        bool same = (t0 >> 2) == epoch;
+#pragma unroll
+        for (int c = 1; c < NC; ++c) same = same && pair_tag(r[c]) == t0;
+        return same ? (uint32_t)(t0 & 3u) : 0u;
+    };
+    while (top >= 0) {
+        ++rounds;
+        // lanes before tile 0 read the tile's own slot instead (one request
+        // per wave; a shared dummy address would be hammered by every tile)
+        const u32x4 *ptr[kLbW];
+#pragma unroll
+        for (int q = 0; q < kLbW; ++q) {
+            const int32_t t = top - lane - kWave * q;
+            ptr[q] = lb + (int64_t)(t >= 0 ? t : (int32_t)tile) * kLbSlot;
+        }
+        double val[kLbW][NC];
+        uint32_t stb = 0;  // bits 2q, 2q+1: state of predecessor top - lane - 64 q
+        {
+            u32x4 r[kLbW][NC];
+            ld_lb<kLbW, NC>(ptr, r);
+#pragma unroll
+            for (int q = 0; q < kLbW; ++q) {
+                const int32_t t = top - lane - kWave * q;
+                // before tile 0: an empty inclusive prefix
+                const uint32_t st = t < 0 ? (uint32_t)kStateInc : state_of(r[q]);
+                stb |= st << (2 * q);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) val[q][c] = t < 0 ? 0.0 : pair_value(r[q][c]);
+            }
+        }
+        // nearest inclusive prefix: first window holding one, lowest lane in it
+        int fq = -1, fl = 0;
+        auto nearest_inclusive = [&]() {
+            fq = -1;
+            fl = 0;
+#pragma unroll
+            for (int q = 0; q < kLbW; ++q) {
+                const uint64_t m = __ballot(((stb >> (2 * q)) & 3u) == kStateInc);
+                if (fq < 0 && m) {
+                    fq = q;
+                    fl = __ffsll((unsigned long long)m) - 1;
+                }
+            }
+        };
+        nearest_inclusive();
+        auto needed = [&](int q) {
+            return fq < 0 || q < fq || (q == fq && lane <= fl);
+        };
+        // poll again only the needed predecessors that were not ready
+        for (;;) {
+            bool pend = false;
+#pragma unroll
+            for (int q = 0; q < kLbW; ++q) {
+                if (needed(q) && ((stb >> (2 * q)) & 3u) == 0u) {
+                    u32x4 r[NC];
+                    ld_pairs<NC>(ptr[q], r);
+                    const uint32_t st = state_of(r);
+                    stb |= st << (2 * q);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) val[q][c] = pair_value(r[c]);
+                    pend = pend || st == 0u;
+                }
+            }
+            if (!__any(pend)) break;
+            ++waits;
+            if (++spins > kSpinLimit) {
+                if (lane == 0)
+                    __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        // a predecessor polled again may now hold its inclusive prefix: the
+        // nearest one can only have moved closer, and every position before it
+        // is ready
+        nearest_inclusive();
+        double sum[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sum[c] = 0.0;
+#pragma unroll
+        for (int q = 0; q < kLbW; ++q) {
+            const bool take = needed(q);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sum[c] += take ? val[q][c] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) excl[c] += wave_sum(sum[c]);
+        if (fq >= 0) break;
+        top -= kWave * kLbW;
+    }
+    if (lb_stats && lane == 0) *lb_stats = ((uint64_t)rounds << 32) | waits;
+    return true;
+}
+
+
+// ---------------------------------------------------- look-back, flags
+// Slot: flag word (epoch << 2) | state and the two payloads; a payload is
+// written before its flag (release order) and read after it (acquire order).
 struct alignas(128) LbSlot {
     uint64_t flag;
     double agg[kMaxComp];
     double inc[kMaxComp];
 };
+static_assert(sizeof(LbSlot) == 16 * kLbSlot, "both look-back variants use 128-byte slots");
 
 // Wave 0, lane 0: payload, then flag.
 template <int NC>
@@ -80,7 +226,7 @@ __device__ __forceinline__ void publish_lb(LbSlot *slot, const double (&v)[NC], 
 // and each needed payload is loaded once (aggregate, or the inclusive prefix
 // at the nearest one).  The states stay packed, two bits per predecessor.
 template <int NC>
-__device__ bool look_back(const LbSlot *lb, int64_t tile, uint64_t epoch, WsHeader *hdr,
+__device__ bool look_back_flags(const LbSlot *lb, int64_t tile, uint64_t epoch, WsHeader *hdr,
                           double (&excl)[NC], uint64_t *lb_stats = nullptr)
 {
     constexpr int kLbW = 4;  // windows of 64 per round (8 measured slower: registers)
@@ -183,19 +329,6 @@ __device__ bool look_back(const LbSlot *lb, int64_t tile, uint64_t epoch, WsHead
     }
     if (lb_stats && lane == 0) *lb_stats = ((uint64_t)rounds << 32) | waits;
     return true;
-}
-
-// Lanes 0 .. NC-1 of the calling wave store one pair each.
-template <int NC>
-__device__ __forceinline__ void publish_pairs(u32x4 *slot, const double (&v)[NC],
-                                              uint64_t tag)
-{
-    const int lane = lane_id();
-    double x = v[0];
-#pragma unroll
-    for (int c = 1; c < NC; ++c)
-        if (lane == c) x = v[c];
-    if (lane < NC) st_pair(slot + lane, x, tag);
 }
 
 // Polls three pairs until all carry `tag`; false if the wait gave up (then
@@ -591,31 +724,37 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     // ---- 6. decoupled look-back for the tile's exclusive prefix
     SS_TRACE(ws, tile, 2);
     if (w == 0) {
-        LbSlot *lb = reinterpret_cast<LbSlot *>(ws.lb);
+        constexpr bool kPairs = IPT >= 8;  // see the look-back notes above
+        u32x4 *slot = ws.lb + tile * kLbSlot;
+        LbSlot *fslot = reinterpret_cast<LbSlot *>(ws.lb) + tile;
         double ex[NC];
+        uint64_t *lbs = nullptr;
+#ifdef SS_TRACE_TIMES
+        if (tile != ntiles - 1)
+            lbs = reinterpret_cast<uint64_t *>(ws.sw_bc + 8 * ws.max_tiles) + tile * 8 + 5;
+#endif
         if (tile == 0) {
-            if (lane == 0) publish_lb<NC>(lb, agg, true, epoch);
+            if (kPairs) publish_pairs<NC>(slot, agg, (epoch << 2) | kStateInc);
+            else if (lane == 0) publish_lb<NC>(fslot, agg, true, epoch);
 #pragma unroll
             for (int c = 0; c < NC; ++c) ex[c] = 0.0;
         } else {
-            if (lane == 0) publish_lb<NC>(lb + tile, agg, false, epoch);
+            if (kPairs) publish_pairs<NC>(slot, agg, (epoch << 2) | kStateAgg);
+            else if (lane == 0) publish_lb<NC>(fslot, agg, false, epoch);
             SS_TRACE(ws, tile, 6);
             // a wait that gives up has set the error word; the launch still
             // runs to its end
-#ifdef SS_TRACE_TIMES
-            uint64_t *lbs = tile == ntiles - 1 ? nullptr
-                : reinterpret_cast<uint64_t *>(ws.sw_bc + 8 * ws.max_tiles) + tile * 8 + 5;
-            (void)look_back<NC>(lb, tile, epoch, ws.hdr, ex, lbs);
-#else
-            (void)look_back<NC>(lb, tile, epoch, ws.hdr, ex);
-#endif
+            if (kPairs)
+                (void)look_back_pairs<NC>(ws.lb, tile, epoch, ws.hdr, ex, lbs);
+            else
+                (void)look_back_flags<NC>(reinterpret_cast<const LbSlot *>(ws.lb), tile, epoch,
+                                          ws.hdr, ex, lbs);
             SS_TRACE(ws, tile, 7);
-            if (lane == 0) {
-                double inc[NC];
+            double inc[NC];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) inc[c] = ex[c] + agg[c];
-                publish_lb<NC>(lb + tile, inc, true, epoch);
-            }
+            for (int c = 0; c < NC; ++c) inc[c] = ex[c] + agg[c];
+            if (kPairs) publish_pairs<NC>(slot, inc, (epoch << 2) | kStateInc);
+            else if (lane == 0) publish_lb<NC>(fslot, inc, true, epoch);
         }
         if (lane == 0) {
 #pragma unroll
