@@ -19,6 +19,8 @@
 // (Sec. 2.7).  The Fine-Gray suffix over later competing events is the
 // grand total minus the inclusive prefix of the weighted components; the
 // totals come from a short reduction pass launched just before.
+#include <algorithm>
+
 #include "ss_device.h"
 
 namespace ss {
@@ -34,8 +36,7 @@ using namespace dev;
 #define SS_TRACE(ws, tile, slot)                                                   \
     do {                                                                           \
         if (threadIdx.x == 0)                                                      \
-            reinterpret_cast<uint64_t *>((ws).sw_bc + 8 * (ws).max_tiles)          \
-                [(tile) * 8 + (slot)] = __builtin_amdgcn_s_memrealtime();          \
+            trace_base(ws)[(tile) * 8 + (slot)] = __builtin_amdgcn_s_memrealtime(); \
     } while (0)
 #else
 #define SS_TRACE(ws, tile, slot) do { } while (0)
@@ -731,7 +732,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
         uint64_t *lbs = nullptr;
 #ifdef SS_TRACE_TIMES
         if (tile != ntiles - 1)
-            lbs = reinterpret_cast<uint64_t *>(ws.sw_bc + 8 * ws.max_tiles) + tile * 8 + 5;
+            lbs = trace_base(ws) + tile * 8 + 5;
 #endif
         if (tile == 0) {
             if (kPairs) publish_pairs<NC>(slot, agg, (epoch << 2) | kStateInc);
@@ -1028,8 +1029,8 @@ size_t fused_ws_bytes(int64_t n)
     b = align_up(b + 16 * 4 * (size_t)tiles, 256);   // sw_part
     b = align_up(b + 16 * (size_t)tiles, 256);       // sw_step
     b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // sw_pre
-    b = align_up(b + 16 * 16 * (size_t)tiles, 256);  // sw_pub
-    b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // sw_bc
+    b = align_up(b + 16 * 16 * (size_t)std::max<int64_t>(tiles, 2 * kMaxSweepBlocks),
+                 256);                                // sw_pub
 #ifdef SS_TRACE_TIMES
     b = align_up(b + sizeof(uint64_t) * 64 * (size_t)tiles, 256);
 #endif
@@ -1059,8 +1060,7 @@ bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v)
     v->sw_part = take(16 * 4 * (size_t)tiles);
     v->sw_step = take(16 * (size_t)tiles);
     v->sw_pre = take(16 * 8 * (size_t)tiles);
-    v->sw_pub = take(16 * 16 * (size_t)tiles);
-    v->sw_bc = take(16 * 8 * (size_t)tiles);
+    v->sw_pub = take(16 * 16 * (size_t)std::max<int64_t>(tiles, 2 * kMaxSweepBlocks));
     v->max_tiles = tiles;
     return true;
 }

@@ -602,5 +602,6 @@ __device__ __forceinline__ void ld_lb<1, 6>(const u32x4 *const (&p)[1],
                  : "memory");
 }
 
+
 }  // namespace dev
 }  // namespace ss

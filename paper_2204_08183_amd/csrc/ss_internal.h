@@ -94,7 +94,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // and U = ceil(T / kGroup) + 1 tile groups:
 //   WsHeader | lb[T][8] | part[T][4] | fg_part[T][4] | gpart[U][4] |
 //   fg_gpart[U][4] | sw_agg[T][8] | sw_part[T][4] | sw_step[T] |
-//   sw_pre[T][8] | sw_pub[T][16] | sw_bc[T][8]
+//   sw_pre[T][8] | sw_pub[max(T, 2 kMaxSweepBlocks)][16]
 struct alignas(256) WsHeader {
     uint64_t epoch;       // number of completed fused launches
     uint64_t fg_epoch;    // number of completed Fine-Gray totals passes
@@ -114,6 +114,9 @@ constexpr uint64_t kStateInc = 2;
 // Tiles per group of the two-level reduction of the per-tile partial sums.
 constexpr int kGroup = 64;
 
+// Upper bound on the number of workgroups (segments) of one persistent sweep.
+constexpr int kMaxSweepBlocks = 512;
+
 // Upper bound on polls of one bounded wait before it gives up (each poll is
 // an uncached load plus a short sleep, so this is on the order of a second).
 constexpr uint32_t kSpinLimit = 1u << 20;
@@ -130,10 +133,19 @@ struct WsView {
     u32x4 *sw_part;   // [max_tiles][4]
     u32x4 *sw_step;   // [max_tiles]
     u32x4 *sw_pre;    // [max_tiles][8]
-    u32x4 *sw_pub;    // [max_tiles][16]
-    u32x4 *sw_bc;     // [max_tiles][8]
+    u32x4 *sw_pub;    // [max(max_tiles, 2 kMaxSweepBlocks)][16]
     int64_t max_tiles;
 };
+
+#ifdef SS_TRACE_TIMES
+// Phase timestamps of analysis builds live behind the regular workspace:
+// 8 slots per tile (fused kernels) or 8 x 8 per workgroup (sweeps).
+__device__ __forceinline__ uint64_t *trace_base(const WsView &ws)
+{
+    const int64_t np = ws.max_tiles > 2 * kMaxSweepBlocks ? ws.max_tiles : 2 * kMaxSweepBlocks;
+    return reinterpret_cast<uint64_t *>(ws.sw_pub + 16 * np);
+}
+#endif
 
 size_t fused_ws_bytes(int64_t n);
 bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v);

@@ -37,7 +37,7 @@ using namespace dev;
 #define SW_TRACE(a, b, jj, slot)                                                    \
     do {                                                                            \
         if (threadIdx.x == 0 && (jj) - (a).j_begin < 8)                             \
-            reinterpret_cast<uint64_t *>((a).ws.sw_bc + 8 * (a).ws.max_tiles)      \
+            trace_base((a).ws)                                                      \
                 [((b) * 8 + ((jj) - (a).j_begin)) * 8 + (slot)] =                   \
                 __builtin_amdgcn_s_memrealtime();                                   \
     } while (0)
@@ -111,8 +111,6 @@ __device__ __forceinline__ void apply_step(const SweepArgs &a, int32_t jc, doubl
     }
 }
 
-// Upper bound on the number of workgroups (segments) of one sweep.
-constexpr int kMaxSweepBlocks = 512;
 
 template <int BLOCK, int IPT, int MODEL, bool VALS>
 __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
@@ -514,22 +512,29 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
 //
 // With x in {0, 1}, the update of column j multiplies e by exp(s_j) at the
 // rows of column j, so a segment's tuple aggregate for the next coordinate
-// is  A + expm1(s_j) D  with  A = sum e (1, x_{j+1}, x_{j+1}^2)  over the
-// segment and  D  the same sum over the rows of column j -- both known
-// before s_j is.  Every workgroup therefore publishes, in one go, its
-// partial sums for coordinate j together with A and D for coordinate j+1;
-// workgroup 0 adds the partials, takes the coordinate update, forms every
-// segment's aggregate for j+1, scans them in segment order and broadcasts
-// (s_j, exclusive prefix) to each workgroup: one round trip per coordinate.
+// is  A + expm1(s_j) D  with  A = sum e (1, x_{j+1})  over the segment and D
+// the same sum over the rows of column j -- both known before s_j is.  Every
+// workgroup therefore publishes, in one go, its partial sums for coordinate
+// j together with A and D for coordinate j+1, then reads all G publications
+// itself, forms the sums in the same fixed order, takes the same coordinate
+// update (bit-identical everywhere) and its own prefix
+// scan(A) + expm1(s_j) scan(D) over the segments before it.  (Gathering in
+// workgroup 0 and broadcasting back was measured slower: 9.9 against 8.4 us
+// per coordinate at N = 1e6, Cox.)
 //
-// Between receiving the broadcast and publishing, a workgroup touches no
-// global memory: eta of its segment lives in LDS and e in registers, the
-// update of the previous column is applied in place (eta += s, e *= exp(s)),
-// and the rows of column j+2 are scattered into LDS while the workgroup
-// waits for the broadcast.  Column c's rows live in bit (c mod 3) of the
-// LDS flag bytes, so the previous column, the current one and the next one
-// are all at hand.  eta and e = exp(eta) go back to global memory once, at
-// the end of the sweep.
+// Between its publication and the next coordinate's a workgroup touches
+// global memory only for the exchange itself: e in registers, eta of its
+// segment in LDS, the previous column patched in place (eta += s,
+// e *= exp(s)), the rows of column j+2 scattered into LDS while the
+// publications arrive.  Column c's rows live in bit (c mod 3) of the LDS
+// flag bytes.  eta and e = exp(eta) go back to global memory once, at the
+// end of the sweep.  Publications alternate between two slot sets by round parity:
+// a workgroup can be at most one round ahead of the slowest reader (it
+// needs everyone's publication of a round before it can publish the next),
+// so a slot is never overwritten before all have read it.  c_j, beta_j and
+// delta_j are read before publishing round j, and workgroup 0 writes beta_j
+// and delta_j only after it has read every publication of that round, so
+// no workgroup can see the updated values for the same coordinate.
 template <int BLOCK, int IPT, int MODEL>
 __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
 {
@@ -540,10 +545,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
     constexpr int NT = FG ? 4 : 2;
     constexpr int NW = BLOCK / kWave;
     constexpr int NPUB = 3 + 2 * NT;  // partial sums, A, D
-    constexpr int NBC = 1 + NT;       // step, prefix (Fine-Gray: suffix starts)
-    constexpr int NLEAD = 3 + 2 * NT; // per-wave totals in the leader round
+    // block sums after a gather: partials (3), A and D before this segment
+    // (2 NT), and for Fine-Gray the totals of the weighted A and D (4)
+    constexpr int NSUM = 3 + 2 * NT + (FG ? 4 : 0);
     constexpr int K = (kMaxSweepBlocks + BLOCK - 1) / BLOCK;
-    static_assert(K <= 2, "the leader takes at most two segments per thread");
+    static_assert(K <= 2, "at most two segments per thread in a gather");
     static_assert(S % SS_CHUNK == 0, "segment must be whole chunks");
 
     __shared__ __attribute__((aligned(16))) uint8_t s_flag[S];
@@ -551,10 +557,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
     __shared__ double s_g[FG ? S : 1];   // G(y) at each position, same layout
     __shared__ double s_wsum[NW][NT];
     __shared__ double s_wred[NW][NPUB];
-    __shared__ double s_lead[NW][NLEAD];  // leader round only
-    __shared__ double s_bc[NBC];
+    __shared__ double s_sum[2][NW][NSUM];  // by round parity
     __shared__ uint64_t s_ep0;
-    __shared__ double s_step;
     __shared__ int s_abort;
 
     const int tid = threadIdx.x;
@@ -640,8 +644,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
 #pragma unroll
         for (int q = 0; q < IPT / 4; ++q) f32[q] &= keep;
     };
+    // Publication slot of segment q in round r: two sets by parity.
+    auto pub_slot = [&](uint64_t r, int64_t q) {
+        return a.ws.sw_pub + ((int64_t)(r & 1u) * kMaxSweepBlocks + q) * 16;
+    };
     // Block sums of NPUB values, published by thread 0 as pairs.
-    auto publish = [&](double (&v)[NPUB], uint64_t tag) {
+    auto publish = [&](double (&v)[NPUB], uint64_t r, uint64_t tag) {
 #pragma unroll
         for (int c = 0; c < NPUB; ++c) {
             const double t = dpp_wave_sum(v[c]);
@@ -649,39 +657,34 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
         }
         __syncthreads();
         if (tid == 0) {
+            u32x4 *dst = pub_slot(r, b);
 #pragma unroll
             for (int c = 0; c < NPUB; ++c) {
                 double t = 0.0;
 #pragma unroll
                 for (int q = 0; q < NW; ++q) t += s_wred[q][c];
-                st_pair(a.ws.sw_pub + b * 16 + c, t, tag);
+                st_pair(dst + c, t, tag);
             }
         }
     };
-    // Workgroup 0: gathers every workgroup's (partials, A, D), takes the
-    // update of column jc (none when jc < 0), and broadcasts (step, prefix).
-    // The exclusive scans of A and D over the segments run alongside the
-    // sum of the partials; the prefix of each segment is then
-    // scan(A) + expm1(s) scan(D).
-    auto leader_round = [&](int32_t jc, uint64_t tag) -> bool {
-        double cj = 0.0, bj = 0.0, dj = 0.0;
-        if (tid == 0 && jc >= 0) {  // in flight while the partials arrive
-            cj = a.c[jc];
-            bj = a.beta[jc];
-            dj = a.delta[jc];
-        }
+    // Reads every segment's publication of round r and forms the sums in a
+    // fixed order (identical in every workgroup): out[0..2] partial sums,
+    // out[3..] A and D over the segments before this one (then, for
+    // Fine-Gray, the totals of the weighted A and D).  Returns false if a
+    // wait gave up.
+    auto gather = [&](uint64_t r, uint64_t tag, double (&out)[NSUM]) -> bool {
         double v[K][NPUB];
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int c = 0; c < NPUB; ++c) v[k][c] = 0.0;
         bool bad = false;
-        const int q0 = tid * K;
+        const int q0 = tid * K;  // segments q0 .. q0 + K - 1
         if (K == 2 && q0 + 1 < G) {
             u32x4 r0[NPUB], r1[NPUB];
             uint32_t spins = 0;
             for (;;) {
-                ld_pairs2<NPUB>(a.ws.sw_pub + (int64_t)q0 * 16, r0, r1);
+                ld_pairs2<NPUB>(pub_slot(r, q0), r0, r1);
                 bool ok = true;
 #pragma unroll
                 for (int c = 0; c < NPUB; ++c)
@@ -704,136 +707,68 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
                 }
             }
         } else if (q0 < G) {
-            u32x4 r[NPUB];
-            if (wait_pairs<NPUB>(a.ws.sw_pub + (int64_t)q0 * 16, tag, hdr, r)) {
+            u32x4 rr[NPUB];
+            if (wait_pairs<NPUB>(pub_slot(r, q0), tag, hdr, rr)) {
 #pragma unroll
-                for (int c = 0; c < NPUB; ++c) v[0][c] = pair_value(r[c]);
+                for (int c = 0; c < NPUB; ++c) v[0][c] = pair_value(rr[c]);
             } else {
                 bad = true;
             }
         }
-        // thread totals: partial sums, and A, D for the scans
-        double ps[3], tA[NT], tD[NT];
+        double t[NSUM];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double t = 0.0;
-#pragma unroll
-            for (int k = 0; k < K; ++k) t += v[k][c];
-            ps[c] = dpp_wave_sum(t);
-        }
-        double iA[NT], iD[NT];
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            double ta = 0.0, td = 0.0;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                ta += v[k][3 + c];
-                td += v[k][3 + NT + c];
-            }
-            tA[c] = ta;
-            tD[c] = td;
-            iA[c] = dpp_incl_scan(ta);
-            iD[c] = dpp_incl_scan(td);
-        }
-        if (lane == kWave - 1) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) s_lead[w][c] = ps[c];
-#pragma unroll
-            for (int c = 0; c < NT; ++c) {
-                s_lead[w][3 + c] = iA[c];
-                s_lead[w][3 + NT + c] = iD[c];
-            }
-        }
-        if (jc >= 0) SW_TRACE(a, b, jc, 6);
-        if (__syncthreads_or(bad)) return false;
-        if (tid == 0) {
-            double st = 0.0;
-            if (jc >= 0) {
-                double tot[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    double t = 0.0;
-#pragma unroll
-                    for (int q = 0; q < NW; ++q) t += s_lead[q][c];
-                    tot[c] = t;
-                }
-                const double g1 = cj - tot[0];
-                const double g2 = -tot[1];
-                ccd_apply(g1, g2, a.penalty, a.lambda, &bj, &dj, &st);
-                a.beta[jc] = bj;
-                a.delta[jc] = dj;
-                a.steps[jc] = st;
-                if (a.g12_out) {
-                    a.g12_out[3 * jc] = g1;
-                    a.g12_out[3 * jc + 1] = g2;
-                    a.g12_out[3 * jc + 2] = tot[2];
-                }
-            }
-            s_step = st;
-        }
-        // exclusive scans of A and D up to this thread's first segment
-        double eA[NT], eD[NT], allA[NT], allD[NT];
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            double bA = 0.0, bD = 0.0, sA = 0.0, sD = 0.0;
-#pragma unroll
-            for (int q = 0; q < NW; ++q) {
-                const double xa = s_lead[q][3 + c], xd = s_lead[q][3 + NT + c];
-                if (q < w) {
-                    bA += xa;
-                    bD += xd;
-                }
-                sA += xa;
-                sD += xd;
-            }
-            eA[c] = bA + iA[c] - tA[c];
-            eD[c] = bD + iD[c] - tD[c];
-            allA[c] = sA;
-            allD[c] = sD;
-        }
-        __syncthreads();
-        if (jc >= 0) SW_TRACE(a, b, jc, 7);
-        const double st = s_step;
-        const double f = expm1(st);
+        for (int c = 0; c < NSUM; ++c) t[c] = 0.0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int q = q0 + k;
-            if (q < G) {
-                st_pair(a.ws.sw_bc + (int64_t)q * 8, st, tag);
+            const bool before = q0 + k < b;
 #pragma unroll
-                for (int c = 0; c < NT; ++c) {
-                    const double pre = eA[c] + f * eD[c];
-                    const double out = (FG && c >= 2) ? (allA[c] + f * allD[c]) - pre : pre;
-                    st_pair(a.ws.sw_bc + (int64_t)q * 8 + 1 + c, out, tag);
-                }
-            }
+            for (int c = 0; c < 3; ++c) t[c] += v[k][c];
 #pragma unroll
-            for (int c = 0; c < NT; ++c) {
-                eA[c] += v[k][3 + c];
-                eD[c] += v[k][3 + NT + c];
+            for (int c = 0; c < 2 * NT; ++c) t[3 + c] += before ? v[k][3 + c] : 0.0;
+            if (FG) {
+                // weighted components of A (indices 2, 3) and D (2, 3), all segments
+                t[3 + 2 * NT + 0] += v[k][3 + 2];
+                t[3 + 2 * NT + 1] += v[k][3 + 3];
+                t[3 + 2 * NT + 2] += v[k][3 + NT + 2];
+                t[3 + 2 * NT + 3] += v[k][3 + NT + 3];
             }
+        }
+        const int par = (int)(r & 1u);
+#pragma unroll
+        for (int c = 0; c < NSUM; ++c) {
+            const double x = dpp_wave_sum(t[c]);
+            if (lane == 0) s_sum[par][w][c] = x;
+        }
+        if (__syncthreads_or(bad)) return false;
+#pragma unroll
+        for (int c = 0; c < NSUM; ++c) {
+            double x = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) x += s_sum[par][q][c];
+            out[c] = x;
         }
         return true;
     };
-    // Thread 0 waits for this workgroup's broadcast; all threads get it.
-    auto receive = [&](uint64_t tag) -> bool {
-        if (tid == 0) {
-            u32x4 r[NBC];
-            if (wait_pairs<NBC>(a.ws.sw_bc + b * 8, tag, hdr, r)) {
+    // prefix of this segment (Fine-Gray: plus the suffix starts) for the
+    // coordinate after an update s, from the gathered sums
+    auto prefix_from = [&](const double (&sm)[NSUM], double st, double (&pre)[NT]) {
+        const double f = expm1(st);
 #pragma unroll
-                for (int c = 0; c < NBC; ++c) s_bc[c] = pair_value(r[c]);
-            } else {
-                s_abort = 1;
+        for (int c = 0; c < NT; ++c) pre[c] = sm[3 + c] + f * sm[3 + NT + c];
+        if (FG) {
+#pragma unroll
+            for (int c = 2; c < 4; ++c) {
+                const double tot = sm[3 + 2 * NT + (c - 2)] + f * sm[3 + 2 * NT + 2 + (c - 2)];
+                pre[c] = tot - pre[c];
             }
         }
-        __syncthreads();
-        return !s_abort;
     };
 
     // ---- round 0: aggregates of coordinate jb; rows of jb and jb+1
     scatter(jb, 0);
     if (jb + 1 < je) scatter(jb + 1, 0);
     __syncthreads();
+    double pre[NT];
     {
         double v[NPUB];
 #pragma unroll
@@ -851,20 +786,21 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
                 v[6] += (fl[i] & bj) ? ew : 0.0;
             }
         }
-        publish(v, (ep0 << 1) | 1u);
+        const uint64_t tag = (ep0 << 1) | 1u;
+        publish(v, 0, tag);
+        double sm[NSUM];
+        if (!gather(0, tag, sm)) return;
+        prefix_from(sm, 0.0, pre);
     }
-    if (b == 0 && !leader_round(-1, (ep0 << 1) | 1u)) return;
-    if (!receive((ep0 << 1) | 1u)) return;
+    double st_prev = 0.0;
 
     for (int32_t j = jb; j < je; ++j) {
         const uint64_t r = (uint64_t)(j - jb) + 1;  // exchange round of coordinate j
         const uint64_t tag = ((ep0 + r) << 1) | 1u;
         SW_TRACE(a, b, j, 0);
-        // ---- s_{j-1} and the prefix of coordinate j arrived in round r-1
-        const double st_prev = s_bc[0];
-        double pre[NT];
-#pragma unroll
-        for (int c = 0; c < NT; ++c) pre[c] = s_bc[1 + c];
+        // the coordinate's constants, read before this round is published
+        const double cj = a.c[j];
+        double bj = a.beta[j], dj = a.delta[j];
         uint8_t fl[IPT];
         lds_bytes<IPT>(s_flag + tid * IPT, fl);
         const uint8_t bcur = (uint8_t)(1u << (j % 3));
@@ -972,21 +908,36 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
                 }
             }
         }
-        publish(v, tag);
+        publish(v, r, tag);
         SW_TRACE(a, b, j, 3);
-        if (b == 0) {
-            if (!leader_round(j, tag)) return;
-            SW_TRACE(a, b, j, 4);
+        // ---- rows of column j+2 while the publications arrive
+        if (j + 2 < je) scatter(j + 2, 0);
+        // ---- every segment's publication: the update of j, the prefix of j+1
+        double sm[NSUM];
+        if (!gather(r, tag, sm)) return;
+        SW_TRACE(a, b, j, 4);
+        double st = 0.0;
+        {
+            const double g1 = cj - sm[0];
+            const double g2 = -sm[1];
+            ccd_apply(g1, g2, a.penalty, a.lambda, &bj, &dj, &st);
+            if (b == 0 && tid == 0) {
+                a.beta[j] = bj;
+                a.delta[j] = dj;
+                a.steps[j] = st;
+                if (a.g12_out) {
+                    a.g12_out[3 * j] = g1;
+                    a.g12_out[3 * j + 1] = g2;
+                    a.g12_out[3 * j + 2] = sm[2];
+                }
+            }
         }
-        // ---- rows of column j+2 while the broadcast is on its way (wave 0
-        // stays free to poll)
-        if (j + 2 < je && w > 0) scatter(j + 2, kWave);
-        if (!receive(tag)) return;
+        prefix_from(sm, st, pre);
+        st_prev = st;
         SW_TRACE(a, b, j, 5);
     }
 
     // ---- the last coordinate's update, then eta and e back to memory
-    const double st = s_bc[0];
     {
         uint8_t fl[IPT];
         lds_bytes<IPT>(s_flag + tid * IPT, fl);
@@ -996,12 +947,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
             const int64_t k = base + i;
             if (k < a.n) {
                 double h = s_eta[i * BLOCK + tid];
-                if (st != 0.0 && (fl[i] & blast)) h += st;
+                if (st_prev != 0.0 && (fl[i] & blast)) h += st_prev;
                 a.eta[k] = h;
                 a.e[k] = exp(h);
             }
         }
     }
+    // every workgroup read the epoch before publishing round 0, which
+    // workgroup 0 has gathered
     if (b == 0 && tid == 0)
         st_relaxed_u64(&hdr->epoch, ep0 + (uint64_t)(je - jb) + 1);
 }
@@ -1052,7 +1005,10 @@ int32_t launch_sweep_persistent(const SweepCall &call, const WsView &ws, hipStre
 {
     // segments of 2048 to 8192 positions; LDS holds a segment's flags,
     // column values, patched e and (Fine-Gray) G(y)
-    static const Shape shapes[] = {{256, 8}, {256, 16}, {512, 8}, {512, 16}};
+    static const Shape shapes_valued[] = {{256, 8}, {256, 16}, {512, 8}, {512, 16}};
+    // 0/1 designs: every workgroup reads all G publications per coordinate,
+    // so fewer, larger segments first
+    static const Shape shapes_indicator[] = {{256, 16}, {512, 8}, {256, 8}, {512, 16}};
     int dev = 0;
     SS_HIP_CHECK(hipGetDevice(&dev));
     int cus = 0, coop = 0;
@@ -1060,7 +1016,7 @@ int32_t launch_sweep_persistent(const SweepCall &call, const WsView &ws, hipStre
     SS_HIP_CHECK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     if (!coop) return SS_EUNSUPPORTED;
     const bool vals = call.col.vals != nullptr;
-    for (const Shape &sh : shapes) {
+    for (const Shape &sh : vals ? shapes_valued : shapes_indicator) {
         const int64_t seg = (int64_t)sh.block * sh.ipt;
         const int64_t G = ceil_div(call.n, seg);
         // a few hundred segments at most: the all-to-all exchange reads G
