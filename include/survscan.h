@@ -59,6 +59,11 @@ extern "C" {
 #define SS_PENALTY_L1   1      /* pi = -gamma |beta_j|        (Sec. 2.3)   */
 #define SS_PENALTY_L2   2      /* pi = -beta_j^2 / (2 tau)    (Sec. 2.3)   */
 
+/* accumulation of the FP32-storage path (ss_grad_hess_mixed) */
+#define SS_ACC_F32       0     /* plain FP32 sums                          */
+#define SS_ACC_F32_COMP  1     /* compensated FP32: hi + lo by two-sum     */
+#define SS_ACC_F64       2     /* FP64 sums of the FP32 inputs             */
+
 /* Granularity (in sorted positions) of the per-column chunk index built by
  * ss_prepare; tiles of the fused kernels are whole multiples of it. */
 #define SS_CHUNK 1024
@@ -208,6 +213,37 @@ int32_t ss_exp(int64_t n, const double *eta, double *e, void *stream);
  * order (dst and src must not overlap). */
 int32_t ss_gather(int64_t n, const int32_t *perm, const double *src,
                   double *dst, void *stream);
+
+/* ---------------------------------------------- FP32 storage of e
+ * The paper stores the per-subject quantities in FP64 (Sec. 2.7); these two
+ * calls keep e = exp(X beta) in FP32 instead, to measure what that costs in
+ * accuracy with three ways of accumulating the scans and sums.
+ *
+ * ss_exp_f32: e32_k = (float) exp(eta_k - m) for k < n with m = max_k eta_k
+ * written to *shift (device, one double).  The shift keeps exp inside the
+ * FP32 range (it overflows from about 88); g' and g'' do not depend on it
+ * and sum_k d_k log S0_k moves by m sum_k d_k.  Uses `ws` (a workspace of
+ * ss_workspace_bytes(model, n) bytes for any model) as scratch.
+ *
+ * ss_grad_hess_mixed: out[3] = g', g'', sum_k d_k log S0_k as ss_grad_hess,
+ * from e32 (sorted order, FP32; S0 as e32 gives it, i.e. shifted) with every
+ * prefix sum, transform and reduction carried out in the precision `acc`
+ * selects (SS_ACC_*).  Other arguments as for ss_grad_hess; e32 needs no
+ * particular alignment.  A reduce-then-scan in a fixed order (per-tile
+ * aggregates, one scan, the tile pass, the final sum): results are
+ * deterministic.  Errors: SS_EINVAL for a bad argument or an unknown `acc`,
+ * SS_EWORKSPACE as ss_grad_hess. */
+int32_t ss_exp_f32(int64_t n, const double *eta, float *e32, double *shift,
+                   void *ws, size_t ws_bytes, void *stream);
+int32_t ss_grad_hess_mixed(int32_t model, int32_t acc, int64_t n, int64_t p,
+                           int64_t j, const float *e32, const uint8_t *d8,
+                           const int32_t *d32, const double *w_comp,
+                           const double *g_end, const int64_t *col_ptr,
+                           const int32_t *rows_sorted,
+                           const double *vals_sorted,
+                           const int32_t *chunk_ptr, const double *c,
+                           double *out, void *ws, size_t ws_bytes,
+                           void *stream);
 
 #ifdef __cplusplus
 }

@@ -298,4 +298,34 @@ int32_t ss_gather(int64_t n, const int32_t *perm, const double *src, double *dst
     return launch_gather(n, perm, src, dst, (hipStream_t)stream);
 }
 
+int32_t ss_exp_f32(int64_t n, const double *eta, float *e32, double *shift, void *ws,
+                   size_t ws_bytes, void *stream)
+{
+    if (n < 1 || n > INT32_MAX || !eta || !e32 || !shift) return SS_EINVAL;
+    WsView v;
+    if (!fused_ws_view(ws, ws_bytes, n, &v)) return SS_EWORKSPACE;
+    return launch_exp_f32(n, eta, e32, shift, v, (hipStream_t)stream);
+}
+
+int32_t ss_grad_hess_mixed(int32_t model, int32_t acc, int64_t n, int64_t p, int64_t j,
+                           const float *e32, const uint8_t *d8, const int32_t *d32,
+                           const double *w_comp, const double *g_end,
+                           const int64_t *col_ptr, const int32_t *rows_sorted,
+                           const double *vals_sorted, const int32_t *chunk_ptr,
+                           const double *c, double *out, void *ws, size_t ws_bytes,
+                           void *stream)
+{
+    if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
+    if (acc != SS_ACC_F32 && acc != SS_ACC_F32_COMP && acc != SS_ACC_F64) return SS_EINVAL;
+    if (bad_size(n, p) || j < 0 || j >= p) return SS_EINVAL;
+    if (!e32 || !d8 || !d32) return SS_EINVAL;
+    if (model == SS_FINE_GRAY && (!w_comp || !g_end)) return SS_EINVAL;
+    if (!col_ptr || !rows_sorted || !chunk_ptr || !c || !out) return SS_EINVAL;
+    WsView v;
+    if (!fused_ws_view(ws, ws_bytes, n, &v)) return SS_EWORKSPACE;
+    return launch_mixed(acc, model, n, p, (int32_t)j, e32, d8, d32, w_comp, g_end,
+                        column(col_ptr, rows_sorted, vals_sorted, chunk_ptr, n), c, out, v,
+                        (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -220,6 +220,12 @@ int32_t launch_apply(int64_t n, int32_t j, const double *step, double *eta,
 int32_t launch_ccd_scalar(int32_t penalty, double lambda, int32_t j,
                           const double *g12, double *beta, double *delta,
                           double *step, hipStream_t stream);
+int32_t launch_mixed(int32_t acc, int32_t model, int64_t n, int64_t p, int32_t j,
+                     const float *e32, const uint8_t *d8, const int32_t *d32,
+                     const double *w_comp, const double *g_end, const Column &col,
+                     const double *c, double *out, const WsView &ws, hipStream_t s);
+int32_t launch_exp_f32(int64_t n, const double *eta, float *e32, double *shift,
+                       const WsView &ws, hipStream_t s);
 int32_t launch_exp(int64_t n, const double *eta, double *e,
                    hipStream_t stream);
 int32_t launch_gather(int64_t n, const int32_t *perm, const double *src,

@@ -28,6 +28,10 @@ CHUNK = 1024
 
 MODELS = {"cox": COX, "fg": FINE_GRAY, "fine_gray": FINE_GRAY}
 PENALTIES = {"none": PENALTY_NONE, "l1": PENALTY_L1, "l2": PENALTY_L2}
+ACC_F32 = 0
+ACC_F32_COMP = 1
+ACC_F64 = 2
+ACCUMULATIONS = {"f32": ACC_F32, "f32c": ACC_F32_COMP, "f64": ACC_F64}
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -56,6 +60,9 @@ SIGNATURES = {
                             _sz, _vp]),
     "ss_exp": (_i32, [_i64, _vp, _vp, _vp]),
     "ss_gather": (_i32, [_i64, _vp, _vp, _vp, _vp]),
+    "ss_exp_f32": (_i32, [_i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ss_grad_hess_mixed": (_i32, [_i32, _i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp,
+                                  _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
 }
 
 
@@ -192,6 +199,27 @@ class Problem:
                                  _p(self.vals_sorted), _p(self.chunk_ptr), _p(self.c),
                                  _p(out), self.ws.ptr, self.ws.nbytes, _stream(self.device))
         check(rc, "ss_grad_hess")
+        return out
+
+    def make_e32(self):
+        """FP32 copy of e, shifted: (e32 = exp(eta - m) as float, m) as device tensors."""
+        e32 = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        shift = torch.empty(1, dtype=torch.float64, device=self.device)
+        check(load().ss_exp_f32(self.n, _p(self.eta), _p(e32), _p(shift), self.ws.ptr,
+                                self.ws.nbytes, _stream(self.device)), "ss_exp_f32")
+        return e32, shift
+
+    def grad_hess_mixed(self, j, e32, acc, out=None):
+        """(g', g'', sum d log S0 of the shifted e) of coordinate j from FP32 e,
+        accumulated as `acc` ("f32", "f32c" or "f64")."""
+        out = torch.empty(3, dtype=torch.float64, device=self.device) if out is None else out
+        rc = load().ss_grad_hess_mixed(self.model, ACCUMULATIONS[acc], self.n, self.p, int(j),
+                                       _p(e32), _p(self.d8), _p(self.d32), _p(self.w_comp),
+                                       _p(self.g_end), _p(self.col_ptr), _p(self.rows_sorted),
+                                       _p(self.vals_sorted), _p(self.chunk_ptr), _p(self.c),
+                                       _p(out), self.ws.ptr, self.ws.nbytes,
+                                       _stream(self.device))
+        check(rc, "ss_grad_hess_mixed")
         return out
 
     def loglik(self, beta=None, out=None):
