@@ -302,3 +302,57 @@ def test_prep_order_runs_and_counts():
     ys = y[o]
     np.testing.assert_array_equal(prep.run_end(ys), [2, 2, 2, 3, 5, 5])
     np.testing.assert_array_equal(prep.d_end(ys, s[o]), [0, 0, 2, 1, 0, 1])
+
+
+# ---------------------------------------------------------------- full gradient in eta
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+@pytest.mark.parametrize("seed,n,ties", [(21, 1, 0), (22, 9, 0), (23, 120, 15), (24, 400, 0)])
+def test_eta_gradient_complex_step(model, seed, n, ties):
+    """dl/deta_m from the chain-rule definition equals the complex-step
+    derivative Im l(eta + i h e_m) / h of the likelihood itself (h = 1e-30),
+    for every m (ties included)."""
+    y, s, eta, _ = _rand_problem(seed, n, model, ties=ties)
+    from oracle import adjoint
+    g = adjoint.eta_gradient_brute(model, y, s, eta)
+    h = 1e-30
+    for m in range(n):
+        etac = eta.astype(np.complex128)
+        etac[m] += 1j * h
+        cs = np.imag(risk.loglik(model, y, s, etac)) / h
+        assert cs == pytest.approx(g[m], rel=1e-12, abs=1e-13)
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+@pytest.mark.parametrize("seed,n,ties", [(25, 1, 0), (26, 2, 0), (27, 300, 0), (28, 900, 40),
+                                          (29, 2000, 300)])
+def test_eta_gradient_scan_matches_brute(model, seed, n, ties):
+    """The O(N) prefix/suffix form equals the O(N^2) definition; its inner
+    product with a column is the coordinate gradient g' (the directional
+    derivative of l along x_j); it sums to zero (l(eta + c) = l(eta))."""
+    from oracle import adjoint
+    y, s, eta, x = _rand_problem(seed, n, model, ties=ties)
+    gb = adjoint.eta_gradient_brute(model, y, s, eta)
+    gs = adjoint.eta_gradient_scan(model, y, s, eta)
+    scale = np.sum(np.abs(gb)) + 1.0
+    assert np.max(np.abs(gs - gb)) <= 1e-12 * scale
+    r = risk.brute(model, y, s, eta, x)
+    assert float(np.dot(x, gs)) == pytest.approx(r["g1"], rel=1e-11, abs=1e-11 * scale)
+    assert abs(float(np.sum(gs))) <= 1e-11 * scale
+    assert adjoint.loglik_eta(model, y, s, eta) == pytest.approx(
+        risk.loglik(model, y, s, eta), rel=1e-12, abs=1e-12)
+
+
+def test_eta_gradient_hand_example():
+    """Three subjects, times 3 > 2 > 1, all events, e = (1, 2, 4): the risk
+    sets at the event times 3, 2, 1 have S0 = 1, 3, 7, and a subject's
+    derivative is 1 - e_m times the sum of 1/S0 over the events whose risk
+    set holds it (event times at or below its own time): subject at t=3:
+    1 - 1 (1/1 + 1/3 + 1/7); t=2: 1 - 2 (1/3 + 1/7); t=1: 1 - 4 (1/7)."""
+    from oracle import adjoint
+    y = np.array([3.0, 2.0, 1.0])
+    s = np.array([1, 1, 1])
+    eta = np.log([1.0, 2.0, 4.0])
+    want = np.array([1 - (1 + 1 / 3 + 1 / 7), 1 - 2 * (1 / 3 + 1 / 7), 1 - 4 / 7])
+    np.testing.assert_allclose(adjoint.eta_gradient_brute("cox", y, s, eta), want, rtol=1e-14)
+    np.testing.assert_allclose(adjoint.eta_gradient_scan("cox", y, s, eta), want, rtol=1e-14)
