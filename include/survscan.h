@@ -245,6 +245,42 @@ int32_t ss_grad_hess_mixed(int32_t model, int32_t acc, int64_t n, int64_t p,
                            double *out, void *ws, size_t ws_bytes,
                            void *stream);
 
+/* ss_eta_gradient: the gradient of the log (pseudo-)likelihood with respect
+ * to the linear predictor, for every subject at once -- the vector
+ * delta - P delta of Sec. 2.9 (Cox, Sec. 2.1 eq. for l(beta)) and its
+ * Fine-Gray analogue (Sec. 2.2, IPCW weights), whose product with X' is the
+ * full gradient in beta a proximal-gradient method needs.  O(N) by prefix
+ * and suffix sums in decreasing-time order, the Sec. 2.7 form that Sec. 2.9
+ * points to, with Breslow ties:
+ *
+ *   dl/deta_m = delta_m - e_m * ( sum over run ends k at or after m of
+ *               d_k / S0_k  [+ w_comp_m * sum over run ends k before m of
+ *               d_k G(Y_k) / S0_k, Fine-Gray] )
+ *
+ * and *loglik = sum_m delta_m eta_m - sum_k d_k log S0_k (the value whose
+ * gradient this is).  delta_m = 1 for an event of interest (Cox: status
+ * != 0; Fine-Gray: status == 1).
+ *
+ * Arguments (device memory): perm, d8, d32, w_comp, g_end as ss_prepare
+ * wrote them; status[n] int8 in ORIGINAL subject order (as given to
+ * ss_prepare); eta[n] and e[n] = exp(eta) in SORTED order (as ss_gather /
+ * ss_exp produce them; e is not recomputed from eta, so the pair must agree);
+ * grad[n] is written in ORIGINAL subject order; *loglik one double.  The
+ * workspace (any 256-byte-aligned device buffer of
+ * ss_eta_gradient_workspace_bytes(n) bytes, caller-owned, no
+ * initialisation) holds five N-vectors of partial results and the scan
+ * carries; it is distinct from the ss_grad_hess workspace.  All sums are
+ * taken in a fixed order: results are deterministic.  Errors: SS_EINVAL
+ * for an unknown-size or null argument, SS_EUNSUPPORTED for an unknown
+ * model, SS_EWORKSPACE for a short or misaligned workspace. */
+size_t ss_eta_gradient_workspace_bytes(int64_t n);
+int32_t ss_eta_gradient(int32_t model, int64_t n, const int32_t *perm,
+                        const int8_t *status, const double *eta,
+                        const double *e, const uint8_t *d8,
+                        const int32_t *d32, const double *w_comp,
+                        const double *g_end, double *grad, double *loglik,
+                        void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -695,4 +695,18 @@ int32_t run_prepare(int32_t model, int64_t n, int64_t p, int64_t nnz, const doub
     return err ? SS_EINVAL : SS_OK;
 }
 
+int32_t scan_add_f64(const double *in, double *out, int64_t m, bool rev, bool excl,
+                     void *sums, hipStream_t s)
+{
+    uint64_t *w = reinterpret_cast<uint64_t *>(sums);
+    if (rev) {
+        return excl ? device_scan<double, OpAdd<double>, true, true>(in, out, m, w, s)
+                    : device_scan<double, OpAdd<double>, true, false>(in, out, m, w, s);
+    }
+    return excl ? device_scan<double, OpAdd<double>, false, true>(in, out, m, w, s)
+                : device_scan<double, OpAdd<double>, false, false>(in, out, m, w, s);
+}
+
+size_t scan_sums_bytes(int64_t m) { return 8 * (size_t)ceil_div(m, ST); }
+
 }  // namespace ss

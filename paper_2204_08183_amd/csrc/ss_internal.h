@@ -220,6 +220,16 @@ int32_t launch_apply(int64_t n, int32_t j, const double *step, double *eta,
 int32_t launch_ccd_scalar(int32_t penalty, double lambda, int32_t j,
                           const double *g12, double *beta, double *delta,
                           double *step, hipStream_t stream);
+// Deterministic FP64 add-scan of in[0..m) into out (may alias): forward or
+// reverse (suffix), inclusive or exclusive; `sums` holds scan_sums_bytes(m).
+int32_t scan_add_f64(const double *in, double *out, int64_t m, bool rev, bool excl,
+                     void *sums, hipStream_t s);
+size_t scan_sums_bytes(int64_t m);
+size_t adjoint_ws_bytes(int64_t n);
+int32_t launch_eta_gradient(int32_t model, int64_t n, const int32_t *perm, const int8_t *status,
+                            const double *eta, const double *e, const uint8_t *d8,
+                            const int32_t *d32, const double *w_comp, const double *g_end,
+                            double *grad, double *loglik, void *ws, hipStream_t s);
 int32_t launch_mixed(int32_t acc, int32_t model, int64_t n, int64_t p, int32_t j,
                      const float *e32, const uint8_t *d8, const int32_t *d32,
                      const double *w_comp, const double *g_end, const Column &col,

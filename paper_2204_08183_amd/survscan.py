@@ -63,6 +63,9 @@ SIGNATURES = {
     "ss_exp_f32": (_i32, [_i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_grad_hess_mixed": (_i32, [_i32, _i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp,
                                   _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ss_eta_gradient_workspace_bytes": (_sz, [_i64]),
+    "ss_eta_gradient": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                               _vp, _sz, _vp]),
 }
 
 
@@ -141,6 +144,7 @@ class Problem:
         self.vals_in = None if vals is None else \
             torch.as_tensor(vals, dtype=torch.float64).to(dev).contiguous()
         self.col_ptr = col_ptr
+        self.status = status
         self.perm = torch.empty(n, dtype=torch.int32, device=dev)
         self.inv_perm = torch.empty(n, dtype=torch.int32, device=dev)
         self.d8 = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -222,6 +226,23 @@ class Problem:
         check(rc, "ss_grad_hess_mixed")
         return out
 
+    def eta_gradient(self, grad=None, loglik=None):
+        """dl/deta for every subject (original order) and l at the current
+        eta, as device tensors (grad [n], loglik [1])."""
+        lib = load()
+        if getattr(self, "adj_ws", None) is None:
+            self.adj_ws = Workspace(lib.ss_eta_gradient_workspace_bytes(self.n), self.device)
+        grad = torch.empty(self.n, dtype=torch.float64, device=self.device) \
+            if grad is None else grad
+        loglik = torch.empty(1, dtype=torch.float64, device=self.device) \
+            if loglik is None else loglik
+        rc = lib.ss_eta_gradient(self.model, self.n, _p(self.perm), _p(self.status),
+                                 _p(self.eta), _p(self.e), _p(self.d8), _p(self.d32),
+                                 _p(self.w_comp), _p(self.g_end), _p(grad), _p(loglik),
+                                 self.adj_ws.ptr, self.adj_ws.nbytes, _stream(self.device))
+        check(rc, "ss_eta_gradient")
+        return grad, loglik
+
     def loglik(self, beta=None, out=None):
         beta = self.beta if beta is None else \
             torch.as_tensor(beta, dtype=torch.float64).to(self.device).contiguous()
@@ -258,3 +279,27 @@ class Problem:
         check(load().ss_workspace_error(self.ws.ptr, ctypes.byref(flag),
                                         _stream(self.device)), "ss_workspace_error")
         return int(flag.value)
+
+
+class LogLikEta(torch.autograd.Function):
+    """l(eta) of a prepared problem as a differentiable function of the
+    per-subject linear predictor (original order, float64 on the problem's
+    device).  The forward pass computes l and dl/deta in one call of
+    ss_eta_gradient; the backward pass scales the stored gradient."""
+
+    @staticmethod
+    def forward(ctx, eta, prob):
+        prob.set_eta(eta.detach())
+        grad, loglik = prob.eta_gradient()
+        ctx.save_for_backward(grad)
+        return loglik[0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return g * grad, None
+
+
+def loglik_eta(prob, eta):
+    """l(eta) with autograd support; see LogLikEta."""
+    return LogLikEta.apply(eta, prob)

@@ -1,0 +1,145 @@
+"""GPU: the full gradient in eta (ss_eta_gradient) against the oracle.
+
+Checks, element by element on the same seeded inputs:
+  * dl/deta against oracle.adjoint.eta_gradient_scan (itself pinned to the
+    chain-rule definition and to complex steps on the CPU), each element
+    within 1e-10 of its condition scale delta_m + e_m * (inner sum);
+  * l against oracle.adjoint.loglik_eta, within 1e-10 of
+    sum |delta eta| + sum d |log S0|;
+  * x_j' (dl/deta) = g' of coordinate j from ss_grad_hess (both GPU paths,
+    property that holds at any size) -- the link the proximal-gradient step
+    of Sec. 2.9 relies on;
+  * the autograd wrapper: backward equals the gradient, and torch's
+    finite-difference gradcheck passes on a small case.
+Edge cases: one subject, all censored (gradient zero, l = 0), all events,
+heavy ties, a ragged size across many scan tiles, the N = 1e6 sweep design.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as oadj, prep as oprep, scan as oscan
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2204_08183_amd import survscan as ss  # noqa: E402
+
+from test_gpu_parity import make_case, gpu_problem, xcol  # noqa: E402
+
+DEV = "cuda:0"
+TOL = 1e-10
+
+
+def check_gradient(model, c, prob=None):
+    prob = prob or gpu_problem(model, c)
+    grad, ll = prob.eta_gradient()
+    got = grad.cpu().numpy()
+    want = oadj.eta_gradient_scan(model, c["y"], c["status"], c["eta"])
+    ev = oprep.event_indicator(model, c["status"]).astype(np.float64)
+    scale = ev + np.abs(ev - want)            # delta_m + e_m * inner_m
+    err = np.abs(got - want) / np.maximum(scale, 1e-300)
+    assert float(err.max(initial=0.0)) <= TOL, (model, c["n"], float(err.max()),
+                                                int(err.argmax()))
+    want_l = oadj.loglik_eta(model, c["y"], c["status"], c["eta"])
+    l_scale = float(np.sum(np.abs(c["eta"] * ev))) + abs(want_l) + 1.0
+    assert abs(float(ll.cpu()[0]) - want_l) <= TOL * l_scale, (float(ll.cpu()[0]), want_l)
+    return prob, got
+
+
+CASES = [("cox", 1000, 3, 0, 0, False), ("cox", 50001, 4, 1, 40, False),
+         ("cox", 20000, 3, 2, 0, True), ("fg", 1000, 3, 3, 0, False),
+         ("fg", 50001, 4, 4, 40, False), ("fg", 20000, 3, 5, 0, True)]
+
+
+@pytest.mark.parametrize("model,n,p,seed,ties,valued", CASES)
+def test_eta_gradient_matches_oracle(model, n, p, seed, ties, valued):
+    c = make_case(model, n, p, seed, ties, 0.1, valued)
+    prob, got = check_gradient(model, c)
+    # x_j' grad = g' (GPU fused coordinate kernel) for every column
+    for j in range(p):
+        x = xcol(c, j)
+        g1 = float(prob.grad_hess(j).cpu()[0])
+        scale = float(np.sum(np.abs(x) * (np.abs(got) + 1.0)))
+        assert abs(float(x @ got) - g1) <= TOL * scale, (model, j, float(x @ got), g1)
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+def test_eta_gradient_edges(model):
+    # one subject
+    c = make_case(model, 1, 1, 6, 0, 1.0, False)
+    check_gradient(model, c)
+    # everything censored: no events, gradient zero, l = 0
+    c = make_case(model, 3000, 2, 7, 0, 0.2, False, status="censored")
+    prob, got = check_gradient(model, c)
+    assert np.all(got == 0.0)
+    assert float(prob.eta_gradient()[1].cpu()[0]) == 0.0
+    # every subject an event of interest
+    c = make_case(model, 3000, 2, 8, 5, 0.2, False, status="events")
+    check_gradient(model, c)
+    # one tie run holding every subject
+    c = make_case(model, 2049, 2, 9, 0, 0.2, False)
+    c["y"] = np.full(c["n"], 1.5)
+    check_gradient(model, c)
+    # ragged size across many scan tiles, large eta offset
+    c = make_case(model, 262145, 2, 10, 0, 0.05, False, eta_shift=30.0)
+    check_gradient(model, c)
+
+
+def test_eta_gradient_sweep_design():
+    """The N = 1e6, P = 1000 design of the l1 CCD sweep (one column set per
+    model), at the eta a partial sweep leaves."""
+    import gen
+    for model in ("cox", "fg"):
+        d = gen.cox_data(0, 1_000_000, 50, 0.05) if model == "cox" else \
+            gen.fg_data(0, 1_000_000, 50, 0.05)
+        rng = np.random.default_rng(12)
+        c = {"y": d["y"], "status": d["status"], "col_ptr": d["col_ptr"], "rows": d["rows"],
+             "vals": None, "eta": rng.normal(0.0, 0.5, d["n"]), "n": d["n"], "p": d["p"]}
+        prob, got = check_gradient(model, c)
+        pr = oscan.Prepared(model, c["y"], c["status"])
+        for j in (0, 17, 49):
+            x = xcol(c, j)
+            want = pr.coordinate(c["eta"], x)
+            assert abs(float(x @ got) - want["g1"]) <= TOL * want["scale_g1"] * 10
+
+
+def test_eta_gradient_rejects_bad_arguments():
+    c = make_case("cox", 1000, 1, 11, 0, 0.2, False)
+    prob = gpu_problem("cox", c)
+    lib = ss.load()
+    grad = torch.empty(prob.n, dtype=torch.float64, device=DEV)
+    ll = torch.empty(1, dtype=torch.float64, device=DEV)
+    ws = ss.Workspace(lib.ss_eta_gradient_workspace_bytes(prob.n), DEV)
+    args = [prob.perm.data_ptr(), prob.status.data_ptr(), prob.eta.data_ptr(),
+            prob.e.data_ptr(), prob.d8.data_ptr(), prob.d32.data_ptr(), None, None,
+            grad.data_ptr(), ll.data_ptr()]
+    assert lib.ss_eta_gradient(7, prob.n, *args, ws.ptr, ws.nbytes, None) == ss.SS_EUNSUPPORTED
+    assert lib.ss_eta_gradient(ss.COX, 0, *args, ws.ptr, ws.nbytes, None) == ss.SS_EINVAL
+    assert lib.ss_eta_gradient(ss.COX, prob.n, *args, ws.ptr, ws.nbytes - 8,
+                               None) == ss.SS_EWORKSPACE
+    # Fine-Gray needs the IPCW arrays
+    assert lib.ss_eta_gradient(ss.FINE_GRAY, prob.n, *args, ws.ptr, ws.nbytes,
+                               None) == ss.SS_EINVAL
+    assert lib.ss_eta_gradient_workspace_bytes(0) == 0
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+def test_loglik_eta_autograd(model):
+    c = make_case(model, 5000, 1, 13, 10, 0.2, False)
+    prob = gpu_problem(model, c)
+    eta = torch.tensor(c["eta"], dtype=torch.float64, device=DEV, requires_grad=True)
+    l = ss.loglik_eta(prob, eta)
+    (2.5 * l).backward()
+    want = oadj.eta_gradient_scan(model, c["y"], c["status"], c["eta"])
+    got = eta.grad.cpu().numpy()
+    ev = oprep.event_indicator(model, c["status"]).astype(np.float64)
+    assert np.max(np.abs(got - 2.5 * want) / (2.5 * (ev + np.abs(ev - want)))) <= TOL
+    # finite differences through the GPU forward pass (small case)
+    c = make_case(model, 60, 1, 14, 3, 0.2, False)
+    small = gpu_problem(model, c)
+    eta = torch.tensor(c["eta"], dtype=torch.float64, device=DEV, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda t: ss.loglik_eta(small, t), (eta,), eps=1e-6,
+                                    atol=1e-7, rtol=1e-6)
