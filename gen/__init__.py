@@ -4,5 +4,5 @@ likelihood, no weights): it only draws covariates, coefficients and times.
 """
 from .survival import (  # noqa: F401
     indicator_design, cox_data, fg_data, uniform_tuple_data, force_ties,
-    dense_column, linear_predictor, csc_from_dense,
+    dense_column, linear_predictor, csc_from_dense, cv_folds,
 )

@@ -169,3 +169,18 @@ def force_ties(y, levels):
     y = np.asarray(y, dtype=np.float64)
     q = np.quantile(y, np.linspace(0, 1, levels + 1)[1:-1]) if levels > 1 else []
     return np.searchsorted(np.asarray(q), y).astype(np.float64) + 1.0
+
+
+def cv_folds(seed, n, k=10, repeats=10):
+    """Training masks of k-fold cross-validation repeated `repeats` times
+    (Sec. 2.8; 10 folds x 10 repetitions in Sec. 3.3).  Repetition t draws a
+    random partition of the subjects into k folds of sizes differing by at
+    most one; replicate t*k + f trains on every subject outside fold f.
+    Returns uint8 [repeats*k, n], 1 = training subject."""
+    rng = np.random.default_rng(seed)
+    masks = np.ones((repeats * k, n), dtype=np.uint8)
+    for t in range(repeats):
+        fold = rng.permutation(n) % k
+        for f in range(k):
+            masks[t * k + f, fold == f] = 0
+    return masks

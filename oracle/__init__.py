@@ -24,6 +24,10 @@ arXiv 2204.08183) and shares no code with the HIP library:
                  fg_g, fg_h), in plain C with compensated sums.
 * ``ccd``     -- the one-dimensional penalised Newton step with trust region
                  and the l1 directional-derivative rule (Secs. 2.3-2.4).
+* ``adjoint`` -- the gradient of the log-likelihood in the linear predictor
+                 for every subject (Sec. 2.9), brute force and O(N) scan form.
+* ``cv``      -- cross-validation replicates (Sec. 2.8): CCD on a training
+                 subset, the predictive log-likelihood of the held-out one.
 
 Every function computes in IEEE double precision unless stated otherwise.
 """

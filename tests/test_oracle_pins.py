@@ -356,3 +356,88 @@ def test_eta_gradient_hand_example():
     want = np.array([1 - (1 + 1 / 3 + 1 / 7), 1 - 2 * (1 / 3 + 1 / 7), 1 - 4 / 7])
     np.testing.assert_allclose(adjoint.eta_gradient_brute("cox", y, s, eta), want, rtol=1e-14)
     np.testing.assert_allclose(adjoint.eta_gradient_scan("cox", y, s, eta), want, rtol=1e-14)
+
+
+# ---------------------------------------------------------------- cross-validation
+
+def _cv_problem(model, seed, n, p):
+    d = gen.cox_data(seed, n, p, 0.2) if model == "cox" else gen.fg_data(seed, n, p, 0.2)
+    return d
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+def test_cv_fit_equals_fit_on_smaller_data_set(model):
+    """A replicate's fit is CCD on the training subjects as a data set of
+    their own: built independently here from the dense design restricted to
+    the training rows, it gives the same beta bit for bit."""
+    from oracle import cv
+    d = _cv_problem(model, 3, 300, 6)
+    train = gen.cv_folds(5, d["n"], 5, 1)[2]
+    beta, delta, eta_all, hist = cv.fit_replicate(model, d["y"], d["status"], d["col_ptr"],
+                                                  d["rows"], None, train, ccd.PENALTY_L1, 1.0, 2)
+    X = np.stack([gen.dense_column(d["n"], d["col_ptr"], d["rows"], None, j)
+                  for j in range(d["p"])], axis=1)
+    tr = train == 1
+    cp, rr, vv = gen.csc_from_dense(X[tr])
+    b2, d2, eta2, _ = cv.ccd_sweeps(model, d["y"][tr], d["status"][tr], cp, rr, None,
+                                    np.zeros(int(tr.sum())), ccd.PENALTY_L1, 1.0, 2)
+    assert np.array_equal(beta, b2) and np.array_equal(delta, d2)
+    np.testing.assert_allclose(eta_all, X @ beta, rtol=1e-13, atol=1e-13)
+    assert np.any(beta != 0.0)
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+def test_cv_fit_ignores_heldout_subjects(model):
+    """Changing the times, statuses and covariates of held-out subjects
+    leaves the training fit unchanged (a risk set or KM estimate over all
+    subjects would not)."""
+    from oracle import cv
+    d = _cv_problem(model, 4, 250, 5)
+    train = gen.cv_folds(6, d["n"], 4, 1)[1]
+    ho = np.nonzero(train == 0)[0]
+    fit = cv.fit_replicate(model, d["y"], d["status"], d["col_ptr"], d["rows"], None, train,
+                           ccd.PENALTY_NONE, 0.0, 1)
+    y2 = d["y"].copy()
+    s2 = d["status"].copy()
+    rng = np.random.default_rng(0)
+    y2[ho] = rng.exponential(1.0, ho.size)
+    s2[ho] = 2 if model == "fg" else 0
+    rows = np.asarray(d["rows"])
+    keep = np.isin(rows, ho, invert=True)      # drop the held-out non-zeros
+    cp = np.concatenate(([0], np.cumsum([int(keep[d["col_ptr"][j]:d["col_ptr"][j + 1]].sum())
+                                         for j in range(d["p"])])))
+    fit2 = cv.fit_replicate(model, y2, s2, cp, rows[keep], None, train, ccd.PENALTY_NONE,
+                            0.0, 1)
+    assert np.array_equal(fit[0], fit2[0])
+    # the full-data fit differs (the held-out subjects matter there)
+    full = cv.fit_replicate(model, d["y"], d["status"], d["col_ptr"], d["rows"], None,
+                            np.ones(d["n"], np.uint8), ccd.PENALTY_NONE, 0.0, 1)
+    assert not np.array_equal(fit[0], full[0])
+
+
+def test_cv_heldout_loglik_hand_example():
+    """Held-out subjects at times 3 > 2 > 1, all events, e = (1, 2, 4):
+    the held-out risk sets give S0 = 1, 3, 7, so the predictive
+    log-likelihood is (0 + log 2 + log 4) - (log 1 + log 3 + log 7).
+    Training subjects interleaved with them (any time, status, eta) do not
+    enter; the training likelihood is the same form on the training set."""
+    from oracle import cv
+    y = np.array([3.0, 2.5, 2.0, 1.5, 1.0, 0.5])
+    s = np.array([1, 1, 1, 0, 1, 1])
+    eta = np.log([1.0, 5.0, 2.0, 7.0, 4.0, 3.0])
+    train = np.array([0, 1, 0, 1, 0, 1], np.uint8)
+    want = math.log(2) + math.log(4) - (math.log(1) + math.log(3) + math.log(7))
+    assert cv.heldout_loglik("cox", y, s, eta, train) == pytest.approx(want, rel=1e-14)
+    # training set: times 2.5 (event, e 5), 1.5 (censored, e 7), 0.5 (event, e 3)
+    want_tr = math.log(5) + math.log(3) - (math.log(5) + math.log(15))
+    assert cv.training_loglik("cox", y, s, eta, train) == pytest.approx(want_tr, rel=1e-14)
+
+
+def test_cv_folds_partition():
+    m = gen.cv_folds(1, 1003, 10, 3)
+    assert m.shape == (30, 1003)
+    for t in range(3):
+        held = 1 - m[t * 10:(t + 1) * 10].astype(int)
+        assert np.all(held.sum(axis=0) == 1)            # held out exactly once
+        sizes = held.sum(axis=1)
+        assert sizes.max() - sizes.min() <= 1
