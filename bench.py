@@ -13,7 +13,11 @@ One JSON line is printed.  Besides the throughput it carries
   roofline      the fused Cox kernel at N = 2^27 (its HBM-bound size), timed
                 with HIP events on its own stream;
   cpu_baseline  the FP64 oracle (serial C scan) on a bounded sample;
-  context       our fused kernel at N = 1e5 next to the paper's GV100 time.
+  context       our fused kernel at N = 1e5 next to the paper's GV100 time;
+  cv            10-fold x 10-repetition cross-validation (100 replicates) at
+                N = 1e5, P = 1000: one l1 sweep of every replicate in one
+                launch, next to one replicate-sized problem swept alone
+                (times 100: the replicates one after another).
 """
 import argparse
 import hashlib
@@ -47,6 +51,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-context", action="store_true")
+    ap.add_argument("--no-cv", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -139,6 +144,34 @@ def context(torch, ss, gen):
     return {"fused_us_n1e5_ours_back_to_back": round(us, 2),
             "fused_us_n1e5_paper_gv100": 5.2,
             "note": "paper Table 1, steps (2)-(4) fused, N=1e5, Uniform(1,2); other GPU"}
+
+
+def cross_validation(torch, ss, gen):
+    """Sec. 3.3 design at its smallest size: 10 x 10 cross-validation of the
+    l1 Cox model (gamma = sqrt 2) at N = 1e5, P = 1000; one sweep of all 100
+    replicates in one launch, and one replicate-sized problem (N = 9e4, the
+    training set of a 10-fold replicate) swept alone."""
+    n, p, reps = 100_000, 1000, 100
+    gamma = math.sqrt(2.0)
+    d = gen.cox_data(0, n, p, 0.05)
+    train = gen.cv_folds(0, n, 10, 10)
+    prob = ss.Problem("cox", d["y"], d["status"], d["col_ptr"], d["rows"], None, "cuda:0")
+    cvp = ss.CrossValidation(prob, train)
+    cvp.sweep("l1", gamma)
+    torch.cuda.synchronize()
+    us_cv = event_time_us(torch, lambda: cvp.sweep("l1", gamma), 5)
+    one = gen.cox_data(1, 90_000, p, 0.05)
+    p1 = ss.Problem("cox", one["y"], one["status"], one["col_ptr"], one["rows"], None,
+                    "cuda:0")
+    p1.sweep("l1", gamma)
+    torch.cuda.synchronize()
+    us_one = event_time_us(torch, lambda: p1.sweep("l1", gamma), 5)
+    return {"workload": "10-fold x 10 cross-validation, l1 Cox, N=1e5, P=1000, 0.05 density",
+            "replicates": reps, "sweep_ms_all_replicates": round(us_cv / 1e3, 3),
+            "replicate_coords_per_s": round(reps * p / (us_cv * 1e-6), 1),
+            "one_replicate_sweep_ms": round(us_one / 1e3, 3),
+            "one_at_a_time_ms_100_replicates": round(100 * us_one / 1e3, 2),
+            "speedup_vs_one_at_a_time": round(100 * us_one / us_cv, 2)}
 
 
 def cpu_baseline(gen, cox, fg, coords):
@@ -271,6 +304,9 @@ def main():
         line["roofline"] = roofline(torch, ss, gen, args.roof_n, args.roof_reps)
     if not args.no_context:
         line["context"] = context(torch, ss, gen)
+    if not args.no_cv:
+        log("cross-validation: 100 replicates, N=1e5, P=1000")
+        line["cv"] = cross_validation(torch, ss, gen)
     if not args.no_cpu:
         log("cpu baseline (oracle) on %d coordinates per model" % args.cpu_coords)
         line["cpu_baseline"] = cpu_baseline(gen, cox, fg, args.cpu_coords)

@@ -281,6 +281,76 @@ int32_t ss_eta_gradient(int32_t model, int64_t n, const int32_t *perm,
                         const double *g_end, double *grad, double *loglik,
                         void *ws, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Cross-validation replicates in one launch (Sec. 2.8; the single larger
+ * kernel for many k-fold repetitions proposed in the paper's concluding
+ * discussion).  R replicates share the prepared problem (order, tie runs,
+ * design) and each is CCD on its own training subjects: held-out subjects
+ * carry e = 0 and drop out of every risk set, event counts and c_j count
+ * training events only, and eta = X beta is kept for every subject so the
+ * held-out log-likelihood can be scored at the fitted beta.  Cox model and
+ * 0/1 designs (the designs of Sec. 3.2); SS_EUNSUPPORTED otherwise.
+ *
+ * Per-replicate vectors are in SORTED order, replicate r starting at
+ * r * ss_cv_stride(n) elements (the stride is a multiple of 16384; the
+ * positions from n to the stride are padding the library keeps at
+ * e = 0).  Sizes the caller allocates (device memory, caller-owned):
+ *   train_s, d8_r: R * stride bytes; d32_r: R * stride int32 (read only
+ *   where d8_r = 255, no initialisation needed); eta, e: R * stride
+ *   doubles; xbits: P * stride / 8 bytes; c_r, beta, delta: R * P doubles
+ *   (replicate-major); g12_out: R * P * 3 doubles or NULL; out of
+ *   ss_cv_loglik: 2 R doubles; ws of ss_cv_prepare:
+ *   ss_cv_prepare_workspace_bytes(n, R) bytes.
+ *
+ * ss_cv_prepare: from ss_prepare's perm and d8, the ORIGINAL-order status
+ * and training masks train[R][n] (1 = training subject, subject order,
+ * replicate-major): the sorted training flags train_s, the training events
+ * per run end d8_r / d32_r (same encoding as ss_prepare), the column
+ * bitmask xbits (bit k of column j, word k/32 of the column's stride/32
+ * 32-bit words) and c_r[r][j] = the training events with x_kj = 1.
+ * vals_sorted must be NULL (0/1 design).
+ *
+ * ss_cv_exp: e = exp(eta) at training positions, 0 elsewhere (all R).
+ *
+ * ss_cv_sweep: for every replicate at once, the coordinates j_begin ..
+ * j_end - 1 in order, each: a1 (the previous step at its column's rows,
+ * e multiplied by exp(step)), the Sec. 2.7 scan and reduction giving g' and
+ * g'' of the replicate's training data, and the a3 update of Sec. 2.4 on
+ * beta[r][j], delta[r][j]; g12_out[r][j] = (g', g'', applied step) if not
+ * NULL.  At the end eta holds X beta and e = exp(eta) (masked) afresh.
+ * One workgroup per replicate, no waits between workgroups, fixed
+ * summation order (deterministic).  Errors: SS_EINVAL for bad sizes or
+ * ranges or a null pointer, SS_EUNSUPPORTED for Fine-Gray.
+ *
+ * ss_cv_loglik: out[2r] = the training log partial likelihood of replicate
+ * r at its current eta, out[2r+1] = the held-out one: the held-out subjects
+ * as a data set of their own (their risk sets, their events), the
+ * predictive log-likelihood of the fold (Sec. 2.8).  d8, d32: ss_prepare's
+ * full-data counts. */
+int64_t ss_cv_stride(int64_t n);
+size_t ss_cv_prepare_workspace_bytes(int64_t n, int32_t reps);
+int32_t ss_cv_prepare(int32_t model, int64_t n, int64_t p, int32_t reps,
+                      const int32_t *perm, const int8_t *status,
+                      const uint8_t *d8, const uint8_t *train,
+                      const int64_t *col_ptr, const int32_t *rows_sorted,
+                      const double *vals_sorted, uint8_t *train_s,
+                      uint8_t *d8_r, int32_t *d32_r, uint32_t *xbits,
+                      double *c_r, void *ws, size_t ws_bytes, void *stream);
+int32_t ss_cv_exp(int64_t n, int32_t reps, const double *eta,
+                  const uint8_t *train_s, double *e, void *stream);
+int32_t ss_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n,
+                    int64_t p, int32_t reps, int64_t j_begin, int64_t j_end,
+                    double *eta, double *e, const uint8_t *d8_r,
+                    const int32_t *d32_r, const uint8_t *train_s,
+                    const uint32_t *xbits, const double *c_r, double *beta,
+                    double *delta, double *g12_out, void *stream);
+int32_t ss_cv_loglik(int32_t model, int64_t n, int32_t reps,
+                     const int32_t *perm, const int8_t *status,
+                     const double *eta, const double *e,
+                     const uint8_t *train_s, const uint8_t *d8,
+                     const int32_t *d32, const uint8_t *d8_r,
+                     const int32_t *d32_r, double *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

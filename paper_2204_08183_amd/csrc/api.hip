@@ -348,4 +348,78 @@ int32_t ss_eta_gradient(int32_t model, int64_t n, const int32_t *perm, const int
                                loglik, ws, (hipStream_t)stream);
 }
 
+int64_t ss_cv_stride(int64_t n)
+{
+    if (n < 1 || n > INT32_MAX) return 0;
+    return cv_stride(n);
+}
+
+size_t ss_cv_prepare_workspace_bytes(int64_t n, int32_t reps)
+{
+    if (n < 1 || n > INT32_MAX || reps < 1 || reps > 65535) return 0;
+    return (size_t)reps * (size_t)(cv_stride(n) / 8);
+}
+
+static bool bad_cv(int64_t n, int64_t p, int32_t reps)
+{
+    return bad_size(n, p) || reps < 1 || reps > 65535;
+}
+
+int32_t ss_cv_prepare(int32_t model, int64_t n, int64_t p, int32_t reps, const int32_t *perm,
+                      const int8_t *status, const uint8_t *d8, const uint8_t *train,
+                      const int64_t *col_ptr, const int32_t *rows_sorted,
+                      const double *vals_sorted, uint8_t *train_s, uint8_t *d8_r,
+                      int32_t *d32_r, uint32_t *xbits, double *c_r, void *ws, size_t ws_bytes,
+                      void *stream)
+{
+    if (model == SS_FINE_GRAY) return SS_EUNSUPPORTED;
+    if (model != SS_COX) return SS_EUNSUPPORTED;
+    if (vals_sorted) return SS_EUNSUPPORTED;
+    if (bad_cv(n, p, reps)) return SS_EINVAL;
+    if (!perm || !status || !d8 || !train || !col_ptr || !rows_sorted || !train_s || !d8_r ||
+        !d32_r || !xbits || !c_r)
+        return SS_EINVAL;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < ss_cv_prepare_workspace_bytes(n, reps))
+        return SS_EWORKSPACE;
+    return launch_cv_prepare(model, n, p, reps, perm, status, d8, train, col_ptr, rows_sorted,
+                             train_s, d8_r, d32_r, xbits, c_r, ws, (hipStream_t)stream);
+}
+
+int32_t ss_cv_exp(int64_t n, int32_t reps, const double *eta, const uint8_t *train_s,
+                  double *e, void *stream)
+{
+    if (n < 1 || n > INT32_MAX || reps < 1 || reps > 65535) return SS_EINVAL;
+    if (!eta || !train_s || !e) return SS_EINVAL;
+    return launch_cv_exp(n, reps, eta, train_s, e, (hipStream_t)stream);
+}
+
+int32_t ss_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, int64_t p,
+                    int32_t reps, int64_t j_begin, int64_t j_end, double *eta, double *e,
+                    const uint8_t *d8_r, const int32_t *d32_r, const uint8_t *train_s,
+                    const uint32_t *xbits, const double *c_r, double *beta, double *delta,
+                    double *g12_out, void *stream)
+{
+    if (model != SS_COX) return SS_EUNSUPPORTED;
+    if (penalty != SS_PENALTY_NONE && penalty != SS_PENALTY_L1 && penalty != SS_PENALTY_L2)
+        return SS_EINVAL;
+    if (bad_cv(n, p, reps) || j_begin < 0 || j_end < j_begin || j_end > p) return SS_EINVAL;
+    if (!eta || !e || !d8_r || !d32_r || !train_s || !xbits || !c_r || !beta || !delta)
+        return SS_EINVAL;
+    return launch_cv_sweep(penalty, lambda, n, p, reps, j_begin, j_end, eta, e, d8_r, d32_r,
+                           train_s, xbits, c_r, beta, delta, g12_out, (hipStream_t)stream);
+}
+
+int32_t ss_cv_loglik(int32_t model, int64_t n, int32_t reps, const int32_t *perm,
+                     const int8_t *status, const double *eta, const double *e,
+                     const uint8_t *train_s, const uint8_t *d8, const int32_t *d32,
+                     const uint8_t *d8_r, const int32_t *d32_r, double *out, void *stream)
+{
+    if (model != SS_COX) return SS_EUNSUPPORTED;
+    if (n < 1 || n > INT32_MAX || reps < 1 || reps > 65535) return SS_EINVAL;
+    if (!perm || !status || !eta || !e || !train_s || !d8 || !d32 || !d8_r || !d32_r || !out)
+        return SS_EINVAL;
+    return launch_cv_loglik(model, n, reps, perm, status, eta, e, train_s, d8, d32, d8_r,
+                            d32_r, out, (hipStream_t)stream);
+}
+
 }  // extern "C"

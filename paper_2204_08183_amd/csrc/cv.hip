@@ -1,0 +1,589 @@
+// Cross-validation replicates in one launch (Sec. 2.8; the single larger
+// kernel for many repetitions of k-fold cross-validation that the paper's
+// concluding discussion proposes in place of one stream per fold).
+//
+// All replicates share the subjects' order by decreasing time, the tie runs
+// and the design X; each has its own training mask, linear predictor eta,
+// coefficients and trust-region widths.  A replicate is the data set of its
+// training subjects: its held-out subjects carry e = 0, so they drop out of
+// every prefix sum, and its event counts per run end and its c_j count
+// training events only.  eta is kept for every subject (X beta), so the
+// held-out log-likelihood can be evaluated at the fitted beta.
+//
+// One workgroup of 1024 threads runs one replicate's coordinates in order:
+// the scan of coordinate j goes over the replicate in chunks of 1024 x IPT
+// positions (each thread owns the same IPT consecutive positions of every
+// chunk for the whole launch), the thread sums are combined by one wave scan
+// and one barrier per chunk, the transform and reduction follow in
+// registers, and the Newton step of Sec. 2.4 is taken by thread 0.  No
+// workgroup ever waits for another, so the launch needs no co-residency, and
+// the summation order is fixed (deterministic results).
+//
+// Designs with x in {0, 1} (the Sec. 3.2 designs): column j is read as a
+// dense bitmask (stride/8 bytes per column, one load per thread per chunk)
+// instead of row indices, the update of column j multiplies e by exp(s) in
+// place at its rows, and S2 = S1 since x^2 = x.  e is recomputed as exp(eta)
+// when the launch ends.
+#include <math.h>
+
+#include "ss_device.h"
+
+namespace ss {
+
+namespace {
+
+using namespace dev;
+
+constexpr int kCvBlock = 1024;
+constexpr int kCvWaves = kCvBlock / kWave;
+constexpr int kCvAlign = 16384;  // per-replicate stride unit (a whole chunk)
+constexpr int kCvList = 512;     // non-zero steps held before eta is brought up to date
+constexpr int kCvGather = 16;    // column bitmask loads in flight while eta is updated
+
+__device__ __forceinline__ bool cv_event(int32_t model, int8_t s)
+{
+    return model == SS_FINE_GRAY ? s == 1 : s != 0;
+}
+
+// Prefix over the 16 wave totals of a chunk: lane q < 16 holds wave q's
+// total; an inclusive scan within the first DPP row of 16 lanes, then the
+// calling wave takes the sum of the waves before it and the chunk total.
+__device__ __forceinline__ void wave_totals_prefix(double v, int w, double &before,
+                                                   double &total)
+{
+    v += dpp_double<0x111, 0xF, true>(v);  // row_shr:1
+    v += dpp_double<0x112, 0xF, true>(v);  // row_shr:2
+    v += dpp_double<0x114, 0xF, true>(v);  // row_shr:4
+    v += dpp_double<0x118, 0xF, true>(v);  // row_shr:8
+    total = read_lane(v, kCvWaves - 1);
+    before = w > 0 ? read_lane(v, w - 1) : 0.0;
+}
+
+__device__ __forceinline__ uint64_t lanes_below(int lane)
+{
+    return lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+}
+
+// ---------------------------------------------------------------- prepare
+// Per replicate, in sorted order: the training flag, the training events
+// per run end (the run's events among the training subjects, at the
+// position where the full data set has its run end with events), and the
+// training-event bitmask (for c_j).  A run end with events is where the
+// full data set's count is non-zero; runs without events there hold no
+// training events either, so the training events of a run are the
+// training events after the previous such position.
+__global__ __launch_bounds__(kCvBlock) void k_cv_prep(int32_t model, int64_t n, int64_t stride,
+                                                      const int32_t *perm, const int8_t *status,
+                                                      const uint8_t *train, const uint8_t *d8,
+                                                      uint8_t *train_s, uint8_t *d8_r,
+                                                      int32_t *d32_r, uint32_t *evbits)
+{
+    __shared__ int s_cnt[kCvWaves];
+    __shared__ int s_last[kCvWaves];
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int w = tid / kWave;
+    const int64_t r = blockIdx.x;
+    const uint8_t *tr_in = train + r * n;
+    const int64_t off = r * stride;
+    int carry_cnt = 0;   // training events before the chunk
+    int carry_last = 0;  // their count at the last run end with events
+    for (int64_t base = 0; base < stride; base += kCvBlock) {
+        const int64_t k = base + tid;
+        int tr = 0, ev = 0, mark = 0;
+        if (k < n) {
+            const int32_t i = perm[k];
+            tr = tr_in[i] != 0;
+            ev = tr && cv_event(model, status[i]);
+            mark = d8[k] != 0;
+        }
+        const uint64_t bev = __ballot(ev);
+        const uint64_t bmark = __ballot(mark);
+        const int cnt_w = __popcll(bev & (lanes_below(lane) | (1ull << lane)));
+        if (lane == kWave - 1) s_cnt[w] = __popcll(bev);
+        __syncthreads();
+        int before = carry_cnt, total = carry_cnt;
+        for (int q = 0; q < kCvWaves; ++q) {
+            const int v = s_cnt[q];
+            if (q < w) before += v;
+            total += v;
+        }
+        const int cnt = before + cnt_w;  // inclusive count at k
+        // count at the nearest run end with events in this wave, below k
+        const uint64_t below = bmark & lanes_below(lane);
+        const int src = below ? 63 - __clzll(below) : lane;
+        const int v_below = __shfl(cnt, src);
+        const int v_top = __shfl(cnt, bmark ? 63 - __clzll(bmark) : 0);
+        if (lane == 0) s_last[w] = bmark ? v_top : -1;
+        __syncthreads();
+        int prev = carry_last, last = carry_last;
+        for (int q = 0; q < kCvWaves; ++q) {
+            const int v = s_last[q];
+            if (v >= 0) {
+                if (q < w) prev = v;
+                last = v;
+            }
+        }
+        if (below) prev = v_below;
+        const int d = mark ? cnt - prev : 0;
+        train_s[off + k] = (uint8_t)tr;
+        d8_r[off + k] = (uint8_t)(d >= 255 ? 255 : d);
+        if (d >= 255) d32_r[off + k] = d;
+        if (lane == 0) evbits[(off + k) / 32] = (uint32_t)bev;
+        if (lane == 32) evbits[(off + k) / 32] = (uint32_t)(bev >> 32);
+        carry_cnt = total;
+        carry_last = last;
+        __syncthreads();
+    }
+}
+
+// Column bitmask of a 0/1 design: bit k of column j is set where x_kj = 1
+// (k a sorted position).  The mask is cleared beforehand.
+__global__ __launch_bounds__(256) void k_cv_bits(int64_t p, int64_t words,
+                                                 const int64_t *col_ptr,
+                                                 const int32_t *rows_sorted, uint32_t *xbits)
+{
+    for (int64_t j = blockIdx.x; j < p; j += gridDim.x) {
+        const int64_t lo = col_ptr[j], hi = col_ptr[j + 1];
+        for (int64_t q = lo + threadIdx.x; q < hi; q += 256) {
+            const int32_t k = rows_sorted[q];
+            atomicOr(&xbits[j * words + (k >> 5)], 1u << (k & 31));
+        }
+    }
+}
+
+// c_j of every replicate: the training events with x_kj = 1.
+__global__ __launch_bounds__(256) void k_cv_c(int64_t p, int64_t words, const uint32_t *xbits,
+                                              const uint32_t *evbits, double *c)
+{
+    __shared__ int s_red[4];
+    const int64_t j = blockIdx.x;
+    const int64_t r = blockIdx.y;
+    const uint32_t *xb = xbits + j * words;
+    const uint32_t *eb = evbits + r * words;
+    int cnt = 0;
+    for (int64_t q = threadIdx.x; q < words; q += 256) cnt += __popc(xb[q] & eb[q]);
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane_id() == 0) s_red[threadIdx.x / kWave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) c[r * p + j] = (double)(s_red[0] + s_red[1] + s_red[2] + s_red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_cv_exp(int64_t total, const double *eta,
+                                                const uint8_t *train_s, double *e)
+{
+    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < total; k += (int64_t)gridDim.x * 256)
+        e[k] = train_s[k] ? exp(eta[k]) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_cv_fill(uint32_t *p, int64_t words)
+{
+    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < words; k += (int64_t)gridDim.x * 256)
+        p[k] = 0u;
+}
+
+// ---------------------------------------------------------------- sweep
+struct CvArgs {
+    int64_t n, p, stride;
+    int64_t j_begin, j_end;
+    int32_t penalty;
+    double lambda;
+    double *eta, *e;
+    const uint8_t *d8;
+    const int32_t *d32;
+    const uint8_t *train_s;
+    const uint8_t *xbits;
+    const double *c;
+    double *beta, *delta, *g12_out;
+};
+
+template <int IPT>
+struct CvChunk {
+    double v[IPT];
+    uint32_t d[IPT / 4];  // event counts, one byte per position
+    uint32_t x;           // column j at the thread's positions
+    uint32_t px;          // the pending column
+};
+
+template <int IPT>
+__device__ __forceinline__ void cv_load(const CvArgs &a, const double *e, const uint8_t *d8,
+                                        int64_t pos, int64_t j, int64_t jp, CvChunk<IPT> &c)
+{
+    const double2 *src = reinterpret_cast<const double2 *>(e + pos);
+#pragma unroll
+    for (int i = 0; i < IPT / 2; ++i) {
+        const double2 t = src[i];
+        c.v[2 * i] = t.x;
+        c.v[2 * i + 1] = t.y;
+    }
+    const int64_t cb = a.stride / 8;
+    if constexpr (IPT == 16) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(d8 + pos);
+        c.d[0] = q.x; c.d[1] = q.y; c.d[2] = q.z; c.d[3] = q.w;
+        c.x = *reinterpret_cast<const uint16_t *>(a.xbits + j * cb + pos / 8);
+        c.px = jp >= 0 ? *reinterpret_cast<const uint16_t *>(a.xbits + jp * cb + pos / 8) : 0u;
+    } else {
+        const uint2 q = *reinterpret_cast<const uint2 *>(d8 + pos);
+        c.d[0] = q.x; c.d[1] = q.y;
+        c.x = a.xbits[j * cb + pos / 8];
+        c.px = jp >= 0 ? a.xbits[jp * cb + pos / 8] : 0u;
+    }
+}
+
+template <int IPT>
+__device__ __forceinline__ uint32_t cv_bits(const CvArgs &a, int64_t j, int64_t pos)
+{
+    const uint8_t *col = a.xbits + j * (a.stride / 8) + pos / 8;
+    if constexpr (IPT == 16) return *reinterpret_cast<const uint16_t *>(col);
+    else return *col;
+}
+
+// eta += step * x_j at this thread's positions for the listed steps, in
+// the order they were taken (the order a coordinate-by-coordinate update
+// would add them); with `resync`, e = exp(eta) at training positions and 0
+// elsewhere afterwards.  Column bitmasks are fetched kCvGather at a time.
+template <int IPT>
+__device__ void cv_apply_steps(const CvArgs &a, double *eta, double *e, const uint8_t *train_s,
+                               const int32_t *lj, const double *ls, int nlist, int nch,
+                               int64_t tpos, bool resync)
+{
+    constexpr int CHUNK = kCvBlock * IPT;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int64_t pos = (int64_t)ch * CHUNK + tpos;
+        double v[IPT];
+        const double2 *src = reinterpret_cast<const double2 *>(eta + pos);
+#pragma unroll
+        for (int i = 0; i < IPT / 2; ++i) {
+            const double2 t = src[i];
+            v[2 * i] = t.x;
+            v[2 * i + 1] = t.y;
+        }
+        for (int q0 = 0; q0 < nlist; q0 += kCvGather) {
+            uint32_t b[kCvGather];
+#pragma unroll
+            for (int u = 0; u < kCvGather; ++u)
+                b[u] = q0 + u < nlist ? cv_bits<IPT>(a, lj[q0 + u], pos) : 0u;
+#pragma unroll
+            for (int u = 0; u < kCvGather; ++u) {
+                if (b[u] != 0u) {
+                    const double st = ls[q0 + u];
+#pragma unroll
+                    for (int i = 0; i < IPT; ++i)
+                        if ((b[u] >> i) & 1u) v[i] += st;
+                }
+            }
+        }
+        double2 *dst = reinterpret_cast<double2 *>(eta + pos);
+#pragma unroll
+        for (int i = 0; i < IPT / 2; ++i) dst[i] = make_double2(v[2 * i], v[2 * i + 1]);
+        if (resync) {
+            double2 *ed = reinterpret_cast<double2 *>(e + pos);
+#pragma unroll
+            for (int i = 0; i < IPT / 2; ++i)
+                ed[i] = make_double2(train_s[pos + 2 * i] ? exp(v[2 * i]) : 0.0,
+                                     train_s[pos + 2 * i + 1] ? exp(v[2 * i + 1]) : 0.0);
+        }
+    }
+}
+
+template <int IPT>
+__global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
+{
+    constexpr int CHUNK = kCvBlock * IPT;
+    __shared__ double s_tot[2][kCvWaves][2];
+    __shared__ double s_red[kCvWaves * 2];
+    __shared__ double s_step[2];
+    __shared__ int32_t s_lj[kCvList];
+    __shared__ double s_ls[kCvList];
+    __shared__ int s_ln;
+
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int w = tid / kWave;
+    const int64_t r = blockIdx.x;
+    const int64_t off = r * a.stride;
+    double *eta = a.eta + off;
+    double *e = a.e + off;
+    const uint8_t *d8 = a.d8 + off;
+    const int32_t *d32 = a.d32 + off;
+    const int nch = (int)(a.stride / CHUNK);
+    const int64_t tpos = (int64_t)tid * IPT;
+
+    double s_prev = 0.0, es_prev = 1.0;  // the pending step and exp of it
+    int64_t jp = -1;                     // its column
+    if (tid == 0) s_ln = 0;
+    __syncthreads();
+    CvChunk<IPT> cur;
+    if (a.j_begin < a.j_end) cv_load<IPT>(a, e, d8, tpos, a.j_begin, -1, cur);
+    int par = 0;
+    for (int64_t j = a.j_begin; j < a.j_end; ++j) {
+        // thread 0 fetches what the update needs now and uses it at the end
+        double cj = 0.0, bj = 0.0, dj = 0.0;
+        if (tid == 0) {
+            cj = a.c[r * a.p + j];
+            bj = a.beta[r * a.p + j];
+            dj = a.delta[r * a.p + j];
+        }
+        double acc1 = 0.0, acc2 = 0.0, carry0 = 0.0, carry1 = 0.0;
+        for (int ch = 0; ch < nch; ++ch) {
+            const int64_t pos = (int64_t)ch * CHUNK + tpos;
+            // a1: the pending step of column jp at this thread's positions
+            // (e only: eta is brought up to date from the list of steps)
+            if (cur.px != 0u && s_prev != 0.0) {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i)
+                    if ((cur.px >> i) & 1u) cur.v[i] *= es_prev;
+                double2 *dst = reinterpret_cast<double2 *>(e + pos);
+#pragma unroll
+                for (int i = 0; i < IPT / 2; ++i)
+                    dst[i] = make_double2(cur.v[2 * i], cur.v[2 * i + 1]);
+            }
+            // event counts; runs of 255 or more events read their count
+            // now, before the prefetch below, so that waiting for these
+            // rare loads never waits for the prefetch (loads complete in
+            // order)
+            uint32_t dv[IPT];
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) dv[i] = (cur.d[i / 4] >> (8 * (i % 4))) & 0xffu;
+#pragma unroll
+            for (int i = 0; i < IPT; ++i)
+                if (dv[i] == 255u) dv[i] = (uint32_t)d32[pos + i];
+            // the next chunk (of this coordinate or the next) is in flight
+            // during this one's arithmetic; issued after the stores above,
+            // which it may read when there is a single chunk.  After the
+            // last coordinate it re-reads column j (unused), so the number
+            // of loads in flight is the same on every path.
+            CvChunk<IPT> nx;
+            const bool last = ch + 1 == nch;
+            const int64_t jn = last ? (j + 1 < a.j_end ? j + 1 : j) : j;
+            cv_load<IPT>(a, e, d8, last ? tpos : pos + CHUNK, jn, last ? j : jp, nx);
+
+            double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                t0 += cur.v[i];
+                t1 += ((cur.x >> i) & 1u) ? cur.v[i] : 0.0;
+            }
+            const double i0 = dpp_incl_scan(t0);
+            const double i1 = dpp_incl_scan(t1);
+            if (lane == kWave - 1) {
+                s_tot[par][w][0] = i0;
+                s_tot[par][w][1] = i1;
+            }
+            __syncthreads();
+            double b0, b1, T0, T1;
+            wave_totals_prefix(lane < kCvWaves ? s_tot[par][lane][0] : 0.0, w, b0, T0);
+            wave_totals_prefix(lane < kCvWaves ? s_tot[par][lane][1] : 0.0, w, b1, T1);
+            const double p0 = carry0 + b0, p1 = carry1 + b1;
+            const double c0 = carry0 + T0, c1 = carry1 + T1;
+            par ^= 1;
+            double S0 = p0 + (i0 - t0);
+            double S1 = p1 + (i1 - t1);
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                S0 += cur.v[i];
+                S1 += ((cur.x >> i) & 1u) ? cur.v[i] : 0.0;
+                const uint32_t d = dv[i];
+                if (d != 0u) {
+                    const double g = S1 / S0;
+                    const double dd = (double)d;
+                    acc1 = fma(dd, g, acc1);
+                    acc2 = fma(dd, g - g * g, acc2);
+                }
+            }
+            carry0 = c0;
+            carry1 = c1;
+            cur = nx;
+        }
+        // g' = c_j - sum d S1/S0, g'' = -sum d (S2/S0 - (S1/S0)^2), S2 = S1
+        double red[2] = {acc1, acc2};
+        block_sum<2, kCvBlock>(red, s_red);
+        if (tid == 0) {
+            const double g1 = cj - red[0];
+            const double g2 = -red[1];
+            double step;
+            ccd_apply(g1, g2, a.penalty, a.lambda, &bj, &dj, &step);
+            a.beta[r * a.p + j] = bj;
+            a.delta[r * a.p + j] = dj;
+            if (a.g12_out) {
+                double *o = a.g12_out + (r * a.p + j) * 3;
+                o[0] = g1;
+                o[1] = g2;
+                o[2] = step;
+            }
+            s_step[0] = step;
+            s_step[1] = exp(step);
+            if (step != 0.0) {
+                s_lj[s_ln] = (int32_t)j;
+                s_ls[s_ln] = step;
+                s_ln = s_ln + 1;
+            }
+        }
+        __syncthreads();
+        s_prev = s_step[0];
+        es_prev = s_step[1];
+        jp = j;
+        if (s_ln == kCvList) {  // uniform: every thread reads the same count
+            cv_apply_steps<IPT>(a, eta, e, a.train_s + off, s_lj, s_ls, kCvList, nch, tpos,
+                                false);
+            __syncthreads();
+            if (tid == 0) s_ln = 0;
+            __syncthreads();
+        }
+    }
+
+    // eta brought up to date, and e = exp(eta) afresh (masked) everywhere
+    cv_apply_steps<IPT>(a, eta, e, a.train_s + off, s_lj, s_ls, s_ln, nch, tpos, true);
+}
+
+// ---------------------------------------------------------------- likelihood
+// Per replicate: the training log-likelihood (the e of the replicate, its
+// event counts) and the held-out one (exp(eta) of the held-out subjects,
+// the full data set's counts minus the training ones), each
+// sum over events of eta minus sum over run ends of d log S0.
+__global__ __launch_bounds__(kCvBlock) void k_cv_loglik(int32_t model, int64_t n,
+                                                        int64_t stride, const int32_t *perm,
+                                                        const int8_t *status,
+                                                        const double *eta, const double *e,
+                                                        const uint8_t *train_s,
+                                                        const uint8_t *d8, const int32_t *d32,
+                                                        const uint8_t *d8_r,
+                                                        const int32_t *d32_r, double *out)
+{
+    __shared__ double s_tot[kCvWaves][2];
+    __shared__ double s_red[kCvWaves * 2];
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int w = tid / kWave;
+    const int64_t r = blockIdx.x;
+    const int64_t off = r * stride;
+    double carry0 = 0.0, carry1 = 0.0, lt = 0.0, lh = 0.0;
+    for (int64_t base = 0; base < n; base += kCvBlock) {
+        const int64_t k = base + tid;
+        double et = 0.0, eh = 0.0, x = 0.0;
+        int dt = 0, dall = 0;
+        bool tr = false, ev = false;
+        if (k < n) {
+            tr = train_s[off + k] != 0;
+            x = eta[off + k];
+            et = e[off + k];
+            eh = tr ? 0.0 : exp(x);
+            ev = cv_event(model, status[perm[k]]);
+            dt = d8_r[off + k];
+            if (dt == 255) dt = d32_r[off + k];
+            dall = d8[k];
+            if (dall == 255) dall = d32[k];
+        }
+        const double i0 = dpp_incl_scan(et);
+        const double i1 = dpp_incl_scan(eh);
+        if (lane == kWave - 1) {
+            s_tot[w][0] = i0;
+            s_tot[w][1] = i1;
+        }
+        __syncthreads();
+        double b0, b1, T0, T1;
+        wave_totals_prefix(lane < kCvWaves ? s_tot[lane][0] : 0.0, w, b0, T0);
+        wave_totals_prefix(lane < kCvWaves ? s_tot[lane][1] : 0.0, w, b1, T1);
+        const double p0 = carry0 + b0, p1 = carry1 + b1;
+        const double c0 = carry0 + T0, c1 = carry1 + T1;
+        const double S0t = p0 + i0, S0h = p1 + i1;
+        const int dh = dall - dt;
+        if (ev) {
+            if (tr) lt += x;
+            else lh += x;
+        }
+        if (dt > 0) lt -= (double)dt * log(S0t);
+        if (dh > 0) lh -= (double)dh * log(S0h);
+        carry0 = c0;
+        carry1 = c1;
+        __syncthreads();
+    }
+    double red[2] = {lt, lh};
+    block_sum<2, kCvBlock>(red, s_red);
+    if (tid == 0) {
+        out[2 * r] = red[0];
+        out[2 * r + 1] = red[1];
+    }
+}
+
+int grid_of(int64_t n, int64_t cap) { return (int)std::max<int64_t>(1, std::min(cap, ceil_div(n, 256))); }
+
+}  // namespace
+
+int64_t cv_stride(int64_t n) { return ceil_div(n, kCvAlign) * kCvAlign; }
+
+int32_t launch_cv_prepare(int32_t model, int64_t n, int64_t p, int32_t reps, const int32_t *perm,
+                          const int8_t *status, const uint8_t *d8, const uint8_t *train,
+                          const int64_t *col_ptr, const int32_t *rows_sorted, uint8_t *train_s,
+                          uint8_t *d8_r, int32_t *d32_r, uint32_t *xbits, double *c_r,
+                          void *ws, hipStream_t s)
+{
+    const int64_t stride = cv_stride(n);
+    const int64_t words = stride / 32;
+    uint32_t *evbits = reinterpret_cast<uint32_t *>(ws);
+    hipLaunchKernelGGL(k_cv_prep, dim3(reps), dim3(kCvBlock), 0, s, model, n, stride, perm,
+                       status, train, d8, train_s, d8_r, d32_r, evbits);
+    SS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cv_fill, dim3(grid_of(p * words, 8192)), dim3(256), 0, s, xbits,
+                       p * words);
+    SS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cv_bits, dim3((unsigned)std::min<int64_t>(p, 65535)), dim3(256), 0, s,
+                       p, words, col_ptr, rows_sorted, xbits);
+    SS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cv_c, dim3((unsigned)p, (unsigned)reps), dim3(256), 0, s, p, words,
+                       xbits, evbits, c_r);
+    SS_LAUNCH_CHECK();
+    return SS_OK;
+}
+
+int32_t launch_cv_exp(int64_t n, int32_t reps, const double *eta, const uint8_t *train_s,
+                      double *e, hipStream_t s)
+{
+    const int64_t total = cv_stride(n) * reps;
+    hipLaunchKernelGGL(k_cv_exp, dim3(grid_of(total, 8192)), dim3(256), 0, s, total, eta,
+                       train_s, e);
+    SS_LAUNCH_CHECK();
+    return SS_OK;
+}
+
+int32_t launch_cv_sweep(int32_t penalty, double lambda, int64_t n, int64_t p, int32_t reps,
+                        int64_t j_begin, int64_t j_end, double *eta, double *e,
+                        const uint8_t *d8_r, const int32_t *d32_r, const uint8_t *train_s,
+                        const uint32_t *xbits, const double *c_r, double *beta, double *delta,
+                        double *g12_out, hipStream_t s)
+{
+    CvArgs a;
+    a.n = n;
+    a.p = p;
+    a.stride = cv_stride(n);
+    a.j_begin = j_begin;
+    a.j_end = j_end;
+    a.penalty = penalty;
+    a.lambda = lambda;
+    a.eta = eta;
+    a.e = e;
+    a.d8 = d8_r;
+    a.d32 = d32_r;
+    a.train_s = train_s;
+    a.xbits = reinterpret_cast<const uint8_t *>(xbits);
+    a.c = c_r;
+    a.beta = beta;
+    a.delta = delta;
+    a.g12_out = g12_out;
+    hipLaunchKernelGGL(k_cv_sweep<8>, dim3(reps), dim3(kCvBlock), 0, s, a);
+    SS_LAUNCH_CHECK();
+    return SS_OK;
+}
+
+int32_t launch_cv_loglik(int32_t model, int64_t n, int32_t reps, const int32_t *perm,
+                         const int8_t *status, const double *eta, const double *e,
+                         const uint8_t *train_s, const uint8_t *d8, const int32_t *d32,
+                         const uint8_t *d8_r, const int32_t *d32_r, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cv_loglik, dim3(reps), dim3(kCvBlock), 0, s, model, n, cv_stride(n),
+                       perm, status, eta, e, train_s, d8, d32, d8_r, d32_r, out);
+    SS_LAUNCH_CHECK();
+    return SS_OK;
+}
+
+}  // namespace ss

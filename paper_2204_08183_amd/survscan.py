@@ -63,6 +63,15 @@ SIGNATURES = {
     "ss_exp_f32": (_i32, [_i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_grad_hess_mixed": (_i32, [_i32, _i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp,
                                   _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ss_cv_stride": (_i64, [_i64]),
+    "ss_cv_prepare_workspace_bytes": (_sz, [_i64, _i32]),
+    "ss_cv_prepare": (_i32, [_i32, _i64, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                             _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ss_cv_exp": (_i32, [_i64, _i32, _vp, _vp, _vp, _vp]),
+    "ss_cv_sweep": (_i32, [_i32, _i32, _f64, _i64, _i64, _i32, _i64, _i64, _vp, _vp, _vp, _vp,
+                           _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ss_cv_loglik": (_i32, [_i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                            _vp, _vp]),
     "ss_eta_gradient_workspace_bytes": (_sz, [_i64]),
     "ss_eta_gradient": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                _vp, _sz, _vp]),
@@ -279,6 +288,82 @@ class Problem:
         check(load().ss_workspace_error(self.ws.ptr, ctypes.byref(flag),
                                         _stream(self.device)), "ss_workspace_error")
         return int(flag.value)
+
+
+class CrossValidation:
+    """R cross-validation replicates of a prepared Cox problem with a 0/1
+    design, fitted together (one workgroup per replicate).
+
+    `train` is [R, n] (1 = training subject, original subject order).
+    Per-replicate state lives in sorted order with replicate r at offset
+    r * stride: eta, e (R * stride), beta, delta ([R, p])."""
+
+    def __init__(self, prob, train):
+        lib = load()
+        self.prob = prob
+        dev = prob.device
+        train = torch.as_tensor(train, dtype=torch.uint8).to(dev).contiguous()
+        if train.dim() != 2 or train.shape[1] != prob.n:
+            raise ValueError("train must be [replicates, n]")
+        self.reps = reps = int(train.shape[0])
+        n, p = prob.n, prob.p
+        self.stride = stride = int(lib.ss_cv_stride(n))
+        self.train = train
+        self.train_s = torch.empty(reps * stride, dtype=torch.uint8, device=dev)
+        self.d8_r = torch.empty(reps * stride, dtype=torch.uint8, device=dev)
+        self.d32_r = torch.empty(reps * stride, dtype=torch.int32, device=dev)
+        self.xbits = torch.empty(p * stride // 32, dtype=torch.int32, device=dev)
+        self.c = torch.empty(reps * p, dtype=torch.float64, device=dev)
+        ws = Workspace(lib.ss_cv_prepare_workspace_bytes(n, reps), dev)
+        check(lib.ss_cv_prepare(prob.model, n, p, reps, _p(prob.perm), _p(prob.status),
+                                _p(prob.d8), _p(train), _p(prob.col_ptr), _p(prob.rows_sorted),
+                                _p(prob.vals_sorted), _p(self.train_s), _p(self.d8_r),
+                                _p(self.d32_r), _p(self.xbits), _p(self.c), ws.ptr, ws.nbytes,
+                                _stream(dev)), "ss_cv_prepare")
+        del ws
+        self.eta = torch.zeros(reps * stride, dtype=torch.float64, device=dev)
+        self.e = torch.empty(reps * stride, dtype=torch.float64, device=dev)
+        self.beta = torch.zeros(reps * p, dtype=torch.float64, device=dev)
+        self.delta = torch.ones(reps * p, dtype=torch.float64, device=dev)
+        check(lib.ss_cv_exp(n, reps, _p(self.eta), _p(self.train_s), _p(self.e),
+                            _stream(dev)), "ss_cv_exp")
+
+    def set_eta(self, eta_subject_order):
+        """Sets every replicate's eta from [R, n] (original order)."""
+        lib = load()
+        src = torch.as_tensor(eta_subject_order, dtype=torch.float64).to(self.prob.device)
+        src = src.contiguous()
+        s = _stream(self.prob.device)
+        for r in range(self.reps):
+            check(lib.ss_gather(self.prob.n, _p(self.prob.perm), _p(src[r]),
+                                ctypes.c_void_p(self.eta.data_ptr() + 8 * r * self.stride), s),
+                  "ss_gather")
+        check(lib.ss_cv_exp(self.prob.n, self.reps, _p(self.eta), _p(self.train_s),
+                            _p(self.e), s), "ss_cv_exp")
+
+    def sweep(self, penalty="none", lam=0.0, j_begin=0, j_end=None, g12_out=None):
+        j_end = self.prob.p if j_end is None else j_end
+        check(load().ss_cv_sweep(self.prob.model, PENALTIES[penalty], float(lam), self.prob.n,
+                                 self.prob.p, self.reps, int(j_begin), int(j_end),
+                                 _p(self.eta), _p(self.e), _p(self.d8_r), _p(self.d32_r),
+                                 _p(self.train_s), _p(self.xbits), _p(self.c), _p(self.beta),
+                                 _p(self.delta), _p(g12_out), _stream(self.prob.device)),
+              "ss_cv_sweep")
+
+    def loglik(self, out=None):
+        """[R, 2]: training and held-out log partial likelihood per replicate."""
+        out = torch.empty(2 * self.reps, dtype=torch.float64, device=self.prob.device) \
+            if out is None else out
+        pr = self.prob
+        check(load().ss_cv_loglik(pr.model, pr.n, self.reps, _p(pr.perm), _p(pr.status),
+                                  _p(self.eta), _p(self.e), _p(self.train_s), _p(pr.d8),
+                                  _p(pr.d32), _p(self.d8_r), _p(self.d32_r), _p(out),
+                                  _stream(pr.device)), "ss_cv_loglik")
+        return out.view(self.reps, 2)
+
+    def sorted_view(self, t):
+        """[R, n] view of a per-replicate sorted vector (eta, e, ...)."""
+        return t.view(self.reps, self.stride)[:, :self.prob.n]
 
 
 class LogLikEta(torch.autograd.Function):
