@@ -318,9 +318,15 @@ int32_t ss_eta_gradient(int32_t model, int64_t n, const int32_t *perm,
  * g'' of the replicate's training data, and the a3 update of Sec. 2.4 on
  * beta[r][j], delta[r][j]; g12_out[r][j] = (g', g'', applied step) if not
  * NULL.  At the end eta holds X beta and e = exp(eta) (masked) afresh.
- * One workgroup per replicate, no waits between workgroups, fixed
- * summation order (deterministic).  Errors: SS_EINVAL for bad sizes or
- * ranges or a null pointer, SS_EUNSUPPORTED for Fine-Gray.
+ * One workgroup per replicate, or two (each half of the positions, one
+ * exchange per coordinate, cooperative launch) when all of them fit on
+ * the device at once; fixed summation order either way (deterministic for
+ * a given device).  ws: ss_cv_workspace_bytes(R) bytes, 256-byte aligned,
+ * zero-filled before first use (ss_workspace_init), kept between calls; a
+ * bounded wait that gives up sets its error word (ss_workspace_error),
+ * after which it must be zero-filled again.  Errors: SS_EINVAL for bad
+ * sizes or ranges or a null pointer, SS_EWORKSPACE for a short or
+ * misaligned workspace, SS_EUNSUPPORTED for Fine-Gray.
  *
  * ss_cv_loglik: out[2r] = the training log partial likelihood of replicate
  * r at its current eta, out[2r+1] = the held-out one: the held-out subjects
@@ -338,12 +344,14 @@ int32_t ss_cv_prepare(int32_t model, int64_t n, int64_t p, int32_t reps,
                       double *c_r, void *ws, size_t ws_bytes, void *stream);
 int32_t ss_cv_exp(int64_t n, int32_t reps, const double *eta,
                   const uint8_t *train_s, double *e, void *stream);
+size_t ss_cv_workspace_bytes(int32_t reps);
 int32_t ss_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n,
                     int64_t p, int32_t reps, int64_t j_begin, int64_t j_end,
                     double *eta, double *e, const uint8_t *d8_r,
                     const int32_t *d32_r, const uint8_t *train_s,
                     const uint32_t *xbits, const double *c_r, double *beta,
-                    double *delta, double *g12_out, void *stream);
+                    double *delta, double *g12_out, void *ws, size_t ws_bytes,
+                    void *stream);
 int32_t ss_cv_loglik(int32_t model, int64_t n, int32_t reps,
                      const int32_t *perm, const int8_t *status,
                      const double *eta, const double *e,

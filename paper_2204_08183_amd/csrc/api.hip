@@ -393,11 +393,17 @@ int32_t ss_cv_exp(int64_t n, int32_t reps, const double *eta, const uint8_t *tra
     return launch_cv_exp(n, reps, eta, train_s, e, (hipStream_t)stream);
 }
 
+size_t ss_cv_workspace_bytes(int32_t reps)
+{
+    if (reps < 1 || reps > 65535) return 0;
+    return cv_ws_bytes(reps);
+}
+
 int32_t ss_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, int64_t p,
                     int32_t reps, int64_t j_begin, int64_t j_end, double *eta, double *e,
                     const uint8_t *d8_r, const int32_t *d32_r, const uint8_t *train_s,
                     const uint32_t *xbits, const double *c_r, double *beta, double *delta,
-                    double *g12_out, void *stream)
+                    double *g12_out, void *ws, size_t ws_bytes, void *stream)
 {
     if (model != SS_COX) return SS_EUNSUPPORTED;
     if (penalty != SS_PENALTY_NONE && penalty != SS_PENALTY_L1 && penalty != SS_PENALTY_L2)
@@ -405,8 +411,9 @@ int32_t ss_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, in
     if (bad_cv(n, p, reps) || j_begin < 0 || j_end < j_begin || j_end > p) return SS_EINVAL;
     if (!eta || !e || !d8_r || !d32_r || !train_s || !xbits || !c_r || !beta || !delta)
         return SS_EINVAL;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < cv_ws_bytes(reps)) return SS_EWORKSPACE;
     return launch_cv_sweep(penalty, lambda, n, p, reps, j_begin, j_end, eta, e, d8_r, d32_r,
-                           train_s, xbits, c_r, beta, delta, g12_out, (hipStream_t)stream);
+                           train_s, xbits, c_r, beta, delta, g12_out, ws, (hipStream_t)stream);
 }
 
 int32_t ss_cv_loglik(int32_t model, int64_t n, int32_t reps, const int32_t *perm,

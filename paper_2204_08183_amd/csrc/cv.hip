@@ -25,6 +25,7 @@
 // place at its rows, and S2 = S1 since x^2 = x.  e is recomputed as exp(eta)
 // when the launch ends.
 #include <math.h>
+#include <stdlib.h>
 
 #include "ss_device.h"
 
@@ -183,9 +184,15 @@ __global__ __launch_bounds__(256) void k_cv_fill(uint32_t *p, int64_t words)
 }
 
 // ---------------------------------------------------------------- sweep
+// Exchange block of one replicate (two-half launches): the epoch of its
+// exchanges, then per round parity a slot of half 0 and one of half 1, each
+// a run of 16-byte (value, tag) pairs.
+constexpr int kCvXchBytes = 1280;
+
 struct CvArgs {
     int64_t n, p, stride;
     int64_t j_begin, j_end;
+    int32_t reps;
     int32_t penalty;
     double lambda;
     double *eta, *e;
@@ -195,7 +202,19 @@ struct CvArgs {
     const uint8_t *xbits;
     const double *c;
     double *beta, *delta, *g12_out;
+    WsHeader *hdr;  // the sticky error word of bounded waits
+    char *xch;      // exchange blocks, kCvXchBytes per replicate
 };
+
+__device__ __forceinline__ uint64_t *cv_epoch(const CvArgs &a, int64_t r)
+{
+    return reinterpret_cast<uint64_t *>(a.xch + r * kCvXchBytes);
+}
+
+__device__ __forceinline__ u32x4 *cv_slot(const CvArgs &a, int64_t r, int h, int par)
+{
+    return reinterpret_cast<u32x4 *>(a.xch + r * kCvXchBytes + 256 + (par * 2 + h) * 256);
+}
 
 template <int IPT>
 struct CvChunk {
@@ -203,32 +222,8 @@ struct CvChunk {
     uint32_t d[IPT / 4];  // event counts, one byte per position
     uint32_t x;           // column j at the thread's positions
     uint32_t px;          // the pending column
+    uint32_t x1;          // column j + 1 (half 0 of a two-half launch)
 };
-
-template <int IPT>
-__device__ __forceinline__ void cv_load(const CvArgs &a, const double *e, const uint8_t *d8,
-                                        int64_t pos, int64_t j, int64_t jp, CvChunk<IPT> &c)
-{
-    const double2 *src = reinterpret_cast<const double2 *>(e + pos);
-#pragma unroll
-    for (int i = 0; i < IPT / 2; ++i) {
-        const double2 t = src[i];
-        c.v[2 * i] = t.x;
-        c.v[2 * i + 1] = t.y;
-    }
-    const int64_t cb = a.stride / 8;
-    if constexpr (IPT == 16) {
-        const uint4 q = *reinterpret_cast<const uint4 *>(d8 + pos);
-        c.d[0] = q.x; c.d[1] = q.y; c.d[2] = q.z; c.d[3] = q.w;
-        c.x = *reinterpret_cast<const uint16_t *>(a.xbits + j * cb + pos / 8);
-        c.px = jp >= 0 ? *reinterpret_cast<const uint16_t *>(a.xbits + jp * cb + pos / 8) : 0u;
-    } else {
-        const uint2 q = *reinterpret_cast<const uint2 *>(d8 + pos);
-        c.d[0] = q.x; c.d[1] = q.y;
-        c.x = a.xbits[j * cb + pos / 8];
-        c.px = jp >= 0 ? a.xbits[jp * cb + pos / 8] : 0u;
-    }
-}
 
 template <int IPT>
 __device__ __forceinline__ uint32_t cv_bits(const CvArgs &a, int64_t j, int64_t pos)
@@ -238,17 +233,42 @@ __device__ __forceinline__ uint32_t cv_bits(const CvArgs &a, int64_t j, int64_t 
     else return *col;
 }
 
-// eta += step * x_j at this thread's positions for the listed steps, in
-// the order they were taken (the order a coordinate-by-coordinate update
-// would add them); with `resync`, e = exp(eta) at training positions and 0
-// elsewhere afterwards.  Column bitmasks are fetched kCvGather at a time.
+template <int IPT>
+__device__ __forceinline__ void cv_load(const CvArgs &a, const double *e, const uint8_t *d8,
+                                        int64_t pos, int64_t j, int64_t jp, int64_t j1,
+                                        CvChunk<IPT> &c)
+{
+    const double2 *src = reinterpret_cast<const double2 *>(e + pos);
+#pragma unroll
+    for (int i = 0; i < IPT / 2; ++i) {
+        const double2 t = src[i];
+        c.v[2 * i] = t.x;
+        c.v[2 * i + 1] = t.y;
+    }
+    if constexpr (IPT == 16) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(d8 + pos);
+        c.d[0] = q.x; c.d[1] = q.y; c.d[2] = q.z; c.d[3] = q.w;
+    } else {
+        const uint2 q = *reinterpret_cast<const uint2 *>(d8 + pos);
+        c.d[0] = q.x; c.d[1] = q.y;
+    }
+    c.x = cv_bits<IPT>(a, j, pos);
+    c.px = jp >= 0 ? cv_bits<IPT>(a, jp, pos) : 0u;
+    c.x1 = j1 >= 0 ? cv_bits<IPT>(a, j1, pos) : 0u;
+}
+
+// eta += step * x_j at this thread's positions of chunks [ch_lo, ch_hi)
+// for the listed steps, in the order they were taken (the order a
+// coordinate-by-coordinate update would add them); with `resync`,
+// e = exp(eta) at training positions and 0 elsewhere afterwards.  Column
+// bitmasks are fetched kCvGather at a time.
 template <int IPT>
 __device__ void cv_apply_steps(const CvArgs &a, double *eta, double *e, const uint8_t *train_s,
-                               const int32_t *lj, const double *ls, int nlist, int nch,
-                               int64_t tpos, bool resync)
+                               const int32_t *lj, const double *ls, int nlist, int ch_lo,
+                               int ch_hi, int64_t tpos, bool resync)
 {
     constexpr int CHUNK = kCvBlock * IPT;
-    for (int ch = 0; ch < nch; ++ch) {
+    for (int ch = ch_lo; ch < ch_hi; ++ch) {
         const int64_t pos = (int64_t)ch * CHUNK + tpos;
         double v[IPT];
         const double2 *src = reinterpret_cast<const double2 *>(eta + pos);
@@ -286,46 +306,132 @@ __device__ void cv_apply_steps(const CvArgs &a, double *eta, double *e, const ui
     }
 }
 
-template <int IPT>
+// KH = 1: one workgroup per replicate.  KH = 2: two, each holding half of
+// the replicate's chunks (a cooperative launch, so both are resident).  Per
+// coordinate the halves exchange once: half 1 publishes its partial sums;
+// half 0 publishes its partial sums, c_j, beta_j, delta_j and what half 1
+// needs for its carry of the NEXT coordinate.  With x in {0, 1} the step s
+// multiplies e by exp(s) at column j, so half 0's totals for coordinate
+// j + 1 are A0 + expm1(s) D0 (all e; D0 = e at column j) and
+// A1 + expm1(s) D1 (e at column j + 1; D1 = e at both columns), all
+// summed during the pass of coordinate j before s is known.  Both halves
+// then take the same Newton step from the same numbers.
+template <int IPT, int KH>
 __global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
 {
     constexpr int CHUNK = kCvBlock * IPT;
     __shared__ double s_tot[2][kCvWaves][2];
-    __shared__ double s_red[kCvWaves * 2];
-    __shared__ double s_step[2];
+    __shared__ double s_red[kCvWaves * 4];
+    __shared__ double s_step[4];  // step, exp(step), half 1's next carry
     __shared__ int32_t s_lj[kCvList];
     __shared__ double s_ls[kCvList];
     __shared__ int s_ln;
+    __shared__ int s_abort;
+    __shared__ uint64_t s_ep0;
 
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int w = tid / kWave;
-    const int64_t r = blockIdx.x;
+    int64_t r;
+    int h;
+    if constexpr (KH == 1) {
+        r = blockIdx.x;
+        h = 0;
+    } else {
+        // the two halves of a replicate are 8 workgroups apart, which puts
+        // them on the same XCD (workgroups go round-robin over the 8)
+        const int b = (int)blockIdx.x;
+        r = (int64_t)(b / 16) * 8 + (b % 8);
+        h = (b % 16) / 8;
+        if (r >= a.reps) return;
+    }
     const int64_t off = r * a.stride;
     double *eta = a.eta + off;
     double *e = a.e + off;
     const uint8_t *d8 = a.d8 + off;
     const int32_t *d32 = a.d32 + off;
     const int nch = (int)(a.stride / CHUNK);
+    // half 0 also sums what half 1's next carry needs: it takes ~40% of
+    // the chunks (measured: 36.4 against 38.3 ms for an even split at
+    // N = 1e5, 100 replicates)
+    const int chm = (nch * 2 + 2) / 5;
+    const int ch_lo = (KH == 2 && h == 1) ? chm : 0;
+    const int ch_hi = (KH == 2 && h == 0) ? chm : nch;
     const int64_t tpos = (int64_t)tid * IPT;
+    const bool lead = h == 0;                 // owns beta, delta, g12_out
+    const bool sums_next = KH == 2 && h == 0;  // sums for half 1's next carry
+    const int64_t T = a.j_end - a.j_begin;
+
+    if (tid == 0) {
+        s_ln = 0;
+        s_abort = 0;
+        s_ep0 = KH == 2 ? ld_relaxed_u64(cv_epoch(a, r)) : 0;
+    }
+    __syncthreads();
+    const uint64_t ep0 = s_ep0;
+    double k0 = 0.0, k1 = 0.0;  // half 1: half 0's totals of the coordinate
+
+    // round 0 of a two-half launch: half 1's carry for the first coordinate
+    if (KH == 2 && T > 0) {
+        const uint64_t tag = (ep0 << 1) | 1u;
+        if (h == 0) {
+            double x[2] = {0.0, 0.0};
+            for (int ch = ch_lo; ch < ch_hi; ++ch) {
+                const int64_t pos = (int64_t)ch * CHUNK + tpos;
+                const double2 *src = reinterpret_cast<const double2 *>(e + pos);
+                const uint32_t xb = cv_bits<IPT>(a, a.j_begin, pos);
+#pragma unroll
+                for (int i = 0; i < IPT / 2; ++i) {
+                    const double2 t = src[i];
+                    x[0] += t.x + t.y;
+                    x[1] += (((xb >> (2 * i)) & 1u) ? t.x : 0.0) +
+                            (((xb >> (2 * i + 1)) & 1u) ? t.y : 0.0);
+                }
+            }
+            block_sum<2, kCvBlock>(x, s_red);
+            if (tid == 0) {
+                u32x4 *sl = cv_slot(a, r, 0, 0);
+                st_pair(sl + 0, x[0], tag);
+                st_pair(sl + 1, x[1], tag);
+                st_pair(sl + 2, 0.0, tag);
+            }
+        } else {
+            if (tid == 0) {
+                u32x4 rr[3];
+                if (wait_pairs<3>(cv_slot(a, r, 0, 0), tag, a.hdr, rr)) {
+                    s_step[2] = pair_value(rr[0]);
+                    s_step[3] = pair_value(rr[1]);
+                } else {
+                    s_abort = 1;
+                    s_step[2] = s_step[3] = 0.0;
+                }
+            }
+            __syncthreads();
+            k0 = s_step[2];
+            k1 = s_step[3];
+        }
+    }
 
     double s_prev = 0.0, es_prev = 1.0;  // the pending step and exp of it
     int64_t jp = -1;                     // its column
-    if (tid == 0) s_ln = 0;
-    __syncthreads();
     CvChunk<IPT> cur;
-    if (a.j_begin < a.j_end) cv_load<IPT>(a, e, d8, tpos, a.j_begin, -1, cur);
+    const bool any = ch_lo < ch_hi;
+    if (T > 0 && any)
+        cv_load<IPT>(a, e, d8, (int64_t)ch_lo * CHUNK + tpos, a.j_begin, -1,
+                     sums_next && a.j_begin + 1 < a.j_end ? a.j_begin + 1 : -1, cur);
     int par = 0;
-    for (int64_t j = a.j_begin; j < a.j_end; ++j) {
-        // thread 0 fetches what the update needs now and uses it at the end
+    for (int64_t j = a.j_begin; j < a.j_end && !s_abort; ++j) {
+        // the lead's thread 0 fetches what the update needs now, uses it at
+        // the end
         double cj = 0.0, bj = 0.0, dj = 0.0;
-        if (tid == 0) {
+        if (lead && tid == 0) {
             cj = a.c[r * a.p + j];
             bj = a.beta[r * a.p + j];
             dj = a.delta[r * a.p + j];
         }
-        double acc1 = 0.0, acc2 = 0.0, carry0 = 0.0, carry1 = 0.0;
-        for (int ch = 0; ch < nch; ++ch) {
+        double acc1 = 0.0, acc2 = 0.0, a1 = 0.0, d1 = 0.0;
+        double carry0 = k0, carry1 = k1;
+        for (int ch = ch_lo; ch < ch_hi; ++ch) {
             const int64_t pos = (int64_t)ch * CHUNK + tpos;
             // a1: the pending step of column jp at this thread's positions
             // (e only: eta is brought up to date from the list of steps)
@@ -354,15 +460,25 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
             // last coordinate it re-reads column j (unused), so the number
             // of loads in flight is the same on every path.
             CvChunk<IPT> nx;
-            const bool last = ch + 1 == nch;
+            const bool last = ch + 1 == ch_hi;
             const int64_t jn = last ? (j + 1 < a.j_end ? j + 1 : j) : j;
-            cv_load<IPT>(a, e, d8, last ? tpos : pos + CHUNK, jn, last ? j : jp, nx);
+            const int64_t jn1 = sums_next && jn + 1 < a.j_end ? jn + 1 : -1;
+            cv_load<IPT>(a, e, d8, last ? (int64_t)ch_lo * CHUNK + tpos : pos + CHUNK, jn,
+                         last ? j : jp, jn1, nx);
 
             double t0 = 0.0, t1 = 0.0;
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
                 t0 += cur.v[i];
                 t1 += ((cur.x >> i) & 1u) ? cur.v[i] : 0.0;
+            }
+            if (sums_next) {
+                const uint32_t both = cur.x & cur.x1;
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    a1 += ((cur.x1 >> i) & 1u) ? cur.v[i] : 0.0;
+                    d1 += ((both >> i) & 1u) ? cur.v[i] : 0.0;
+                }
             }
             const double i0 = dpp_incl_scan(t0);
             const double i1 = dpp_incl_scan(t1);
@@ -396,20 +512,64 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
             cur = nx;
         }
         // g' = c_j - sum d S1/S0, g'' = -sum d (S2/S0 - (S1/S0)^2), S2 = S1
-        double red[2] = {acc1, acc2};
-        block_sum<2, kCvBlock>(red, s_red);
+        double red[4] = {acc1, acc2, a1, d1};
+        if (sums_next) block_sum<4, kCvBlock>(red, s_red);
+        else block_sum<2, kCvBlock>(*reinterpret_cast<double(*)[2]>(red), s_red);
         if (tid == 0) {
-            const double g1 = cj - red[0];
-            const double g2 = -red[1];
-            double step;
-            ccd_apply(g1, g2, a.penalty, a.lambda, &bj, &dj, &step);
-            a.beta[r * a.p + j] = bj;
-            a.delta[r * a.p + j] = dj;
-            if (a.g12_out) {
-                double *o = a.g12_out + (r * a.p + j) * 3;
-                o[0] = g1;
-                o[1] = g2;
-                o[2] = step;
+            double g1, g2, step = 0.0;
+            bool ok = true;
+            if constexpr (KH == 2) {
+                const int64_t t = j - a.j_begin + 1;
+                const uint64_t tag = ((ep0 + (uint64_t)t) << 1) | 1u;
+                const int q = (int)(t & 1);
+                double h0[9], h1[2];
+                if (h == 0) {
+                    h0[0] = red[0]; h0[1] = red[1];
+                    h0[2] = carry0; h0[3] = carry1;  // A0, D0
+                    h0[4] = red[2]; h0[5] = red[3];  // A1, D1
+                    h0[6] = cj; h0[7] = bj; h0[8] = dj;
+                    u32x4 *sl = cv_slot(a, r, 0, q);
+#pragma unroll
+                    for (int m = 0; m < 9; ++m) st_pair(sl + m, h0[m], tag);
+                    u32x4 rr[3];
+                    ok = wait_pairs<3>(cv_slot(a, r, 1, q), tag, a.hdr, rr);
+                    h1[0] = pair_value(rr[0]);
+                    h1[1] = pair_value(rr[1]);
+                } else {
+                    h1[0] = red[0]; h1[1] = red[1];
+                    u32x4 *sl = cv_slot(a, r, 1, q);
+                    st_pair(sl + 0, h1[0], tag);
+                    st_pair(sl + 1, h1[1], tag);
+                    st_pair(sl + 2, 0.0, tag);
+                    u32x4 rr[9];
+                    ok = wait_pairs<9>(cv_slot(a, r, 0, q), tag, a.hdr, rr);
+#pragma unroll
+                    for (int m = 0; m < 9; ++m) h0[m] = pair_value(rr[m]);
+                    cj = h0[6]; bj = h0[7]; dj = h0[8];
+                }
+                g1 = cj - (h0[0] + h1[0]);
+                g2 = -(h0[1] + h1[1]);
+                if (ok) ccd_apply(g1, g2, a.penalty, a.lambda, &bj, &dj, &step);
+                if (h == 1) {
+                    const double em = expm1(step);
+                    s_step[2] = fma(em, h0[3], h0[2]);
+                    s_step[3] = fma(em, h0[5], h0[4]);
+                }
+            } else {
+                g1 = cj - red[0];
+                g2 = -red[1];
+                ccd_apply(g1, g2, a.penalty, a.lambda, &bj, &dj, &step);
+            }
+            if (!ok) s_abort = 1;
+            if (lead && ok) {
+                a.beta[r * a.p + j] = bj;
+                a.delta[r * a.p + j] = dj;
+                if (a.g12_out) {
+                    double *o = a.g12_out + (r * a.p + j) * 3;
+                    o[0] = g1;
+                    o[1] = g2;
+                    o[2] = step;
+                }
             }
             s_step[0] = step;
             s_step[1] = exp(step);
@@ -422,10 +582,14 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
         __syncthreads();
         s_prev = s_step[0];
         es_prev = s_step[1];
+        if (KH == 2 && h == 1) {
+            k0 = s_step[2];
+            k1 = s_step[3];
+        }
         jp = j;
         if (s_ln == kCvList) {  // uniform: every thread reads the same count
-            cv_apply_steps<IPT>(a, eta, e, a.train_s + off, s_lj, s_ls, kCvList, nch, tpos,
-                                false);
+            cv_apply_steps<IPT>(a, eta, e, a.train_s + off, s_lj, s_ls, kCvList, ch_lo, ch_hi,
+                                tpos, false);
             __syncthreads();
             if (tid == 0) s_ln = 0;
             __syncthreads();
@@ -433,7 +597,11 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
     }
 
     // eta brought up to date, and e = exp(eta) afresh (masked) everywhere
-    cv_apply_steps<IPT>(a, eta, e, a.train_s + off, s_lj, s_ls, s_ln, nch, tpos, true);
+    cv_apply_steps<IPT>(a, eta, e, a.train_s + off, s_lj, s_ls, s_ln, ch_lo, ch_hi, tpos, true);
+    // half 0 has seen half 1's last publication, made after half 1 read the
+    // epoch: the next launch's tags start after this launch's
+    if (KH == 2 && h == 0 && tid == 0 && T > 0 && !s_abort)
+        st_relaxed_u64(cv_epoch(a, r), ep0 + (uint64_t)T + 1);
 }
 
 // ---------------------------------------------------------------- likelihood
@@ -546,11 +714,13 @@ int32_t launch_cv_exp(int64_t n, int32_t reps, const double *eta, const uint8_t 
     return SS_OK;
 }
 
+size_t cv_ws_bytes(int32_t reps) { return 256 + (size_t)reps * kCvXchBytes; }
+
 int32_t launch_cv_sweep(int32_t penalty, double lambda, int64_t n, int64_t p, int32_t reps,
                         int64_t j_begin, int64_t j_end, double *eta, double *e,
                         const uint8_t *d8_r, const int32_t *d32_r, const uint8_t *train_s,
                         const uint32_t *xbits, const double *c_r, double *beta, double *delta,
-                        double *g12_out, hipStream_t s)
+                        double *g12_out, void *ws, hipStream_t s)
 {
     CvArgs a;
     a.n = n;
@@ -558,6 +728,7 @@ int32_t launch_cv_sweep(int32_t penalty, double lambda, int64_t n, int64_t p, in
     a.stride = cv_stride(n);
     a.j_begin = j_begin;
     a.j_end = j_end;
+    a.reps = reps;
     a.penalty = penalty;
     a.lambda = lambda;
     a.eta = eta;
@@ -570,7 +741,29 @@ int32_t launch_cv_sweep(int32_t penalty, double lambda, int64_t n, int64_t p, in
     a.beta = beta;
     a.delta = delta;
     a.g12_out = g12_out;
-    hipLaunchKernelGGL(k_cv_sweep<8>, dim3(reps), dim3(kCvBlock), 0, s, a);
+    a.hdr = reinterpret_cast<WsHeader *>(ws);
+    a.xch = reinterpret_cast<char *>(ws) + 256;
+    // two workgroups per replicate when all of them fit on the device at
+    // once (a cooperative launch checks it); one per replicate otherwise.
+    // SURVSCAN_CV_HALVES=1 forces one.
+    const char *env = getenv("SURVSCAN_CV_HALVES");
+    const bool allow2 = !(env && env[0] == '1');
+    if (allow2) {
+        int dev = 0, cus = 0, coop = 0, per_cu = 0;
+        SS_HIP_CHECK(hipGetDevice(&dev));
+        SS_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        SS_HIP_CHECK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        void *k = reinterpret_cast<void *>(k_cv_sweep<8, 2>);
+        SS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kCvBlock, 0));
+        const int64_t G = 16 * ceil_div(reps, 8);
+        if (coop && G <= (int64_t)per_cu * cus) {
+            void *args[] = {&a};
+            SS_HIP_CHECK(hipLaunchCooperativeKernel(k, dim3((unsigned)G), dim3(kCvBlock), args,
+                                                    0, s));
+            return SS_OK;
+        }
+    }
+    hipLaunchKernelGGL((k_cv_sweep<8, 1>), dim3(reps), dim3(kCvBlock), 0, s, a);
     SS_LAUNCH_CHECK();
     return SS_OK;
 }

@@ -238,11 +238,12 @@ int32_t launch_cv_prepare(int32_t model, int64_t n, int64_t p, int32_t reps, con
                           void *ws, hipStream_t s);
 int32_t launch_cv_exp(int64_t n, int32_t reps, const double *eta, const uint8_t *train_s,
                       double *e, hipStream_t s);
+size_t cv_ws_bytes(int32_t reps);
 int32_t launch_cv_sweep(int32_t penalty, double lambda, int64_t n, int64_t p, int32_t reps,
                         int64_t j_begin, int64_t j_end, double *eta, double *e,
                         const uint8_t *d8_r, const int32_t *d32_r, const uint8_t *train_s,
                         const uint32_t *xbits, const double *c_r, double *beta, double *delta,
-                        double *g12_out, hipStream_t s);
+                        double *g12_out, void *ws, hipStream_t s);
 int32_t launch_cv_loglik(int32_t model, int64_t n, int32_t reps, const int32_t *perm,
                          const int8_t *status, const double *eta, const double *e,
                          const uint8_t *train_s, const uint8_t *d8, const int32_t *d32,

@@ -68,27 +68,6 @@ struct SweepArgs {
     WsView ws;
 };
 
-// Polls NP pairs until all carry `tag`.  Returns false if the wait gave up
-// or another workgroup already did.
-template <int NP>
-__device__ bool wait_pairs(const u32x4 *p, uint64_t tag, WsHeader *hdr, u32x4 (&r)[NP])
-{
-    uint32_t spins = 0;
-    for (;;) {
-        ld_pairs<NP>(p, r);
-        bool ok = true;
-#pragma unroll
-        for (int c = 0; c < NP; ++c) ok = ok && pair_tag(r[c]) == tag;
-        if (ok) return true;
-        if ((++spins & 31u) == 0 && ld_relaxed_u32(&hdr->error)) return false;
-        if (spins > kSpinLimit) {
-            __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-}
-
 // Applies `st` times column jc to eta and e inside the segment; with LDS
 // (s_ep, s_flag) also patches the registers of the owners.
 template <int BLOCK, bool VALS, bool PATCH_LDS>

@@ -68,8 +68,9 @@ SIGNATURES = {
     "ss_cv_prepare": (_i32, [_i32, _i64, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                              _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_cv_exp": (_i32, [_i64, _i32, _vp, _vp, _vp, _vp]),
+    "ss_cv_workspace_bytes": (_sz, [_i32]),
     "ss_cv_sweep": (_i32, [_i32, _i32, _f64, _i64, _i64, _i32, _i64, _i64, _vp, _vp, _vp, _vp,
-                           _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+                           _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_cv_loglik": (_i32, [_i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                             _vp, _vp]),
     "ss_eta_gradient_workspace_bytes": (_sz, [_i64]),
@@ -327,6 +328,9 @@ class CrossValidation:
         self.delta = torch.ones(reps * p, dtype=torch.float64, device=dev)
         check(lib.ss_cv_exp(n, reps, _p(self.eta), _p(self.train_s), _p(self.e),
                             _stream(dev)), "ss_cv_exp")
+        self.ws = Workspace(lib.ss_cv_workspace_bytes(reps), dev)
+        check(lib.ss_workspace_init(self.ws.ptr, self.ws.nbytes, _stream(dev)),
+              "ss_workspace_init")
 
     def set_eta(self, eta_subject_order):
         """Sets every replicate's eta from [R, n] (original order)."""
@@ -347,8 +351,16 @@ class CrossValidation:
                                  self.prob.p, self.reps, int(j_begin), int(j_end),
                                  _p(self.eta), _p(self.e), _p(self.d8_r), _p(self.d32_r),
                                  _p(self.train_s), _p(self.xbits), _p(self.c), _p(self.beta),
-                                 _p(self.delta), _p(g12_out), _stream(self.prob.device)),
+                                 _p(self.delta), _p(g12_out), self.ws.ptr, self.ws.nbytes,
+                                 _stream(self.prob.device)),
               "ss_cv_sweep")
+
+    def workspace_error(self):
+        """Non-zero if a bounded wait of a two-half launch gave up."""
+        flag = ctypes.c_int32(0)
+        check(load().ss_workspace_error(self.ws.ptr, ctypes.byref(flag),
+                                        _stream(self.prob.device)), "ss_workspace_error")
+        return int(flag.value)
 
     def loglik(self, out=None):
         """[R, 2]: training and held-out log partial likelihood per replicate."""

@@ -111,6 +111,7 @@ def check_sweeps(d, train, penalty, lam, sweeps, tol, reps_to_check=None):
     eta_s = cvp.sorted_view(cvp.eta).cpu().numpy()
     e_s = cvp.sorted_view(cvp.e).cpu().numpy()
     ll = cvp.loglik().cpu().numpy()
+    assert cvp.workspace_error() == 0
     for r in (range(R) if reps_to_check is None else reps_to_check):
         b, dl, eta_all, hist = ocv.fit_replicate("cox", d["y"], d["status"], d["col_ptr"],
                                                  d["rows"], None, train[r], PEN[penalty], lam,
@@ -136,15 +137,31 @@ def check_sweeps(d, train, penalty, lam, sweeps, tol, reps_to_check=None):
     return prob, cvp
 
 
+HALVES = ["two", "one"]
+
+
+def _halves(monkeypatch, halves):
+    """Two workgroups per replicate (the default when they fit) or one."""
+    if halves == "one":
+        monkeypatch.setenv("SURVSCAN_CV_HALVES", "1")
+    else:
+        monkeypatch.delenv("SURVSCAN_CV_HALVES", raising=False)
+
+
+@pytest.mark.parametrize("halves", HALVES)
 @pytest.mark.parametrize("penalty,lam", [("l1", 2.0), ("l2", 1.0), ("none", 0.0)])
-def test_cv_sweeps_match_oracle(penalty, lam):
+def test_cv_sweeps_match_oracle(penalty, lam, halves, monkeypatch):
+    _halves(monkeypatch, halves)
     d = cox_case(7000, 8, 5, density=0.2)
     train = gen.cv_folds(6, d["n"], 4, 2)
     check_sweeps(d, train, penalty, lam, 2, 1e-9)
 
 
-@pytest.mark.parametrize("n,p,ties", [(1, 2, 0), (3, 2, 0), (8193, 4, 0), (50001, 5, 40)])
-def test_cv_sizes_and_ties(n, p, ties):
+@pytest.mark.parametrize("halves", HALVES)
+@pytest.mark.parametrize("n,p,ties", [(1, 2, 0), (3, 2, 0), (8193, 4, 0), (50001, 5, 40),
+                                      (24577, 3, 0)])
+def test_cv_sizes_and_ties(n, p, ties, halves, monkeypatch):
+    _halves(monkeypatch, halves)
     d = cox_case(n, p, 7, ties=ties, density=0.3 if n < 10 else 0.1)
     train = gen.cv_folds(8, n, 3, 2) if n >= 3 else np.ones((2, n), np.uint8)
     check_sweeps(d, train, "l1", 0.5, 1, 1e-10)
@@ -187,7 +204,9 @@ def test_cv_no_training_events():
     assert ll[1, 1] == pytest.approx(want, rel=1e-11)
 
 
-def test_cv_deterministic_and_set_eta():
+@pytest.mark.parametrize("halves", HALVES)
+def test_cv_deterministic_and_set_eta(halves, monkeypatch):
+    _halves(monkeypatch, halves)
     d = cox_case(40000, 5, 11)
     train = gen.cv_folds(12, d["n"], 5, 1)
     outs = []
@@ -226,7 +245,7 @@ def test_cv_rejects_unsupported():
     lib = ss.load()
     args = [ss._p(cvp.eta), ss._p(cvp.e), ss._p(cvp.d8_r), ss._p(cvp.d32_r),
             ss._p(cvp.train_s), ss._p(cvp.xbits), ss._p(cvp.c), ss._p(cvp.beta),
-            ss._p(cvp.delta), None, None]
+            ss._p(cvp.delta), None, cvp.ws.ptr, cvp.ws.nbytes, None]
     assert lib.ss_cv_sweep(ss.FINE_GRAY, 0, 0.0, prob.n, prob.p, 3, 0, 2,
                            *args) == ss.SS_EUNSUPPORTED
     assert lib.ss_cv_sweep(ss.COX, 0, 0.0, prob.n, prob.p, 3, 0, 3, *args) == ss.SS_EINVAL
@@ -234,6 +253,8 @@ def test_cv_rejects_unsupported():
     assert lib.ss_cv_sweep(ss.COX, 9, 0.0, prob.n, prob.p, 3, 0, 2, *args) == ss.SS_EINVAL
     # an empty coordinate range is a no-op that still resynchronises e
     assert lib.ss_cv_sweep(ss.COX, 0, 0.0, prob.n, prob.p, 3, 1, 1, *args) == ss.SS_OK
+    short = args[:-3] + [cvp.ws.ptr, cvp.ws.nbytes - 1, None]
+    assert lib.ss_cv_sweep(ss.COX, 0, 0.0, prob.n, prob.p, 3, 0, 2, *short) == ss.SS_EWORKSPACE
     valued = ss.Problem("cox", d["y"], d["status"], d["col_ptr"], d["rows"],
                         np.ones(d["rows"].size), DEV)
     with pytest.raises(ss.SurvScanError):
@@ -244,7 +265,9 @@ def test_cv_rejects_unsupported():
         ss.CrossValidation(fprob, gen.cv_folds(1, 3000, 3, 1))
 
 
-def test_cv_ten_by_ten_design():
+@pytest.mark.parametrize("halves", HALVES)
+def test_cv_ten_by_ten_design(halves, monkeypatch):
+    _halves(monkeypatch, halves)
     """10-fold x 10-repetition cross-validation at N = 1e5, P = 1000 (the
     Sec. 3.3 design at its smallest size), one l1 sweep: replicates 0, 57
     and 99 against the oracle over all 1000 coordinates."""
@@ -253,7 +276,9 @@ def test_cv_ten_by_ten_design():
     check_sweeps(d, train, "l1", float(np.sqrt(2.0)), 1, 1e-10, reps_to_check=(0, 57, 99))
 
 
-def test_cv_many_steps_in_one_launch():
+@pytest.mark.parametrize("halves", HALVES)
+def test_cv_many_steps_in_one_launch(halves, monkeypatch):
+    _halves(monkeypatch, halves)
     """More non-zero steps in one launch than the kernel holds before it
     brings eta up to date (no penalty: every coordinate moves), checked
     against the oracle over two sweeps."""
