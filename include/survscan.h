@@ -63,6 +63,8 @@ extern "C" {
 #define SS_ACC_F32       0     /* plain FP32 sums                          */
 #define SS_ACC_F32_COMP  1     /* compensated FP32: hi + lo by two-sum     */
 #define SS_ACC_F64       2     /* FP64 sums of the FP32 inputs             */
+#define SS_ACC_F32_C64   3     /* FP32 inside a tile, FP64 carry between
+                                  tiles and FP64 sum of the tile partials  */
 
 /* Granularity (in sorted positions) of the per-column chunk index built by
  * ss_prepare; tiles of the fused kernels are whole multiples of it. */

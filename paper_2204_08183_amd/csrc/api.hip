@@ -316,7 +316,9 @@ int32_t ss_grad_hess_mixed(int32_t model, int32_t acc, int64_t n, int64_t p, int
                            void *stream)
 {
     if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
-    if (acc != SS_ACC_F32 && acc != SS_ACC_F32_COMP && acc != SS_ACC_F64) return SS_EINVAL;
+    if (acc != SS_ACC_F32 && acc != SS_ACC_F32_COMP && acc != SS_ACC_F64 &&
+        acc != SS_ACC_F32_C64)
+        return SS_EINVAL;
     if (bad_size(n, p) || j < 0 || j >= p) return SS_EINVAL;
     if (!e32 || !d8 || !d32) return SS_EINVAL;
     if (model == SS_FINE_GRAY && (!w_comp || !g_end)) return SS_EINVAL;

@@ -4,6 +4,10 @@
 //   SS_ACC_F32       plain FP32 sums,
 //   SS_ACC_F32_COMP  compensated FP32 sums (hi + lo, two-sum),
 //   SS_ACC_F64       FP64 sums of the FP32 inputs,
+//   SS_ACC_F32_C64   FP32 sums inside a tile, FP64 across tiles: the
+//                    carry between tiles (the prefix a tile starts from)
+//                    and the sum of the tile partials are FP64, everything
+//                    else (in-tile scan, transform, in-tile reduction) FP32,
 // so that the error of each against the FP64 definition can be measured.
 // Accuracy is the point here, so the scan is a plain reduce-then-scan in a
 // fixed order: per-tile aggregates, one scan of them, then the tile pass
@@ -92,6 +96,37 @@ struct Acc<SS_ACC_F64> {
     __device__ double hi() const { return s; }
     __device__ double lo() const { return 0.0; }
     __device__ void set(double h, double) { s = h; }
+};
+
+// FP32 inside a tile, FP64 across tiles: `c` holds what came from other
+// tiles (set() from a stored prefix or partial, merges of such values), `s`
+// what was summed inside this tile.  Tile aggregates and partials leave a
+// tile as c + s and are merged in FP64; the running prefix of the tile pass
+// is the FP64 carry plus the FP32 in-tile sum.
+template <>
+struct Acc<SS_ACC_F32_C64> {
+    typedef float T;
+    double c;
+    float s;
+    __device__ void zero()
+    {
+        c = 0.0;
+        s = 0.f;
+    }
+    __device__ void add(float x) { s += x; }
+    __device__ void merge(const Acc &o)
+    {
+        c += o.c;
+        s += o.s;
+    }
+    __device__ double value() const { return c + (double)s; }
+    __device__ double hi() const { return c + (double)s; }
+    __device__ double lo() const { return 0.0; }
+    __device__ void set(double h, double l)
+    {
+        c = h + l;
+        s = 0.f;
+    }
 };
 
 // Inclusive block scan (Hillis-Steele in LDS, fixed order) of NC
@@ -508,6 +543,7 @@ int32_t launch_mixed(int32_t acc, int32_t model, int64_t n, int64_t p, int32_t j
     case SS_ACC_F32: return launch_mixed_acc<SS_ACC_F32>(a, ws, s);
     case SS_ACC_F32_COMP: return launch_mixed_acc<SS_ACC_F32_COMP>(a, ws, s);
     case SS_ACC_F64: return launch_mixed_acc<SS_ACC_F64>(a, ws, s);
+    case SS_ACC_F32_C64: return launch_mixed_acc<SS_ACC_F32_C64>(a, ws, s);
     default: return SS_EINVAL;
     }
 }

@@ -31,7 +31,8 @@ PENALTIES = {"none": PENALTY_NONE, "l1": PENALTY_L1, "l2": PENALTY_L2}
 ACC_F32 = 0
 ACC_F32_COMP = 1
 ACC_F64 = 2
-ACCUMULATIONS = {"f32": ACC_F32, "f32c": ACC_F32_COMP, "f64": ACC_F64}
+ACC_F32_C64 = 3
+ACCUMULATIONS = {"f32": ACC_F32, "f32c": ACC_F32_COMP, "f64": ACC_F64, "f32x64": ACC_F32_C64}
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32

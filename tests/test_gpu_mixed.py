@@ -2,7 +2,8 @@
 FP64 oracle.
 
 e is kept as exp(eta - m) in FP32 (m = max eta) and the scans and sums run in
-plain FP32, compensated FP32 (two-sum) or FP64.  Checks:
+plain FP32, compensated FP32 (two-sum), FP32 inside tiles with an FP64 carry
+between tiles ("f32x64"), or FP64.  Checks:
   * FP64 accumulation against the oracle evaluated on the same FP32-rounded
     e: the FP64 bound of the parity tests (1e-10, condition-scaled);
   * both FP32 accumulations against the oracle on the original FP64 e: the
@@ -71,7 +72,7 @@ def test_mixed_matches_oracle(model, n, p, seed, ties, valued):
         got = prob.grad_hess_mixed(j, e32, "f64").cpu().numpy()
         e1, e2, eL = scaled_errors(got, want_r)
         assert max(e1, e2, eL) <= TOL64, (model, n, j, "f64", e1, e2, eL)
-        for acc in ("f32", "f32c"):
+        for acc in ("f32", "f32c", "f32x64"):
             got = prob.grad_hess_mixed(j, e32, acc).cpu().numpy()
             e1, e2, eL = scaled_errors(got, want, m * nev)
             assert max(e1, e2, eL) <= TOL32, (model, n, j, acc, e1, e2, eL)
@@ -89,8 +90,9 @@ def test_mixed_shift_overflow():
     m = float(shift.cpu()[0])
     for j in range(3):
         want = pr.coordinate(c["eta"], xcol(c, j))
-        got = prob.grad_hess_mixed(j, e32, "f32c").cpu().numpy()
-        assert max(scaled_errors(got, want, m * nev)) <= TOL32
+        for acc in ("f32c", "f32x64"):
+            got = prob.grad_hess_mixed(j, e32, acc).cpu().numpy()
+            assert max(scaled_errors(got, want, m * nev)) <= TOL32
 
 
 def test_mixed_rejects_bad_accumulation():
@@ -112,7 +114,7 @@ def _report_config(name, model, c, coords):
     m = float(shift.cpu()[0])
     nev = float(np.sum(oprep.event_indicator(model, c["status"])))
     pr = oscan.Prepared(model, c["y"], c["status"])
-    errs = {acc: [] for acc in ("f32", "f32c", "f64")}
+    errs = {acc: [] for acc in ("f32", "f32c", "f32x64", "f64")}
     for j in coords:
         want = pr.coordinate(c["eta"], xcol(c, j))
         for acc in errs:
