@@ -791,7 +791,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
                 if (fl[i] & bprev) {
-                    s_eta[i * BLOCK + tid] += st_prev;
+                    // LDS atomic add, result unused: no wait for a read
+                    // (only this thread touches the position, in order)
+                    __hip_atomic_fetch_add(&s_eta[i * BLOCK + tid], st_prev, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
                     ev[i] *= fe;
                 }
             }
