@@ -12,7 +12,9 @@ density (seed 0), already prepared and resident in HBM when timing starts.
 One JSON line is printed.  Besides the throughput it carries
   roofline      the fused Cox kernel at N = 2^27 (its HBM-bound size), timed
                 with HIP events on its own stream;
-  cpu_baseline  the FP64 oracle (serial C scan) on a bounded sample;
+  cpu_baseline  the FP64 oracle (serial C scan) on a bounded sample, one
+                thread; cpu_baseline_all_cores: the same scan on every host
+                core, coordinates in parallel;
   context       our fused kernel at N = 1e5 next to the paper's GV100 time;
   cv            10-fold x 10-repetition cross-validation (100 replicates) at
                 N = 1e5, P = 1000: one l1 sweep of every replicate in one
@@ -202,6 +204,34 @@ def cpu_baseline(gen, cox, fg, coords):
                                                                   dt)}
 
 
+def cpu_baseline_all_cores(gen, cox, coords_per_thread=60):
+    """The same oracle scan on all host cores: independent coordinates at
+    fixed beta = 0 (Cox, N = 1e6), one C call per coordinate per thread
+    (ctypes releases the interpreter lock during the call)."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    from oracle import scan as oscan
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else \
+        (os.cpu_count() or 1)
+    pr = oscan.Prepared("cox", cox["y"], cox["status"])
+    eta_s = np.zeros(cox["n"])
+    total = min(cox["p"], threads * coords_per_thread)
+    cols = [np.ascontiguousarray(
+        gen.dense_column(cox["n"], cox["col_ptr"], cox["rows"], None, j)[pr.order])
+        for j in range(total)]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda x: pr.coordinate_sorted(eta_s, x), cols))
+    dt = time.perf_counter() - t0
+    return {"value": round(total / dt, 2), "unit": "coords/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d coordinates of the Cox N=%d P=%d data set at beta=0 (gradient and "
+                      "Hessian only, no update), spread over %d threads; %.1f s"
+                      % (total, cox["n"], cox["p"], threads, dt)}
+
+
 def copy_calibration(torch):
     a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
     b = torch.empty_like(a)
@@ -310,6 +340,8 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle) on %d coordinates per model" % args.cpu_coords)
         line["cpu_baseline"] = cpu_baseline(gen, cox, fg, args.cpu_coords)
+        log("cpu baseline (oracle) on all host cores")
+        line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(gen, cox)
     print(json.dumps(line), flush=True)
 
 

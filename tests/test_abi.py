@@ -94,3 +94,62 @@ def test_invalid_arguments_rejected_before_launch(lib):
     assert lib.ss_exp(0, f, f, None) == ss.SS_EINVAL
     assert lib.ss_gather(5, None, f, f, None) == ss.SS_EINVAL
     assert lib.ss_workspace_init(None, 100, None) == ss.SS_EWORKSPACE
+
+
+def test_new_entry_points_validate_on_the_host(lib):
+    f = _fake()
+    big = 1 << 30
+    # full gradient in eta: model, size, pointers, workspace
+    assert lib.ss_eta_gradient_workspace_bytes(0) == 0
+    ws = lib.ss_eta_gradient_workspace_bytes(1000)
+    assert ws >= 5 * 8 * 1000
+    assert lib.ss_eta_gradient(4, 1000, f, f, f, f, f, f, None, None, f, f, f, ws,
+                               None) == ss.SS_EUNSUPPORTED
+    assert lib.ss_eta_gradient(0, 0, f, f, f, f, f, f, None, None, f, f, f, ws,
+                               None) == ss.SS_EINVAL
+    assert lib.ss_eta_gradient(0, 1000, f, f, f, f, f, f, None, None, None, f, f, ws,
+                               None) == ss.SS_EINVAL
+    assert lib.ss_eta_gradient(1, 1000, f, f, f, f, f, f, None, None, f, f, f, ws,
+                               None) == ss.SS_EINVAL
+    assert lib.ss_eta_gradient(0, 1000, f, f, f, f, f, f, None, None, f, f, f, ws - 1,
+                               None) == ss.SS_EWORKSPACE
+    # cross-validation: sizes, Fine-Gray and valued designs unsupported
+    s = lib.ss_cv_stride(100_000)
+    assert s >= 100_000 and s % 16384 == 0
+    assert lib.ss_cv_stride(0) == 0
+    assert lib.ss_cv_prepare_workspace_bytes(100_000, 100) == 100 * s // 8
+    assert lib.ss_cv_prepare_workspace_bytes(100_000, 0) == 0
+    assert lib.ss_cv_workspace_bytes(100) > 100 * 1024
+    assert lib.ss_cv_workspace_bytes(0) == 0
+    prep = [f, f, f, f, f, f, None, f, f, f, f, f, f, big, None]
+    assert lib.ss_cv_prepare(1, 1000, 5, 10, *prep) == ss.SS_EUNSUPPORTED
+    valued = list(prep)
+    valued[6] = f
+    assert lib.ss_cv_prepare(0, 1000, 5, 10, *valued) == ss.SS_EUNSUPPORTED
+    assert lib.ss_cv_prepare(0, 1000, 5, 0, *prep) == ss.SS_EINVAL
+    short = list(prep)
+    short[-2] = 8
+    assert lib.ss_cv_prepare(0, 1000, 5, 10, *short) == ss.SS_EWORKSPACE
+    sw = [f] * 9 + [None, f, big, None]
+    assert lib.ss_cv_sweep(1, 0, 0.0, 1000, 5, 10, 0, 5, *sw) == ss.SS_EUNSUPPORTED
+    assert lib.ss_cv_sweep(0, 0, 0.0, 1000, 5, 10, 0, 6, *sw) == ss.SS_EINVAL
+    assert lib.ss_cv_sweep(0, 3, 0.0, 1000, 5, 10, 0, 5, *sw) == ss.SS_EINVAL
+    assert lib.ss_cv_sweep(0, 0, 0.0, 1000, 5, 70000, 0, 5, *sw) == ss.SS_EINVAL
+    small = sw[:-2] + [16, None]
+    assert lib.ss_cv_sweep(0, 0, 0.0, 1000, 5, 10, 0, 5, *small) == ss.SS_EWORKSPACE
+    assert lib.ss_cv_exp(1000, 0, f, f, f, None) == ss.SS_EINVAL
+    assert lib.ss_cv_loglik(1, 1000, 10, f, f, f, f, f, f, f, f, f, f,
+                            None) == ss.SS_EUNSUPPORTED
+    # FP32 path: unknown accumulation
+    assert lib.ss_grad_hess_mixed(0, 9, 10, 2, 0, f, f, f, None, None, f, f, None, f, f, f,
+                                  f, big, None) == ss.SS_EINVAL
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No CPU fallback: with the library absent every call raises."""
+    monkeypatch.setattr(ss, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(ss, "_lib", None)
+    with pytest.raises(ss.SurvScanError):
+        ss.load()
+    with pytest.raises(ss.SurvScanError):
+        ss.Problem("cox", [1.0, 2.0], [1, 0], [0, 1], [0], None, "cpu")
