@@ -802,8 +802,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
         SW_TRACE(a, b, j, 1);
         // ---- in-segment scan of the tuple of coordinate j
         double texcl[NT];
+        double run[NT];  // thread totals, also the A and D of j+1 that sum all e
         {
-            double run[NT];
 #pragma unroll
             for (int c = 0; c < NT; ++c) run[c] = 0.0;
 #pragma unroll
@@ -877,17 +877,21 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
                     v[1] += dd * (Gk - Gk * Gk);
                     if (a.want_log) v[2] += dd * log(S0);
                 }
-                // A (all positions) and D (rows of column j) for j+1
-                v[3] += ev[i];
+                // A (all positions) and D (rows of column j) for j+1 on
+                // the rows of column j+1; the sums over all positions are
+                // the thread totals of the scan (same terms, same order)
                 v[4] += xn ? ev[i] : 0.0;
-                v[3 + NT] += ex;
                 v[4 + NT] += xn ? ex : 0.0;
                 if (FG) {
-                    v[5] += ew;
                     v[6] += xn ? ew : 0.0;
-                    v[5 + NT] += ewx;
                     v[6 + NT] += xn ? ewx : 0.0;
                 }
+            }
+            v[3] = run[0];
+            v[3 + NT] = run[1];
+            if (FG) {
+                v[5] = run[2];
+                v[5 + NT] = run[3];
             }
         }
         publish(v, r, tag);
