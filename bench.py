@@ -16,6 +16,8 @@ One JSON line is printed.  Besides the throughput it carries
                 thread; cpu_baseline_all_cores: the same scan on every host
                 core, coordinates in parallel;
   context       our fused kernel at N = 1e5 next to the paper's GV100 time;
+  paper_sizes   the fused kernel at N = 1e5 ... 1e6 and the sweeps at
+                N = 1e5 (latency-bound sizes, not an HBM fraction);
   cv            10-fold x 10-repetition cross-validation (100 replicates) at
                 N = 1e5, P = 1000: one l1 sweep of every replicate in one
                 launch, next to one replicate-sized problem swept alone
@@ -146,6 +148,38 @@ def context(torch, ss, gen):
     return {"fused_us_n1e5_ours_back_to_back": round(us, 2),
             "fused_us_n1e5_paper_gv100": 5.2,
             "note": "paper Table 1, steps (2)-(4) fused, N=1e5, Uniform(1,2); other GPU"}
+
+
+def paper_sizes(torch, ss, gen):
+    """The paper's own sizes, latency-bound and cache-resident (not an HBM
+    fraction): the fused kernel on Uniform(1,2) tuples at N = 1e5 ... 1e6
+    (Table 1 workload), and the l1 sweeps of the Sec. 3.2 designs at
+    N = 1e5 (the headline covers N = 1e6)."""
+    fused = {}
+    for n in (100_000, 200_000, 500_000, 1_000_000):
+        u = gen.uniform_tuple_data(2, n)
+        prob = ss.Problem("cox", u["y"], u["status"], u["col_ptr"], u["rows"], u["vals"],
+                          "cuda:0")
+        prob.set_eta(u["eta"])
+        out = torch.empty(3, dtype=torch.float64, device="cuda:0")
+        for _ in range(5):
+            prob.grad_hess(0, out=out)
+        torch.cuda.synchronize()
+        fused[str(n)] = round(event_time_us(torch, lambda: prob.grad_hess(0, out=out), 100), 2)
+    sweeps = {}
+    gamma = math.sqrt(2.0)
+    for model in ("cox", "fg"):
+        d = gen.cox_data(0, 100_000, 1000, 0.05) if model == "cox" else \
+            gen.fg_data(0, 100_000, 1000, 0.05)
+        prob = ss.Problem(model, d["y"], d["status"], d["col_ptr"], d["rows"], None, "cuda:0")
+        prob.sweep("l1", gamma)
+        torch.cuda.synchronize()
+        us = event_time_us(torch, lambda: prob.sweep("l1", gamma), 5)
+        sweeps[model] = {"us_per_coordinate": round(us / d["p"], 3),
+                         "coords_per_s": round(d["p"] / (us * 1e-6), 1)}
+    return {"fused_us_uniform_tuple_by_n": fused,
+            "l1_sweep_n1e5_p1000": sweeps,
+            "note": "back-to-back launches timed with HIP events; latency-bound sizes"}
 
 
 def cross_validation(torch, ss, gen):
@@ -334,6 +368,9 @@ def main():
         line["roofline"] = roofline(torch, ss, gen, args.roof_n, args.roof_reps)
     if not args.no_context:
         line["context"] = context(torch, ss, gen)
+    if not args.no_context:
+        log("paper sizes: fused N=1e5..1e6, sweeps at N=1e5")
+        line["paper_sizes"] = paper_sizes(torch, ss, gen)
     if not args.no_cv:
         log("cross-validation: 100 replicates, N=1e5, P=1000")
         line["cv"] = cross_validation(torch, ss, gen)
