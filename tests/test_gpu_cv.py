@@ -285,3 +285,16 @@ def test_cv_many_steps_in_one_launch(halves, monkeypatch):
     d = cox_case(2500, 700, 14, density=0.05)
     train = gen.cv_folds(15, d["n"], 5, 1)[:2]
     check_sweeps(d, train, "none", 0.0, 2, 1e-9)
+
+
+@pytest.mark.parametrize("reps", [1, 150])
+def test_cv_replicate_counts(reps, monkeypatch):
+    """One replicate, and more replicates than fit two workgroups each on
+    the device at once (the launch then takes one workgroup per replicate
+    by itself); sampled replicates against the oracle."""
+    monkeypatch.delenv("SURVSCAN_CV_HALVES", raising=False)
+    d = cox_case(9000, 4, 16, density=0.1)
+    rng = np.random.default_rng(17)
+    train = (rng.random((reps, d["n"])) < 0.8).astype(np.uint8)
+    check_sweeps(d, train, "l1", 0.7, 2, 1e-9,
+                 reps_to_check=(0,) if reps == 1 else (0, 77, reps - 1))
