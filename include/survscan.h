@@ -151,7 +151,10 @@ int32_t ss_workspace_error(const void *ws, int32_t *flag, void *stream);
  *   Fine-Gray:  S_m,k = sum_{r <= k} e_r x_rj^m
  *                       + g_end_k * sum_{r after k's run} e_r x_rj^m w_comp_r
  * One fused pass: tuple scan with decoupled look-back, transform,
- * reduction; the last tile finishes the reduction (Fig. 3).
+ * reduction; the last tile finishes the reduction (Fig. 3).  The partial
+ * sums are added in a fixed order, but a tile's prefix combines whichever
+ * predecessor values the look-back finds visible first, so repeated calls
+ * can differ in the last bits (far inside the 1e-10 parity bound).
  * Inputs: e[n] in sorted order; the ss_prepare outputs; j in [0, p).
  * Output out[3] (device): g', g'', and sum_k d_k log S0_k. */
 int32_t ss_grad_hess(int32_t model, int64_t n, int64_t p, int64_t j,

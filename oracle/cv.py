@@ -117,3 +117,27 @@ def training_loglik(model, y, status, eta, train):
         return 0.0
     return loglik_eta(model, np.asarray(y)[tr], np.asarray(status)[tr],
                       np.asarray(eta)[tr])
+
+
+def path(model, y, status, col_ptr, rows, vals, train, penalty, gammas, sweeps):
+    """A replicate along a path of penalty strengths: CCD on the training
+    subjects, warm-started from the previous strength (beta, trust widths,
+    eta carried over), `sweeps` sweeps per strength; after each, the
+    held-out log-likelihood at the fitted beta.  Returns one value per
+    strength."""
+    ys, ss_, cp, rr, vv, idx = subset(y, status, col_ptr, rows, vals, train)
+    n = np.asarray(y).size
+    p = np.asarray(col_ptr).size - 1
+    beta = np.zeros(p)
+    delta = np.ones(p)
+    eta = np.zeros(ys.size)
+    out = []
+    for g in gammas:
+        beta, delta, eta, _ = ccd_sweeps(model, ys, ss_, cp, rr, vv, eta, penalty, g, sweeps,
+                                         beta, delta)
+        eta_all = np.zeros(n)
+        for j in range(p):
+            if beta[j] != 0.0:
+                eta_all += beta[j] * column(n, col_ptr, rows, vals, j)
+        out.append(heldout_loglik(model, y, status, eta_all, train))
+    return np.array(out)

@@ -379,6 +379,30 @@ class CrossValidation:
         return t.view(self.reps, self.stride)[:, :self.prob.n]
 
 
+def cv_path(prob, train, gammas, sweeps=5, penalty="l1"):
+    """k-fold cross-validation over a path of penalty strengths (Sec. 2.8).
+
+    Every replicate (a row of `train`, 1 = training subject) is fitted on
+    the GPU for each gamma in the given order, warm-started from the fit of
+    the previous one, with `sweeps` CCD sweeps per gamma (the stopping rule
+    is the caller's); after each gamma the held-out log partial likelihood
+    of every replicate is recorded.  Returns (scores, best): scores is a
+    [len(gammas), R] float64 array of held-out log-likelihoods and best the
+    gamma with the largest mean (reading: larger predictive likelihood is
+    better)."""
+    cvp = CrossValidation(prob, train)
+    rows = []
+    for g in gammas:
+        for _ in range(sweeps):
+            cvp.sweep(penalty, float(g))
+        rows.append(cvp.loglik()[:, 1].cpu())
+    if cvp.workspace_error():
+        raise SurvScanError("cross-validation: a bounded wait gave up")
+    scores = torch.stack(rows).numpy()
+    best = gammas[int(scores.mean(axis=1).argmax())]
+    return scores, best
+
+
 class LogLikEta(torch.autograd.Function):
     """l(eta) of a prepared problem as a differentiable function of the
     per-subject linear predictor (original order, float64 on the problem's

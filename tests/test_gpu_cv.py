@@ -298,3 +298,21 @@ def test_cv_replicate_counts(reps, monkeypatch):
     train = (rng.random((reps, d["n"])) < 0.8).astype(np.uint8)
     check_sweeps(d, train, "l1", 0.7, 2, 1e-9,
                  reps_to_check=(0,) if reps == 1 else (0, 77, reps - 1))
+
+
+def test_cv_path_matches_oracle():
+    """Sec. 2.8 over a path of l1 strengths with warm starts: the held-out
+    log-likelihood of every replicate at every strength, and the chosen
+    strength, against the oracle's path on the training subsets."""
+    d = cox_case(3000, 8, 18, density=0.2)
+    train = gen.cv_folds(19, d["n"], 5, 1)
+    gammas = [16.0, 8.0, 4.0, 2.0, 1.0]
+    prob = ss.Problem("cox", d["y"], d["status"], d["col_ptr"], d["rows"], None, DEV)
+    scores, best = ss.cv_path(prob, train, gammas, sweeps=3)
+    assert scores.shape == (len(gammas), train.shape[0])
+    want = np.stack([ocv.path("cox", d["y"], d["status"], d["col_ptr"], d["rows"], None,
+                              train[r], occd.PENALTY_L1, gammas, 3)
+                     for r in range(train.shape[0])], axis=1)
+    np.testing.assert_allclose(scores, want, rtol=1e-9, atol=1e-9)
+    assert best == gammas[int(want.mean(axis=1).argmax())]
+    assert len(set(np.round(scores.mean(axis=1), 6))) > 1   # the path moves
