@@ -1,0 +1,83 @@
+"""GPU: the fused kernel at the sizes that select its largest tiles
+(16 positions per thread, above 32M positions), including the N = 2^27
+workload the roofline measurement times.
+
+  * Just above the switch, the per-coordinate results against the oracle's
+    O(N) scan: Cox on the Uniform(1,2) tuple workload with a dense valued
+    column (the roofline workload at a smaller N), Fine-Gray on the
+    Sec. 3.2 design.
+  * At N = 2^27 itself (same generator and seed as the roofline
+    measurement), properties that hold at any size and tie the fused
+    kernel to a different algorithm: the full gradient in eta
+    (ss_eta_gradient, three device-wide scans) gives g' = x' dl/deta and
+    sum_d log S0 = sum_{events} eta - l.
+"""
+import numpy as np
+import pytest
+
+import gen
+from oracle import scan as oscan
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2204_08183_amd import survscan as ss  # noqa: E402
+
+DEV = "cuda:0"
+TOL = 1e-10
+
+
+def test_ipt16_cox_dense_valued_matches_oracle():
+    n = 40_000_000
+    u = gen.uniform_tuple_data(1, n)
+    prob = ss.Problem("cox", u["y"], u["status"], u["col_ptr"], u["rows"], u["vals"], DEV)
+    prob.set_eta(u["eta"])
+    got = prob.grad_hess(0).cpu().numpy()
+    pr = oscan.Prepared("cox", u["y"], u["status"])
+    x = np.zeros(n)
+    x[u["rows"]] = u["vals"]
+    want = pr.coordinate(u["eta"], x)
+    assert abs(got[0] - want["g1"]) <= TOL * want["scale_g1"], (got[0], want["g1"])
+    assert abs(got[1] - want["g2"]) <= TOL * want["scale_g2"], (got[1], want["g2"])
+    assert abs(got[2] - want["L"]) <= TOL * want["scale_L"], (got[2], want["L"])
+    assert prob.workspace_error() == 0
+
+
+def test_ipt16_fine_gray_matches_oracle():
+    n = 34_000_000
+    d = gen.fg_data(3, n, 1, 0.05)
+    eta = np.random.default_rng(5).normal(0.0, 0.5, n)
+    prob = ss.Problem("fg", d["y"], d["status"], d["col_ptr"], d["rows"], None, DEV)
+    prob.set_eta(eta)
+    got = prob.grad_hess(0).cpu().numpy()
+    pr = oscan.Prepared("fg", d["y"], d["status"])
+    x = gen.dense_column(n, d["col_ptr"], d["rows"], None, 0)
+    want = pr.coordinate(eta, x)
+    assert abs(got[0] - want["g1"]) <= TOL * want["scale_g1"], (got[0], want["g1"])
+    assert abs(got[1] - want["g2"]) <= TOL * want["scale_g2"], (got[1], want["g2"])
+    assert prob.workspace_error() == 0
+
+
+def test_roofline_size_against_the_gradient_in_eta():
+    n = 1 << 27
+    u = gen.uniform_tuple_data(1, n)
+    prob = ss.Problem("cox", u["y"], u["status"], u["col_ptr"], u["rows"], u["vals"], DEV)
+    prob.set_eta(u["eta"])
+    out = prob.grad_hess(0).cpu().numpy()
+    grad, ll = prob.eta_gradient()
+    grad = grad.cpu().numpy()
+    x = np.zeros(n)
+    x[u["rows"]] = u["vals"]
+    ev = u["status"] != 0
+    # g' = x' dl/deta; the scale is the sum of the absolute terms
+    g1 = float(np.dot(x, grad))
+    scale = float(np.sum(np.abs(x) * (np.abs(grad) + 1.0)))
+    assert abs(out[0] - g1) <= TOL * scale, (out[0], g1)
+    # sum_k d_k log S0_k = sum_{events} eta - l
+    sdl = float(np.sum(u["eta"][ev])) - float(ll.cpu()[0])
+    assert abs(out[2] - sdl) <= TOL * (abs(sdl) + float(np.sum(np.abs(u["eta"][ev])))), \
+        (out[2], sdl)
+    assert prob.workspace_error() == 0
