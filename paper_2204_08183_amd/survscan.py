@@ -291,6 +291,32 @@ class Problem:
                                         _stream(self.device)), "ss_workspace_error")
         return int(flag.value)
 
+    def objective(self, penalty="none", lam=0.0):
+        """l(beta) + pi(beta) at the current state (Sec. 2.3), with eta = X beta;
+        l from ss_loglik, the penalty of the P coefficients on the host."""
+        l = float(self.loglik().cpu()[0])
+        b = self.beta.cpu()
+        if penalty == "l1":
+            return l - lam * float(b.abs().sum())
+        if penalty == "l2":
+            return l - float((b * b).sum()) / (2.0 * lam)
+        return l
+
+    def fit(self, penalty="l1", lam=0.0, max_sweeps=100, tol=1e-10):
+        """Cyclic coordinate descent to convergence (Secs. 2.3-2.4, the
+        GPU-resident workflow of the Sec. 2.7 figure): whole sweeps on the
+        device until the relative change of the penalised log-likelihood,
+        |f - f_prev| / (|f| + 1), falls below `tol` (the stopping rule is
+        not fixed by the paper).  Returns the number of sweeps taken."""
+        f_prev = self.objective(penalty, lam)
+        for k in range(1, max_sweeps + 1):
+            self.sweep(penalty, lam)
+            f = self.objective(penalty, lam)
+            if abs(f - f_prev) / (abs(f) + 1.0) < tol:
+                return k
+            f_prev = f
+        return max_sweeps
+
 
 class CrossValidation:
     """R cross-validation replicates of a prepared Cox problem with a 0/1

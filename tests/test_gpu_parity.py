@@ -333,3 +333,33 @@ def test_sweep_deterministic_and_consistent(model, monkeypatch):
         assert prob.workspace_error() == 0
     for a_, b_ in zip(outs[0], outs[1]):
         np.testing.assert_array_equal(a_, b_)
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+@pytest.mark.parametrize("penalty,lam", [("l1", 4.0), ("l2", 0.5)])
+def test_fit_reaches_kkt(model, penalty, lam):
+    """Sweeps to convergence satisfy the optimality conditions of the
+    penalised objective: l1, |g'_j| <= gamma where beta_j = 0 and
+    g'_j = gamma sgn(beta_j) elsewhere; l2, g'_j = beta_j / tau.  The
+    coefficients also match the oracle's coordinate descent run for the
+    same number of sweeps."""
+    c = make_case(model, 6000, 8, 90, 0, 0.2)
+    c["eta"] = np.zeros(c["n"])
+    prob = gpu_problem(model, c)
+    sweeps = prob.fit(penalty, lam, max_sweeps=300, tol=1e-15)
+    assert sweeps < 300
+    beta = prob.beta.cpu().numpy()
+    pen = {"l1": occd.PENALTY_L1, "l2": occd.PENALTY_L2}[penalty]
+    b_or, _, _, _ = oracle_sweeps(model, c, pen, lam, sweeps)
+    np.testing.assert_allclose(beta, b_or, rtol=1e-7, atol=1e-10)
+    g = np.array([prob.grad_hess(j).cpu().numpy() for j in range(c["p"])])
+    g1, g2 = g[:, 0], g[:, 1]
+    # what is left of a Newton step at the optimum: at most 1e-6
+    if penalty == "l1":
+        assert np.any(beta == 0.0) and np.any(beta != 0.0)
+        zero = beta == 0.0
+        assert np.all(np.abs(g1[zero]) - lam <= 1e-6 * np.abs(g2[zero]))
+        assert np.all(np.abs(g1[~zero] - lam * np.sign(beta[~zero]))
+                      <= 1e-6 * np.abs(g2[~zero]))
+    else:
+        assert np.all(np.abs(g1 - beta / lam) <= 1e-6 * (np.abs(g2) + 1.0 / lam))
