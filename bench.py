@@ -18,6 +18,7 @@ One JSON line is printed.  Besides the throughput it carries
   context       our fused kernel at N = 1e5 next to the paper's GV100 time;
   paper_sizes   the fused kernel at N = 1e5 ... 1e6 and the sweeps at
                 N = 1e5 (latency-bound sizes, not an HBM fraction);
+  eta_gradient  the full gradient in eta at N = 1e6 and 2^27;
   cv            10-fold x 10-repetition cross-validation (100 replicates) at
                 N = 1e5, P = 1000: one l1 sweep of every replicate in one
                 launch, next to one replicate-sized problem swept alone
@@ -180,6 +181,30 @@ def paper_sizes(torch, ss, gen):
     return {"fused_us_uniform_tuple_by_n": fused,
             "l1_sweep_n1e5_p1000": sweeps,
             "note": "back-to-back launches timed with HIP events; latency-bound sizes"}
+
+
+def eta_gradient(torch, ss, gen):
+    """The full gradient in eta (ss_eta_gradient, Cox) on the Uniform(1,2)
+    tuple workload: time per call and algorithmic bandwidth, counting each
+    input read once and the output written once (perm 4, status 1, eta 8,
+    e 8, d 1, grad 8 = 30 bytes per subject)."""
+    res = {}
+    for n in (1_000_000, 1 << 27):
+        u = gen.uniform_tuple_data(1, n)
+        prob = ss.Problem("cox", u["y"], u["status"], u["col_ptr"], u["rows"], u["vals"],
+                          "cuda:0")
+        prob.set_eta(u["eta"])
+        del u
+        grad = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        ll = torch.empty(1, dtype=torch.float64, device="cuda:0")
+        prob.eta_gradient(grad, ll)
+        torch.cuda.synchronize()
+        us = event_time_us(torch, lambda: prob.eta_gradient(grad, ll), 10)
+        res[str(n)] = {"us": round(us, 1), "algo_gbs": round(30.0 * n / (us * 1e3), 1),
+                       "frac_of_hbm_peak": round(30.0 * n / (us * 1e3) / HBM_PEAK_GBS, 4)}
+        del prob, grad
+        torch.cuda.empty_cache()
+    return res
 
 
 def cross_validation(torch, ss, gen):
@@ -371,6 +396,9 @@ def main():
     if not args.no_context:
         log("paper sizes: fused N=1e5..1e6, sweeps at N=1e5")
         line["paper_sizes"] = paper_sizes(torch, ss, gen)
+    if not args.no_context:
+        log("gradient in eta: N=1e6 and 2^27")
+        line["eta_gradient"] = eta_gradient(torch, ss, gen)
     if not args.no_cv:
         log("cross-validation: 100 replicates, N=1e5, P=1000")
         line["cv"] = cross_validation(torch, ss, gen)

@@ -266,25 +266,33 @@ int32_t ss_grad_hess_mixed(int32_t model, int32_t acc, int64_t n, int64_t p,
  * gradient this is).  delta_m = 1 for an event of interest (Cox: status
  * != 0; Fine-Gray: status == 1).
  *
- * Arguments (device memory): perm, d8, d32, w_comp, g_end as ss_prepare
- * wrote them; status[n] int8 in ORIGINAL subject order (as given to
- * ss_prepare); eta[n] and e[n] = exp(eta) in SORTED order (as ss_gather /
- * ss_exp produce them; e is not recomputed from eta, so the pair must agree);
- * grad[n] is written in ORIGINAL subject order; *loglik one double.  The
+ * Arguments (device memory): inv_perm, d8, d32, w_comp, g_end as
+ * ss_prepare wrote them; status_sorted[n] int8 in SORTED order
+ * (status[perm[k]], as ss_gather_u8 produces it once per data set); eta[n]
+ * and e[n] = exp(eta) in SORTED order (as ss_gather / ss_exp produce them;
+ * e is not recomputed from eta, so the pair must agree); grad[n] is written
+ * in ORIGINAL subject order (gathered through inv_perm); *loglik one
+ * double.  The
  * workspace (any 256-byte-aligned device buffer of
  * ss_eta_gradient_workspace_bytes(n) bytes, caller-owned, no
- * initialisation) holds five N-vectors of partial results and the scan
- * carries; it is distinct from the ss_grad_hess workspace.  All sums are
- * taken in a fixed order: results are deterministic.  Errors: SS_EINVAL
- * for an unknown-size or null argument, SS_EUNSUPPORTED for an unknown
- * model, SS_EWORKSPACE for a short or misaligned workspace. */
+ * initialisation) holds four N-vectors of partial results, the block sums
+ * of l and the scan carries; it is distinct from the ss_grad_hess
+ * workspace.  All sums are taken in a fixed order: results are
+ * deterministic.  Errors: SS_EINVAL for an unknown-size or null argument,
+ * SS_EUNSUPPORTED for an unknown model, SS_EWORKSPACE for a short or
+ * misaligned workspace.
+ *
+ * ss_gather_u8: dst[k] = src[perm[k]] for k < n (bytes; e.g. the status
+ * vector into sorted order).  SS_EINVAL for a bad size or null pointer. */
 size_t ss_eta_gradient_workspace_bytes(int64_t n);
-int32_t ss_eta_gradient(int32_t model, int64_t n, const int32_t *perm,
-                        const int8_t *status, const double *eta,
+int32_t ss_eta_gradient(int32_t model, int64_t n, const int32_t *inv_perm,
+                        const int8_t *status_sorted, const double *eta,
                         const double *e, const uint8_t *d8,
                         const int32_t *d32, const double *w_comp,
                         const double *g_end, double *grad, double *loglik,
                         void *ws, size_t ws_bytes, void *stream);
+int32_t ss_gather_u8(int64_t n, const int32_t *perm, const uint8_t *src,
+                     uint8_t *dst, void *stream);
 
 /* ---------------------------------------------------------------------
  * Cross-validation replicates in one launch (Sec. 2.8; the single larger

@@ -336,17 +336,26 @@ size_t ss_eta_gradient_workspace_bytes(int64_t n)
     return adjoint_ws_bytes(n);
 }
 
-int32_t ss_eta_gradient(int32_t model, int64_t n, const int32_t *perm, const int8_t *status,
-                        const double *eta, const double *e, const uint8_t *d8,
-                        const int32_t *d32, const double *w_comp, const double *g_end,
-                        double *grad, double *loglik, void *ws, size_t ws_bytes, void *stream)
+int32_t ss_gather_u8(int64_t n, const int32_t *perm, const uint8_t *src, uint8_t *dst,
+                     void *stream)
 {
+    if (n < 1 || n > INT32_MAX || !perm || !src || !dst) return SS_EINVAL;
+    return launch_gather_u8(n, perm, src, dst, (hipStream_t)stream);
+}
+
+int32_t ss_eta_gradient(int32_t model, int64_t n, const int32_t *inv_perm,
+                        const int8_t *status_sorted, const double *eta, const double *e,
+                        const uint8_t *d8, const int32_t *d32, const double *w_comp,
+                        const double *g_end, double *grad, double *loglik, void *ws,
+                        size_t ws_bytes, void *stream)
+{
+    const int8_t *status = status_sorted;
     if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
     if (n < 1 || n > INT32_MAX) return SS_EINVAL;
-    if (!perm || !status || !eta || !e || !d8 || !d32 || !grad || !loglik) return SS_EINVAL;
+    if (!inv_perm || !status || !eta || !e || !d8 || !d32 || !grad || !loglik) return SS_EINVAL;
     if (model == SS_FINE_GRAY && (!w_comp || !g_end)) return SS_EINVAL;
     if (!ws || ((uintptr_t)ws & 255) || ws_bytes < adjoint_ws_bytes(n)) return SS_EWORKSPACE;
-    return launch_eta_gradient(model, n, perm, status, eta, e, d8, d32, w_comp, g_end, grad,
+    return launch_eta_gradient(model, n, inv_perm, status, eta, e, d8, d32, w_comp, g_end, grad,
                                loglik, ws, (hipStream_t)stream);
 }
 

@@ -226,7 +226,10 @@ int32_t scan_add_f64(const double *in, double *out, int64_t m, bool rev, bool ex
                      void *sums, hipStream_t s);
 size_t scan_sums_bytes(int64_t m);
 size_t adjoint_ws_bytes(int64_t n);
-int32_t launch_eta_gradient(int32_t model, int64_t n, const int32_t *perm, const int8_t *status,
+int32_t launch_gather_u8(int64_t n, const int32_t *perm, const uint8_t *src, uint8_t *dst,
+                         hipStream_t s);
+int32_t launch_eta_gradient(int32_t model, int64_t n, const int32_t *inv_perm,
+                            const int8_t *status_s,
                             const double *eta, const double *e, const uint8_t *d8,
                             const int32_t *d32, const double *w_comp, const double *g_end,
                             double *grad, double *loglik, void *ws, hipStream_t s);

@@ -74,6 +74,7 @@ SIGNATURES = {
                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_cv_loglik": (_i32, [_i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                             _vp, _vp]),
+    "ss_gather_u8": (_i32, [_i64, _vp, _vp, _vp, _vp]),
     "ss_eta_gradient_workspace_bytes": (_sz, [_i64]),
     "ss_eta_gradient": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                _vp, _sz, _vp]),
@@ -243,11 +244,15 @@ class Problem:
         lib = load()
         if getattr(self, "adj_ws", None) is None:
             self.adj_ws = Workspace(lib.ss_eta_gradient_workspace_bytes(self.n), self.device)
+            self.status_sorted = torch.empty(self.n, dtype=torch.int8, device=self.device)
+            check(lib.ss_gather_u8(self.n, _p(self.perm), _p(self.status),
+                                   _p(self.status_sorted), _stream(self.device)),
+                  "ss_gather_u8")
         grad = torch.empty(self.n, dtype=torch.float64, device=self.device) \
             if grad is None else grad
         loglik = torch.empty(1, dtype=torch.float64, device=self.device) \
             if loglik is None else loglik
-        rc = lib.ss_eta_gradient(self.model, self.n, _p(self.perm), _p(self.status),
+        rc = lib.ss_eta_gradient(self.model, self.n, _p(self.inv_perm), _p(self.status_sorted),
                                  _p(self.eta), _p(self.e), _p(self.d8), _p(self.d32),
                                  _p(self.w_comp), _p(self.g_end), _p(grad), _p(loglik),
                                  self.adj_ws.ptr, self.adj_ws.nbytes, _stream(self.device))
