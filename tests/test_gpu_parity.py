@@ -363,3 +363,22 @@ def test_fit_reaches_kkt(model, penalty, lam):
                       <= 1e-6 * np.abs(g2[~zero]))
     else:
         assert np.all(np.abs(g1 - beta / lam) <= 1e-6 * (np.abs(g2) + 1.0 / lam))
+
+
+@pytest.mark.parametrize("name", ["cox_hand", "cox_ties_hand", "fg_hand"])
+def test_hand_examples(name):
+    """The HIP path on the hand-derived examples of tests/golden."""
+    import golden
+    g = golden.load(name)
+    n = len(g["y"])
+    x = np.array(g["x"])
+    rows = np.nonzero(x)[0].astype(np.int32)
+    prob = ss.Problem(g["model"], g["y"], np.array(g["status"], np.int8),
+                      np.array([0, rows.size], np.int64), rows, None, DEV)
+    prob.set_eta(np.array(g["eta"]))
+    got = prob.grad_hess(0).cpu().numpy()
+    assert got[0] == pytest.approx(g["g1"], rel=1e-14, abs=1e-15)
+    assert got[1] == pytest.approx(g["g2"], rel=1e-14, abs=1e-15)
+    ll = float(prob.loglik().cpu()[0])
+    assert ll == pytest.approx(g["loglik"], rel=1e-14, abs=1e-15)
+    assert n == prob.n
