@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-cv", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--only", choices=["cv", "eta_gradient"],
+                    help="only run one of the secondary measurements (for profiling)")
     return ap.parse_args()
 
 
@@ -320,6 +322,12 @@ def main():
     ss.load()
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+    if args.only == "cv":
+        print(json.dumps({"cv": cross_validation(torch, ss, gen)}), flush=True)
+        return
+    if args.only == "eta_gradient":
+        print(json.dumps({"eta_gradient": eta_gradient(torch, ss, gen)}), flush=True)
         return
 
     log("generating Cox and Fine-Gray data N=%d P=%d density=%g" % (args.n, args.p,
