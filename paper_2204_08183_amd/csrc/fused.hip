@@ -76,10 +76,16 @@ __device__ __forceinline__ void publish_pairs(u32x4 *slot, const double (&v)[NC]
                                               uint64_t tag)
 {
     const int lane = lane_id();
+    // the components pass through an empty asm statement: a select chain
+    // over the array itself is folded into an indexed load, which puts the
+    // array in scratch memory
     double x = v[0];
 #pragma unroll
-    for (int c = 1; c < NC; ++c)
-        if (lane == c) x = v[c];
+    for (int c = 1; c < NC; ++c) {
+        double y = v[c];
+        asm volatile("" : "+v"(y));
+        x = lane == c ? y : x;
+    }
     if (lane < NC) st_pair(slot + lane, x, tag);
 }
 
