@@ -40,6 +40,12 @@ constexpr int kCvWaves = kCvBlock / kWave;
 constexpr int kCvAlign = 16384;  // per-replicate stride unit (a whole chunk)
 constexpr int kCvList = 512;     // non-zero steps held before eta is brought up to date
 constexpr int kCvGather = 16;    // column bitmask loads in flight while eta is updated
+#ifndef CV_SPLIT_NUM
+#define CV_SPLIT_NUM 12
+#define CV_SPLIT_DEN 25
+#endif
+constexpr int kCvSplitNum = CV_SPLIT_NUM;  // share of the chunks taken by half 0
+constexpr int kCvSplitDen = CV_SPLIT_DEN;
 
 __device__ __forceinline__ bool cv_event(int32_t model, int8_t s)
 {
@@ -350,11 +356,12 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
     double *e = a.e + off;
     const uint8_t *d8 = a.d8 + off;
     const int32_t *d32 = a.d32 + off;
-    const int nch = (int)(a.stride / CHUNK);
-    // half 0 also sums what half 1's next carry needs: it takes ~40% of
-    // the chunks (measured: 36.4 against 38.3 ms for an even split at
-    // N = 1e5, 100 replicates)
-    const int chm = (nch * 2 + 2) / 5;
+    // chunks that hold subjects (the stride's padding beyond n is skipped;
+    // its e stays 0)
+    const int nch = (int)min(a.stride / CHUNK, (a.n + CHUNK - 1) / CHUNK);
+    // half 0 also sums what half 1's next carry needs, so it takes fewer
+    // of the chunks: kCvSplitNum / kCvSplitDen of them, rounded
+    const int chm = (nch * kCvSplitNum + kCvSplitDen / 2) / kCvSplitDen;
     const int ch_lo = (KH == 2 && h == 1) ? chm : 0;
     const int ch_hi = (KH == 2 && h == 0) ? chm : nch;
     const int64_t tpos = (int64_t)tid * IPT;

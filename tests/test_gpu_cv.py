@@ -158,8 +158,10 @@ def test_cv_sweeps_match_oracle(penalty, lam, halves, monkeypatch):
 
 
 @pytest.mark.parametrize("halves", HALVES)
+# chunks of 8192 positions, strides of 16384: 16384 fills its stride,
+# 16385 and 50001 leave a chunk of pure padding that the sweep skips
 @pytest.mark.parametrize("n,p,ties", [(1, 2, 0), (3, 2, 0), (8193, 4, 0), (50001, 5, 40),
-                                      (24577, 3, 0)])
+                                      (24577, 3, 0), (16384, 3, 0), (16385, 3, 5)])
 def test_cv_sizes_and_ties(n, p, ties, halves, monkeypatch):
     _halves(monkeypatch, halves)
     d = cox_case(n, p, 7, ties=ties, density=0.3 if n < 10 else 0.1)
