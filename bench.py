@@ -293,6 +293,20 @@ def cpu_baseline_all_cores(gen, cox, coords_per_thread=60):
                       % (total, cox["n"], cox["p"], threads, dt)}
 
 
+def host_cpu():
+    """The host the CPU baselines ran on: its CPU model and os.cpu_count()."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count()}
+
+
 def copy_calibration(torch):
     a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
     b = torch.empty_like(a)
@@ -415,6 +429,9 @@ def main():
         line["cpu_baseline"] = cpu_baseline(gen, cox, fg, args.cpu_coords)
         log("cpu baseline (oracle) on all host cores")
         line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(gen, cox)
+        host = host_cpu()
+        line["cpu_baseline"].update(host)
+        line["cpu_baseline_all_cores"].update(host)
     print(json.dumps(line), flush=True)
 
 
