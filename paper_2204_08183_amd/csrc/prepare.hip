@@ -77,17 +77,81 @@ __device__ __forceinline__ int64_t phys(int64_t i, int64_t m)
     return REV ? m - 1 - i : i;
 }
 
+// A thread's SI items are consecutive in memory (descending addresses when
+// REV): a whole, 16-byte aligned run moves as 16-byte vectors, anything
+// else item by item.
+template <typename T, bool REV>
+__device__ __forceinline__ const T *item_run(const T *p, int64_t base, int64_t m)
+{
+    if (base + SI > m) return nullptr;
+    const T *r = p + (REV ? m - base - SI : base);
+    return ((uintptr_t)r & 15u) == 0 ? r : nullptr;
+}
+
+template <typename T, typename Op, bool REV>
+__device__ __forceinline__ void load_items(const T *in, int64_t base, int64_t m, T (&it)[SI])
+{
+    static_assert((SI * sizeof(T)) % 16 == 0, "a run of items is whole 16-byte vectors");
+    constexpr int PV = 16 / sizeof(T);  // items per vector
+    if (const T *r = item_run<T, REV>(in, base, m)) {
+        const uint4 *v = reinterpret_cast<const uint4 *>(r);
+#pragma unroll
+        for (int q = 0; q < SI / PV; ++q) {
+            union {
+                uint4 u;
+                T t[PV];
+            } x;
+            x.u = v[q];
+#pragma unroll
+            for (int k = 0; k < PV; ++k) {
+                const int i = q * PV + k;  // memory order
+                it[REV ? SI - 1 - i : i] = x.t[k];
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < SI; ++i) {
+        const int64_t l = base + i;
+        it[i] = l < m ? in[phys<T, REV>(l, m)] : Op::id();
+    }
+}
+
+template <typename T, bool REV>
+__device__ __forceinline__ void store_items(T *out, int64_t base, int64_t m, const T (&it)[SI])
+{
+    constexpr int PV = 16 / sizeof(T);
+    if (T *r = const_cast<T *>(item_run<T, REV>(out, base, m))) {
+        uint4 *v = reinterpret_cast<uint4 *>(r);
+#pragma unroll
+        for (int q = 0; q < SI / PV; ++q) {
+            union {
+                uint4 u;
+                T t[PV];
+            } x;
+#pragma unroll
+            for (int k = 0; k < PV; ++k) {
+                const int i = q * PV + k;
+                x.t[k] = it[REV ? SI - 1 - i : i];
+            }
+            v[q] = x.u;
+        }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < SI; ++i) {
+        const int64_t l = base + i;
+        if (l < m) out[phys<T, REV>(l, m)] = it[i];
+    }
+}
+
 template <typename T, typename Op, bool REV>
 __global__ __launch_bounds__(SB) void k_scan_reduce(const T *in, int64_t m, T *sums)
 {
     __shared__ T s_w[SB / kWave];
     T it[SI];
     const int64_t base = (int64_t)blockIdx.x * ST + (int64_t)threadIdx.x * SI;
-#pragma unroll
-    for (int i = 0; i < SI; ++i) {
-        const int64_t l = base + i;
-        it[i] = l < m ? in[phys<T, REV>(l, m)] : Op::id();
-    }
+    load_items<T, Op, REV>(in, base, m, it);
     T tot = block_scan<T, Op>(it, Op::id(), s_w);
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
@@ -139,20 +203,12 @@ __global__ __launch_bounds__(SB) void k_scan_down(const T *in, T *out, int64_t m
     __shared__ T s_last[SB / kWave];
     T it[SI];
     const int64_t base = (int64_t)blockIdx.x * ST + (int64_t)threadIdx.x * SI;
-#pragma unroll
-    for (int i = 0; i < SI; ++i) {
-        const int64_t l = base + i;
-        it[i] = l < m ? in[phys<T, REV>(l, m)] : Op::id();
-    }
+    load_items<T, Op, REV>(in, base, m, it);
     const T carry = sums[blockIdx.x];
     block_scan<T, Op>(it, carry, s_w);
     if (EXCL) inclusive_to_exclusive<T>(it, carry, s_last);
     __syncthreads();  // `in` and `out` may alias: every read is done
-#pragma unroll
-    for (int i = 0; i < SI; ++i) {
-        const int64_t l = base + i;
-        if (l < m) out[phys<T, REV>(l, m)] = it[i];
-    }
+    store_items<T, REV>(out, base, m, it);
 }
 
 // ------------------------------------------------------------ radix sort
