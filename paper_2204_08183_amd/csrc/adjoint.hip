@@ -11,11 +11,14 @@
 //
 // with w = I(status = 2) / G(y) the competing-event weight.  Scans (prefix
 // of e, suffix of d/S0, and for Fine-Gray the prefix of e w and of d G/S0)
-// around element-wise passes in sorted order; the gradient reaches subject
-// order by one gather through the inverse permutation.  l is a sum of fixed-grid block
-// partials; every sum is taken in a fixed order.
+// in sorted order, the run-end terms computed in the last pass of the scan
+// of e and the gradient in the last pass of the suffix scan of d/S0; the
+// gradient reaches subject order by one gather through the inverse
+// permutation.  l is a sum of per-tile partials; every sum is taken in a
+// fixed order.
 #include <math.h>
 
+#include "scan_device.h"
 #include "ss_internal.h"
 
 namespace ss {
@@ -34,66 +37,132 @@ __global__ __launch_bounds__(256) void k_adj_mul(int64_t n, const double *a, con
         out[k] = a[k] * b[k];
 }
 
-// At run ends: q = d / S0, q2 = d G / S0 (Fine-Gray); the likelihood terms
-// delta eta - d log S0 summed per block (fixed grid, fixed order) into
-// lpart[blockIdx].
-constexpr int kAdjGrid = 2048;
+constexpr int kAdjGrid = 2048;  // workgroups of the element-wise passes
 
-__global__ __launch_bounds__(256) void k_adj_terms(int32_t model, int64_t n,
-                                                   const int8_t *status_s, const double *eta,
-                                                   const uint8_t *d8, const int32_t *d32,
-                                                   const double *g_end, const double *p0,
-                                                   const double *pw, double *q, double *q2,
-                                                   double *lpart)
+// Eight consecutive bytes of a thread's scan items (memory order).
+__device__ __forceinline__ void load_bytes8(const uint8_t *p, int64_t k0, int64_t n,
+                                            uint8_t (&b)[SI])
 {
-    __shared__ double s_red[4];
-    const bool fg = model == SS_FINE_GRAY;
-    const double tot_w = fg ? pw[n - 1] : 0.0;
-    double lsum = 0.0;
-    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
-        int d = d8[k];
-        if (d == 255) d = d32[k];
-        double l = is_event(model, status_s[k]) ? eta[k] : 0.0;
-        double qk = 0.0, q2k = 0.0;
-        if (d != 0) {
-            double s0 = p0[k];
-            if (fg) s0 += g_end[k] * (tot_w - pw[k]);
-            qk = (double)d / s0;
-            if (fg) q2k = (double)d * g_end[k] / s0;
-            l -= (double)d * log(s0);
+    if (k0 + SI <= n && ((uintptr_t)(p + k0) & 7u) == 0) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(p + k0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            b[i] = (uint8_t)(v.x >> (8 * i));
+            b[4 + i] = (uint8_t)(v.y >> (8 * i));
         }
-        q[k] = qk;
-        if (fg) q2[k] = q2k;
-        lsum += l;
+        return;
     }
-    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_down(lsum, o);
-    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = lsum;
-    __syncthreads();
-    if (threadIdx.x == 0) lpart[blockIdx.x] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+#pragma unroll
+    for (int i = 0; i < SI; ++i) b[i] = k0 + i < n ? p[k0 + i] : 0;
 }
 
-// dl/deta in sorted order (coalesced); block 0 adds the likelihood
-// partials in order.
-__global__ __launch_bounds__(256) void k_adj_grad(int32_t model, int64_t n,
-                                                  const int8_t *status_s, const double *e,
-                                                  const double *w_comp, const double *r,
-                                                  const double *q2x, const double *lpart,
-                                                  int nlpart, double *grad_s, double *loglik)
+// Fixed-order sum of one value per thread of the workgroup; thread 0 gets it.
+__device__ __forceinline__ double block_total(double v, double *s_red)
 {
-    const bool fg = model == SS_FINE_GRAY;
-    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
-        double inner = r[k];
-        if (fg) inner += w_comp[k] * q2x[k];
-        grad_s[k] = (is_event(model, status_s[k]) ? 1.0 : 0.0) - e[k] * inner;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+}
+
+// Last pass of the prefix scan of e, with the run-end terms: S0 at k is the
+// prefix (Fine-Gray: plus G(Y_k) times the e w after k, from pw), q = d/S0,
+// q2 = d G/S0, and the tile's sum of delta eta - d log S0 into lpart[tile].
+template <bool FG>
+__global__ __launch_bounds__(SB) void k_adj_scan_terms(int64_t n, const double *e,
+                                                       const double *carry,
+                                                       const int8_t *status_s,
+                                                       const double *eta, const uint8_t *d8,
+                                                       const int32_t *d32, const double *g_end,
+                                                       const double *pw, double *q,
+                                                       double *q2, double *lpart)
+{
+    static_assert(SB == 4 * kWave, "block_total sums four waves");
+    __shared__ double s_w[SB / kWave];
+    __shared__ double s_red[SB / kWave];
+    const int64_t k0 = (int64_t)blockIdx.x * ST + (int64_t)threadIdx.x * SI;
+    double s0[SI], et[SI];
+    load_items<double, OpAdd<double>, false>(e, k0, n, s0);
+    block_scan<double, OpAdd<double>>(s0, carry[blockIdx.x], s_w);
+    load_items<double, OpAdd<double>, false>(eta, k0, n, et);
+    uint8_t dd[SI], st[SI];
+    load_bytes8(d8, k0, n, dd);
+    load_bytes8(reinterpret_cast<const uint8_t *>(status_s), k0, n, st);
+    const double tot_w = FG ? pw[n - 1] : 0.0;
+    double qv[SI], q2v[SI];
+    double lsum = 0.0;
+#pragma unroll
+    for (int i = 0; i < SI; ++i) {
+        const int64_t k = k0 + i;
+        qv[i] = 0.0;
+        q2v[i] = 0.0;
+        if (k < n) {
+            int d = dd[i];
+            if (d == 255) d = d32[k];
+            double l = is_event(FG ? SS_FINE_GRAY : SS_COX, (int8_t)st[i]) ? et[i] : 0.0;
+            if (d != 0) {
+                double S0 = s0[i];
+                double g = 0.0;
+                if (FG) {
+                    g = g_end[k];
+                    S0 += g * (tot_w - pw[k]);
+                }
+                qv[i] = (double)d / S0;
+                if (FG) q2v[i] = (double)d * g / S0;
+                l -= (double)d * log(S0);
+            }
+            lsum += l;
+        }
     }
+    store_items<double, false>(q, k0, n, qv);
+    if (FG) store_items<double, false>(q2, k0, n, q2v);
+    const double t = block_total(lsum, s_red);
+    if (threadIdx.x == 0) lpart[blockIdx.x] = t;
+}
+
+// Last pass of the suffix scan of q = d/S0: R at k is the suffix, and
+// dl/deta_k = delta_k - e_k (R + w_k Q_k) (Q: the exclusive prefix of
+// q2, Fine-Gray) goes to grad_s in sorted order.  Workgroup 0 also adds
+// the likelihood partials in order.
+template <bool FG>
+__global__ __launch_bounds__(SB) void k_adj_scan_grad(int64_t n, const double *q,
+                                                      const double *carry,
+                                                      const int8_t *status_s, const double *e,
+                                                      const double *w_comp, const double *q2x,
+                                                      const double *lpart, int64_t nlpart,
+                                                      double *grad_s, double *loglik)
+{
+    __shared__ double s_w[SB / kWave];
+    __shared__ double s_red[SB / kWave];
+    // scan position l holds sorted position n - 1 - l; a thread's items are
+    // the descending run of sorted positions n - 1 - l0 .. n - SI - l0
+    const int64_t l0 = (int64_t)blockIdx.x * ST + (int64_t)threadIdx.x * SI;
+    double r[SI], ev[SI], wq[SI];
+    load_items<double, OpAdd<double>, true>(q, l0, n, r);
+    block_scan<double, OpAdd<double>>(r, carry[blockIdx.x], s_w);
+    load_items<double, OpAdd<double>, true>(e, l0, n, ev);
+    if (FG) {
+        double wv[SI], qx[SI];
+        load_items<double, OpAdd<double>, true>(w_comp, l0, n, wv);
+        load_items<double, OpAdd<double>, true>(q2x, l0, n, qx);
+#pragma unroll
+        for (int i = 0; i < SI; ++i) wq[i] = wv[i] * qx[i];
+    }
+    double gv[SI];
+#pragma unroll
+    for (int i = 0; i < SI; ++i) {
+        const int64_t l = l0 + i;
+        double inner = r[i];
+        if (FG) inner += wq[i];
+        const bool ev_k = l < n && is_event(FG ? SS_FINE_GRAY : SS_COX, status_s[n - 1 - l]);
+        gv[i] = (ev_k ? 1.0 : 0.0) - ev[i] * inner;
+    }
+    store_items<double, true>(grad_s, l0, n, gv);
     if (blockIdx.x == 0) {
-        __shared__ double s_red[4];
-        double l = 0.0;
-        for (int b = threadIdx.x; b < nlpart; b += 256) l += lpart[b];
-        for (int o = 32; o > 0; o >>= 1) l += __shfl_down(l, o);
-        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = l;
-        __syncthreads();
-        if (threadIdx.x == 0) *loglik = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+        double v = 0.0;
+        for (int64_t b = threadIdx.x; b < nlpart; b += SB) v += lpart[b];
+        const double t = block_total(v, s_red);
+        if (threadIdx.x == 0) *loglik = t;
     }
 }
 
@@ -125,7 +194,7 @@ size_t adj_layout(int64_t n, void *ws, AdjWs *w)
     t.b = (double *)take(8 * (size_t)n);
     t.q = (double *)take(8 * (size_t)n);
     t.q2 = (double *)take(8 * (size_t)n);
-    t.lpart = (double *)take(8 * (size_t)kAdjGrid);
+    t.lpart = (double *)take(8 * (size_t)ceil_div(n, ST));
     t.sums = take(scan_sums_bytes(n));
     if (w) *w = t;
     return off;
@@ -162,27 +231,40 @@ int32_t launch_eta_gradient(int32_t model, int64_t n, const int32_t *inv_perm,
     adj_layout(n, ws, &w);
     const bool fg = model == SS_FINE_GRAY;
     const int grid = grid_of(n);
-    int32_t rc = scan_add_f64(e, w.a, n, false, false, w.sums, s);  // prefix of e
-    if (rc) return rc;
+    const unsigned tiles = (unsigned)ceil_div(n, ST);
+    const double *carry = reinterpret_cast<const double *>(w.sums);
+    int32_t rc;
     if (fg) {
         hipLaunchKernelGGL(k_adj_mul, dim3(grid), dim3(256), 0, s, n, e, w_comp, w.b);
         SS_LAUNCH_CHECK();
         rc = scan_add_f64(w.b, w.b, n, false, false, w.sums, s);      // prefix of e w
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_adj_terms, dim3(grid), dim3(256), 0, s, model, n, status_s, eta, d8,
-                       d32, g_end, w.a, w.b, w.q, w.q2, w.lpart);
+    rc = scan_carries_f64(e, n, false, w.sums, s);                    // prefix of e, then
+    if (rc) return rc;                                                 // the run-end terms
+    if (fg) {
+        hipLaunchKernelGGL(k_adj_scan_terms<true>, dim3(tiles), dim3(SB), 0, s, n, e, carry,
+                           status_s, eta, d8, d32, g_end, w.b, w.q, w.q2, w.lpart);
+    } else {
+        hipLaunchKernelGGL(k_adj_scan_terms<false>, dim3(tiles), dim3(SB), 0, s, n, e, carry,
+                           status_s, eta, d8, d32, g_end, w.b, w.q, w.q2, w.lpart);
+    }
     SS_LAUNCH_CHECK();
-    rc = scan_add_f64(w.q, w.a, n, true, false, w.sums, s);           // suffix of d / S0
-    if (rc) return rc;
     if (fg) {
         rc = scan_add_f64(w.q2, w.b, n, false, true, w.sums, s);      // run ends before k
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_adj_grad, dim3(grid), dim3(256), 0, s, model, n, status_s, e, w_comp,
-                       w.a, w.b, w.lpart, grid, w.q, loglik);
+    rc = scan_carries_f64(w.q, n, true, w.sums, s);                   // suffix of d / S0,
+    if (rc) return rc;                                                 // then the gradient
+    if (fg) {
+        hipLaunchKernelGGL(k_adj_scan_grad<true>, dim3(tiles), dim3(SB), 0, s, n, w.q, carry,
+                           status_s, e, w_comp, w.b, w.lpart, (int64_t)tiles, w.a, loglik);
+    } else {
+        hipLaunchKernelGGL(k_adj_scan_grad<false>, dim3(tiles), dim3(SB), 0, s, n, w.q, carry,
+                           status_s, e, w_comp, w.b, w.lpart, (int64_t)tiles, w.a, loglik);
+    }
     SS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_adj_to_subjects, dim3(grid), dim3(256), 0, s, n, inv_perm, w.q, grad);
+    hipLaunchKernelGGL(k_adj_to_subjects, dim3(grid), dim3(256), 0, s, n, inv_perm, w.a, grad);
     SS_LAUNCH_CHECK();
     return SS_OK;
 }

@@ -12,6 +12,7 @@
 // identical from run to run.
 #include <vector>
 
+#include "scan_device.h"
 #include "ss_internal.h"
 
 namespace ss {
@@ -19,131 +20,7 @@ namespace ss {
 namespace {
 
 // ------------------------------------------------------------ generic scan
-template <typename T>
-struct OpAdd {
-    __device__ static T id() { return T(0); }
-    __device__ static T op(T a, T b) { return a + b; }
-};
-template <typename T>
-struct OpMul {
-    __device__ static T id() { return T(1); }
-    __device__ static T op(T a, T b) { return a * b; }
-};
-
-constexpr int SB = 256;          // scan block
-constexpr int SI = 8;            // items per thread
-constexpr int ST = SB * SI;      // items per scan tile
-
-// Block-wide inclusive scan of SI items per thread (blocked arrangement)
-// with a carry-in; returns the block total (carry excluded) to all threads.
-template <typename T, typename Op>
-__device__ T block_scan(T (&it)[SI], T carry, T *s_w)
-{
-    constexpr int NW = SB / kWave;
-    const int lane = lane_id();
-    const int w = threadIdx.x / kWave;
-    T run = Op::id();
-#pragma unroll
-    for (int i = 0; i < SI; ++i) {
-        run = Op::op(run, it[i]);
-        it[i] = run;
-    }
-    T inc = run;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        T y = __shfl_up(inc, off, kWave);
-        if (lane >= off) inc = Op::op(y, inc);
-    }
-    if (lane == kWave - 1) s_w[w] = inc;
-    __syncthreads();
-    T before = Op::id(), total = Op::id();
-    for (int q = 0; q < NW; ++q) {
-        if (q < w) before = Op::op(before, s_w[q]);
-        total = Op::op(total, s_w[q]);
-    }
-    __syncthreads();
-    // exclusive prefix of this thread = carry (+) wave prefix (+) lanes before
-    T lanes_before = __shfl_up(inc, 1, kWave);
-    T pre = Op::op(carry, before);
-    if (lane > 0) pre = Op::op(pre, lanes_before);
-#pragma unroll
-    for (int i = 0; i < SI; ++i) it[i] = Op::op(pre, it[i]);
-    return total;
-}
-
-template <typename T, bool REV>
-__device__ __forceinline__ int64_t phys(int64_t i, int64_t m)
-{
-    return REV ? m - 1 - i : i;
-}
-
-// A thread's SI items are consecutive in memory (descending addresses when
-// REV): a whole, 16-byte aligned run moves as 16-byte vectors, anything
-// else item by item.
-template <typename T, bool REV>
-__device__ __forceinline__ const T *item_run(const T *p, int64_t base, int64_t m)
-{
-    if (base + SI > m) return nullptr;
-    const T *r = p + (REV ? m - base - SI : base);
-    return ((uintptr_t)r & 15u) == 0 ? r : nullptr;
-}
-
-template <typename T, typename Op, bool REV>
-__device__ __forceinline__ void load_items(const T *in, int64_t base, int64_t m, T (&it)[SI])
-{
-    static_assert((SI * sizeof(T)) % 16 == 0, "a run of items is whole 16-byte vectors");
-    constexpr int PV = 16 / sizeof(T);  // items per vector
-    if (const T *r = item_run<T, REV>(in, base, m)) {
-        const uint4 *v = reinterpret_cast<const uint4 *>(r);
-#pragma unroll
-        for (int q = 0; q < SI / PV; ++q) {
-            union {
-                uint4 u;
-                T t[PV];
-            } x;
-            x.u = v[q];
-#pragma unroll
-            for (int k = 0; k < PV; ++k) {
-                const int i = q * PV + k;  // memory order
-                it[REV ? SI - 1 - i : i] = x.t[k];
-            }
-        }
-        return;
-    }
-#pragma unroll
-    for (int i = 0; i < SI; ++i) {
-        const int64_t l = base + i;
-        it[i] = l < m ? in[phys<T, REV>(l, m)] : Op::id();
-    }
-}
-
-template <typename T, bool REV>
-__device__ __forceinline__ void store_items(T *out, int64_t base, int64_t m, const T (&it)[SI])
-{
-    constexpr int PV = 16 / sizeof(T);
-    if (T *r = const_cast<T *>(item_run<T, REV>(out, base, m))) {
-        uint4 *v = reinterpret_cast<uint4 *>(r);
-#pragma unroll
-        for (int q = 0; q < SI / PV; ++q) {
-            union {
-                uint4 u;
-                T t[PV];
-            } x;
-#pragma unroll
-            for (int k = 0; k < PV; ++k) {
-                const int i = q * PV + k;
-                x.t[k] = it[REV ? SI - 1 - i : i];
-            }
-            v[q] = x.u;
-        }
-        return;
-    }
-#pragma unroll
-    for (int i = 0; i < SI; ++i) {
-        const int64_t l = base + i;
-        if (l < m) out[phys<T, REV>(l, m)] = it[i];
-    }
-}
+// (block-level pieces in scan_device.h)
 
 template <typename T, typename Op, bool REV>
 __global__ __launch_bounds__(SB) void k_scan_reduce(const T *in, int64_t m, T *sums)
@@ -154,24 +31,6 @@ __global__ __launch_bounds__(SB) void k_scan_reduce(const T *in, int64_t m, T *s
     load_items<T, Op, REV>(in, base, m, it);
     T tot = block_scan<T, Op>(it, Op::id(), s_w);
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
-}
-
-// Turns the inclusive values left by block_scan into exclusive ones: the
-// exclusive value of an item is the inclusive value of the item before it,
-// and the block's first item gets `carry`.
-template <typename T>
-__device__ void inclusive_to_exclusive(T (&it)[SI], T carry, T *s_last)
-{
-    const int lane = lane_id();
-    const int w = threadIdx.x / kWave;
-    const T prev = __shfl_up(it[SI - 1], 1, kWave);
-    if (lane == kWave - 1) s_last[w] = it[SI - 1];
-    __syncthreads();
-    const T first = lane > 0 ? prev : (w > 0 ? s_last[w - 1] : carry);
-    __syncthreads();
-#pragma unroll
-    for (int i = SI - 1; i > 0; --i) it[i] = it[i - 1];
-    it[0] = first;
 }
 
 // Single workgroup: exclusive scan of sums[0..nb) in place.
@@ -764,5 +623,22 @@ int32_t scan_add_f64(const double *in, double *out, int64_t m, bool rev, bool ex
 }
 
 size_t scan_sums_bytes(int64_t m) { return 8 * (size_t)ceil_div(m, ST); }
+
+int32_t scan_carries_f64(const double *in, int64_t m, bool rev, void *sums, hipStream_t s)
+{
+    if (m <= 0) return SS_OK;
+    double *w = reinterpret_cast<double *>(sums);
+    const int64_t nb = ceil_div(m, ST);
+    if (rev)
+        hipLaunchKernelGGL((k_scan_reduce<double, OpAdd<double>, true>), dim3((unsigned)nb),
+                           dim3(SB), 0, s, in, m, w);
+    else
+        hipLaunchKernelGGL((k_scan_reduce<double, OpAdd<double>, false>), dim3((unsigned)nb),
+                           dim3(SB), 0, s, in, m, w);
+    SS_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_scan_spine<double, OpAdd<double>>), dim3(1), dim3(SB), 0, s, w, nb);
+    SS_LAUNCH_CHECK();
+    return SS_OK;
+}
 
 }  // namespace ss

@@ -225,6 +225,10 @@ int32_t launch_ccd_scalar(int32_t penalty, double lambda, int32_t j,
 int32_t scan_add_f64(const double *in, double *out, int64_t m, bool rev, bool excl,
                      void *sums, hipStream_t s);
 size_t scan_sums_bytes(int64_t m);
+// The first two passes of scan_add_f64 alone: sums[t] = the exclusive carry
+// of scan tile t (tiles of 2048 items, in scan order), for a kernel that
+// finishes the scan itself.
+int32_t scan_carries_f64(const double *in, int64_t m, bool rev, void *sums, hipStream_t s);
 size_t adjoint_ws_bytes(int64_t n);
 int32_t launch_gather_u8(int64_t n, const int32_t *perm, const uint8_t *src, uint8_t *dst,
                          hipStream_t s);
