@@ -586,6 +586,20 @@ __device__ __forceinline__ void ld_lb<2, 6>(const u32x4 *const (&p)[2],
 }
 
 template <>
+__device__ __forceinline__ void ld_lb<1, 3>(const u32x4 *const (&p)[1],
+                                               u32x4 (&r)[1][3])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %3, off sc1\n\t"
+                 "global_load_dwordx4 %1, %3, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %3, off offset:32 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0][0]), "=&v"(r[0][1]), "=&v"(r[0][2])
+                 : "v"(p[0])
+                 : "memory");
+}
+
+template <>
 __device__ __forceinline__ void ld_lb<1, 6>(const u32x4 *const (&p)[1],
                                                u32x4 (&r)[1][6])
 {
