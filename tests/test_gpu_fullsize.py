@@ -1,8 +1,8 @@
-"""GPU: the fused kernel at the sizes that select its largest tiles
-(16 positions per thread, above 32M positions), including the N = 2^27
+"""GPU: the fused kernel well inside the range of its largest tiles
+(16 positions per thread, above 1.5M positions), including the N = 2^27
 workload the roofline measurement times.
 
-  * Just above the switch, the per-coordinate results against the oracle's
+  * At 34M-40M positions, the per-coordinate results against the oracle's
     O(N) scan: Cox on the Uniform(1,2) tuple workload with a dense valued
     column (the roofline workload at a smaller N), Fine-Gray on the
     Sec. 3.2 design.
