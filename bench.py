@@ -112,7 +112,7 @@ def roofline(torch, ss, gen, n, reps):
             traffic = t.get("bytes_per_launch")
     err = prob.workspace_error()
     copy_gbs = copy_peak_gbs(torch)
-    ipt = 4 if n <= 4 << 20 else 8 if n <= 32 << 20 else 16  # tile shape the library picks
+    ipt = 8 if n <= 3 << 19 else 16  # tile shape the library picks
     del prob
     torch.cuda.empty_cache()
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

@@ -8,8 +8,8 @@
  * Cox log partial likelihood become prefix sums and the Fine-Gray ones a
  * prefix plus a weighted suffix sum (Sec. 2.7, eqs. cox_g, cox_h, fg_g,
  * fg_h); one coordinate's g' and g'' are a scan, an element-wise transform
- * and a reduction, fused into one pass over the data (Sec. 2.7, Fig. 3),
- * inside cyclic coordinate descent (Sec. 2.4, Fig. 4).
+ * and a reduction, fused into one pass over the data (Sec. 2.7, Fig. 2),
+ * inside cyclic coordinate descent (Sec. 2.4, Fig. 3).
  *
  * Conventions for every entry point
  *  - All array pointers are DEVICE pointers (hipMalloc'd or torch CUDA
@@ -151,7 +151,7 @@ int32_t ss_workspace_error(const void *ws, int32_t *flag, void *stream);
  *   Fine-Gray:  S_m,k = sum_{r <= k} e_r x_rj^m
  *                       + g_end_k * sum_{r after k's run} e_r x_rj^m w_comp_r
  * One fused pass: tuple scan with decoupled look-back, transform,
- * reduction; the last tile finishes the reduction (Fig. 3).  The partial
+ * reduction; the last tile finishes the reduction (Fig. 2).  The partial
  * sums are added in a fixed order, but a tile's prefix combines whichever
  * predecessor values the look-back finds visible first, so repeated calls
  * can differ in the last bits (far inside the 1e-10 parity bound).
@@ -174,6 +174,21 @@ int32_t ss_loglik(int32_t model, int64_t n, int64_t p,
                   const double *beta, const double *c, double *out,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* Penalised objective g = l + pi (Secs. 2.3-2.4: CCD maximises the log
+ * (pseudo-) likelihood plus the log prior), at beta[p] (device) and the
+ * e = exp(X beta) that goes with it: l as ss_loglik computes it, and
+ *   pi = -gamma sum_j |beta_j|           (SS_PENALTY_L1, lambda = gamma)
+ *   pi = -sum_j beta_j^2 / (2 tau)       (SS_PENALTY_L2, lambda = tau)
+ *   pi = 0                               (SS_PENALTY_NONE, lambda ignored)
+ * Output out[3] (device): l + pi, l, pi.  One fused launch, the penalty
+ * summed by the last tile.  Errors as ss_loglik, plus SS_EUNSUPPORTED for an
+ * unknown penalty and SS_EINVAL for a penalty with lambda <= 0. */
+int32_t ss_objective(int32_t model, int32_t penalty, double lambda, int64_t n,
+                     int64_t p, const double *e, const uint8_t *d8,
+                     const int32_t *d32, const double *w_comp,
+                     const double *g_end, const double *beta, const double *c,
+                     double *out, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------ a3 (+ a1)
  * One coordinate update (Secs. 2.3-2.4): from g12[0..1] = (g', g'') of the
  * unpenalised likelihood (device, e.g. the out of ss_grad_hess), take the
@@ -182,7 +197,7 @@ int32_t ss_loglik(int32_t model, int64_t n, int64_t p,
  *   beta_j += sgn(s) min(|s|, delta_j),  delta_j <- max(2|s|, delta_j/2),
  * store the applied step in *step, and if it is non-zero update
  * eta_k += x_kj * step and e_k = exp(eta_k) at the non-zeros of column j
- * (Sec. 2.7 step (1); Fig. 4's conditional kernel).  lambda is gamma (l1)
+ * (Sec. 2.7 step (1); Fig. 3's conditional kernel).  lambda is gamma (l1)
  * or tau (l2), ignored for no penalty.  A penalised second derivative that
  * is not strictly negative gives a zero step. */
 int32_t ss_ccd_update(int32_t penalty, double lambda, int64_t n, int64_t p,
@@ -192,7 +207,7 @@ int32_t ss_ccd_update(int32_t penalty, double lambda, int64_t n, int64_t p,
                       const double *vals_sorted, void *stream);
 
 /* ------------------------------------------------------------ fused sweep
- * Cyclic coordinate descent over coordinates j_begin..j_end-1 (Fig. 4)
+ * Cyclic coordinate descent over coordinates j_begin..j_end-1 (Fig. 3)
  * without any host round trip: per coordinate one fused launch (Fine-Gray:
  * two) that applies the previous coordinate's update to eta and e (step
  * (1)), computes g', g'' (steps (2)-(4)) and, in its last tile, the update
@@ -371,6 +386,19 @@ int32_t ss_cv_loglik(int32_t model, int64_t n, int32_t reps,
                      const uint8_t *train_s, const uint8_t *d8,
                      const int32_t *d32, const uint8_t *d8_r,
                      const int32_t *d32_r, double *out, void *stream);
+
+/* ss_cv_select: the choice of the penalty strength by cross-validation
+ * (Sec. 2.8, and the largest mean predictive log-likelihood as the reading
+ * of "best").  scores (device) holds n_gamma rows of 2 * reps doubles, row g
+ * as ss_cv_loglik wrote it for the fits at strength g (out[2r+1] = the
+ * held-out log-likelihood of replicate r).  Writes mean[g] (device,
+ * n_gamma doubles) = the mean held-out log-likelihood over the replicates,
+ * summed in replicate order, and *best (device, one int32) = the first g
+ * with the largest mean (a NaN mean never wins; -1 if every mean is NaN).
+ * One small launch; deterministic.  SS_EINVAL for n_gamma < 1, reps outside
+ * [1, 65535] or a null pointer. */
+int32_t ss_cv_select(int32_t n_gamma, int32_t reps, const double *scores,
+                     double *mean, int32_t *best, void *stream);
 
 #ifdef __cplusplus
 }

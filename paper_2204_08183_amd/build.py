@@ -33,18 +33,37 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose=False):
-    """Compile every HIP source into the shared library (always rebuilds)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", INCLUDE, "-I", CSRC] + srcs + ["-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         sys.stderr.write(proc.stdout + proc.stderr)
-        raise RuntimeError("hipcc failed building libsurvscan.so")
+        raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
+
+
+def build(verbose=False):
+    """Compile every HIP source (in parallel, one object each) and link the
+    shared library (always rebuilds)."""
+    import concurrent.futures as cf
+    objdir = os.path.join(ROOT, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    tag = "%d" % os.getpid()
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src.replace(".hip", ".%s.o" % tag))
+        jobs.append(([hipcc()] + compile_flags + ["-I", INCLUDE, "-I", CSRC, "-c",
+                                                   os.path.join(CSRC, src), "-o", obj], obj))
+    workers = min(len(jobs), max(1, min(8, os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(lambda j: _run(j[0], verbose), jobs))
+    tmp = LIB + ".tmp" + tag
+    _run([hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC"] + [o for _, o in jobs] +
+         ["-o", tmp], verbose)
     os.replace(tmp, LIB)
+    for _, o in jobs:
+        os.remove(o)
     return LIB
 
 

@@ -9,6 +9,7 @@
 
 namespace ss {
 
+
 static thread_local char g_last_hip[256] = "no HIP error recorded";
 
 int32_t record_hip_error(hipError_t err)
@@ -33,23 +34,6 @@ static Column column(const int64_t *col_ptr, const int32_t *rows, const double *
     c.chunk_ptr = chunk_ptr;
     c.nchunk1 = ss_chunk_count(n) + 1;
     return c;
-}
-
-static bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
-
-// The fused kernels read e, w_comp and g_end with 16-byte loads and d8 with
-// 8-byte loads.
-static bool model_arrays_ok(int32_t model, const double *e, const uint8_t *d8,
-                            const int32_t *d32, const double *w_comp,
-                            const double *g_end)
-{
-    if (!e || !d8 || !d32) return false;
-    if (!aligned(e, 16) || !aligned(d8, 8)) return false;
-    if (model == SS_FINE_GRAY) {
-        if (!w_comp || !g_end) return false;
-        if (!aligned(w_comp, 16) || !aligned(g_end, 16)) return false;
-    }
-    return true;
 }
 
 }  // namespace ss
@@ -152,13 +136,16 @@ int32_t ss_grad_hess(int32_t model, int64_t n, int64_t p, int64_t j, const doubl
     a.c = c;
     a.out = out;
     a.want_log = 1;
+    a.obj_penalty = -1;
+    a.jnext = -1;
     return launch_fused(a, v, (hipStream_t)stream);
 }
 
-int32_t ss_loglik(int32_t model, int64_t n, int64_t p, const double *e, const uint8_t *d8,
-                  const int32_t *d32, const double *w_comp, const double *g_end,
-                  const double *beta, const double *c, double *out, void *ws,
-                  size_t ws_bytes, void *stream)
+static int32_t loglik_call(int32_t model, int32_t penalty, double lambda, int64_t n,
+                           int64_t p, const double *e, const uint8_t *d8, const int32_t *d32,
+                           const double *w_comp, const double *g_end, const double *beta,
+                           const double *c, double *out, void *ws, size_t ws_bytes,
+                           void *stream)
 {
     if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
     if (bad_size(n, p)) return SS_EINVAL;
@@ -187,7 +174,31 @@ int32_t ss_loglik(int32_t model, int64_t n, int64_t p, const double *e, const ui
     a.out = out;
     a.beta_ll = beta;
     a.want_log = 1;
+    a.obj_penalty = penalty;
+    a.obj_lambda = lambda;
+    a.jnext = -1;
     return launch_fused(a, v, (hipStream_t)stream);
+}
+
+int32_t ss_loglik(int32_t model, int64_t n, int64_t p, const double *e, const uint8_t *d8,
+                  const int32_t *d32, const double *w_comp, const double *g_end,
+                  const double *beta, const double *c, double *out, void *ws,
+                  size_t ws_bytes, void *stream)
+{
+    return loglik_call(model, -1, 0.0, n, p, e, d8, d32, w_comp, g_end, beta, c, out, ws,
+                       ws_bytes, stream);
+}
+
+int32_t ss_objective(int32_t model, int32_t penalty, double lambda, int64_t n, int64_t p,
+                     const double *e, const uint8_t *d8, const int32_t *d32,
+                     const double *w_comp, const double *g_end, const double *beta,
+                     const double *c, double *out, void *ws, size_t ws_bytes, void *stream)
+{
+    if (penalty != SS_PENALTY_NONE && penalty != SS_PENALTY_L1 && penalty != SS_PENALTY_L2)
+        return SS_EUNSUPPORTED;
+    if (penalty != SS_PENALTY_NONE && !(lambda > 0.0)) return SS_EINVAL;
+    return loglik_call(model, penalty, lambda, n, p, e, d8, d32, w_comp, g_end, beta, c, out,
+                       ws, ws_bytes, stream);
 }
 
 int32_t ss_ccd_update(int32_t penalty, double lambda, int64_t n, int64_t p, int64_t j,
@@ -274,11 +285,18 @@ int32_t ss_ccd_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, i
     a.delta = delta;
     a.steps = steps;
     a.want_log = g12_out != nullptr;
+    a.obj_penalty = -1;
+    // Fine-Gray with a 0/1 design: one launch per coordinate, each carrying
+    // the weighted totals of the next column (a totals pass only before the
+    // first one); valued designs: a totals pass before every scan
+    const bool fg_carry = model == SS_FINE_GRAY && vals_sorted == nullptr;
     for (int64_t j = j_begin; j < j_end; ++j) {
         a.j = (int32_t)j;
         a.jprev = j > j_begin ? (int32_t)(j - 1) : -1;
         a.step_prev = j > j_begin ? steps + (j - 1) : nullptr;
         a.out = g12_out ? g12_out + 3 * j : v.hdr->scratch_out;
+        a.fg_have_totals = fg_carry && j > j_begin;
+        a.jnext = fg_carry && j + 1 < j_end ? (int32_t)(j + 1) : -1;
         int32_t rc = launch_fused(a, v, s);
         if (rc) return rc;
     }
@@ -418,7 +436,8 @@ int32_t ss_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, in
 {
     if (model != SS_COX) return SS_EUNSUPPORTED;
     if (penalty != SS_PENALTY_NONE && penalty != SS_PENALTY_L1 && penalty != SS_PENALTY_L2)
-        return SS_EINVAL;
+        return SS_EUNSUPPORTED;
+    if (penalty != SS_PENALTY_NONE && !(lambda > 0.0)) return SS_EINVAL;
     if (bad_cv(n, p, reps) || j_begin < 0 || j_end < j_begin || j_end > p) return SS_EINVAL;
     if (!eta || !e || !d8_r || !d32_r || !train_s || !xbits || !c_r || !beta || !delta)
         return SS_EINVAL;
@@ -438,6 +457,14 @@ int32_t ss_cv_loglik(int32_t model, int64_t n, int32_t reps, const int32_t *perm
         return SS_EINVAL;
     return launch_cv_loglik(model, n, reps, perm, status, eta, e, train_s, d8, d32, d8_r,
                             d32_r, out, (hipStream_t)stream);
+}
+
+int32_t ss_cv_select(int32_t n_gamma, int32_t reps, const double *scores, double *mean,
+                     int32_t *best, void *stream)
+{
+    if (n_gamma < 1 || reps < 1 || reps > 65535) return SS_EINVAL;
+    if (!scores || !mean || !best) return SS_EINVAL;
+    return launch_cv_select(n_gamma, reps, scores, mean, best, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -682,7 +682,47 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_loglik(int32_t model, int64_t n
 
 int grid_of(int64_t n, int64_t cap) { return (int)std::max<int64_t>(1, std::min(cap, ceil_div(n, 256))); }
 
+// The choice of the penalty strength (Sec. 2.8): thread g sums the held-out
+// scores of strength g over the replicates in replicate order; thread 0 then
+// takes the first strength with the largest mean (NaN means never win).
+__global__ __launch_bounds__(256) void k_cv_select(int32_t n_gamma, int32_t reps,
+                                                   const double *scores, double *mean,
+                                                   int32_t *best)
+{
+    for (int32_t g0 = 0; g0 < n_gamma; g0 += 256) {
+        const int32_t g = g0 + (int32_t)threadIdx.x;
+        if (g < n_gamma) {
+            const double *row = scores + (int64_t)g * 2 * reps;
+            double s = 0.0;
+            for (int32_t r = 0; r < reps; ++r) s += row[2 * r + 1];
+            mean[g] = s / (double)reps;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t b = -1;
+        double bv = 0.0;
+        for (int32_t g = 0; g < n_gamma; ++g) {
+            const double v = mean[g];
+            if (v == v && (b < 0 || v > bv)) {
+                b = g;
+                bv = v;
+            }
+        }
+        *best = b;
+    }
+}
+
 }  // namespace
+
+int32_t launch_cv_select(int32_t n_gamma, int32_t reps, const double *scores, double *mean,
+                         int32_t *best, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cv_select, dim3(1), dim3(256), 0, s, n_gamma, reps, scores, mean,
+                       best);
+    SS_LAUNCH_CHECK();
+    return SS_OK;
+}
 
 int64_t cv_stride(int64_t n) { return ceil_div(n, kCvAlign) * kCvAlign; }
 

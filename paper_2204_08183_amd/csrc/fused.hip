@@ -1,8 +1,8 @@
 // Fused coordinate kernels for gfx950: the sparse update of X beta (step
 // (1) of Sec. 2.7), the single-pass tuple scan with decoupled look-back,
 // the element-wise transform with the event counts and the reduction
-// (steps (2)-(4), fused as in Fig. 3), and the coordinate update in the
-// last tile (Fig. 4's conditional kernel, Secs. 2.3-2.4).
+// (steps (2)-(4), fused as in Fig. 2), and the coordinate update in the
+// last tile (Fig. 3's conditional kernel, Secs. 2.3-2.4).
 //
 // Data layout (sorted order = decreasing observed time):
 //   e[n]  f64      exp(X beta), dense
@@ -43,27 +43,20 @@ using namespace dev;
 #endif
 
 // ---------------------------------------------------------------- look-back
-// Decoupled look-back (single-pass chained scan, Sec. 2.6), in two
-// variants; a launch uses one of them throughout (chosen by tile size).
+// Decoupled look-back (single-pass chained scan, Sec. 2.6).  A tile's slot
+// holds its NC values as 16-byte (value, tag) pairs, tag = (epoch << 2) |
+// state with state 1 = tile aggregate and 2 = inclusive prefix; the inclusive
+// prefix overwrites the aggregate in place.  Each pair is written and read as
+// one 16-byte access, so a reader that sees all NC tags equal has a
+// consistent snapshot (mixed tags: the slot is being overwritten, not ready
+// yet), and one load brings a predecessor's state and value together: no
+// flag word, no ordering wait on either side.  While the data stream
+// saturates memory a round trip through the coherence point takes ~5 us, and
+// one round trip instead of two (flags, then payloads) took the look-back
+// from 11 to 5 us per tile at N = 2^27.
 //
-// Pairs (large tiles, large N): a tile's slot holds its NC values as
-// 16-byte (value, tag) pairs, tag = (epoch << 2) | state with state 1 = tile
-// aggregate and 2 = inclusive prefix; the inclusive prefix overwrites the
-// aggregate in place.  Each pair is written and read as one 16-byte access,
-// so a reader that sees all NC tags equal has a consistent snapshot (mixed
-// tags: the slot is being overwritten, not ready yet), and one load brings a
-// predecessor's state and value together: no flag word, no ordering wait on
-// either side.  While the data stream saturates memory a round trip through
-// the coherence point takes ~5 us, and one round trip instead of two (flags,
-// then payloads) took the look-back from 11 to 5 us per tile at N = 2^27.
-//
-// Flags (small tiles, small N): an 8-byte flag per tile and separate
-// payloads.  When every tile of a launch is resident at once (N up to a few
-// million) all of them look back together, and polling 48 bytes per
-// predecessor instead of 8 made those launches slower.
-//
-// In both, wave 0 looks back over windows of 64 predecessors per round: one
-// load round trip for a round, the nearest inclusive prefix fixes which
+// Wave 0 looks back over a window of 64 predecessors per round: one load
+// round trip for a round, the nearest inclusive prefix fixes which
 // predecessors are needed, and only the needed ones that were not ready are
 // polled again.  Every predecessor started earlier (workgroups start in
 // index order on each XCD) and publishes its aggregate without waiting on
@@ -103,7 +96,7 @@ __device__ bool look_back_pairs(const u32x4 *lb, int64_t tile, uint64_t epoch, W
     const int lane = lane_id();
 #pragma unroll
     for (int c = 0; c < NC; ++c) excl[c] = 0.0;
-    // tile indices fit in 32 bits (n < 2^31, tiles of at least 1024)
+    // tile indices fit in 32 bits (n < 2^31, tiles of at least 2048)
     int32_t top = (int32_t)tile - 1;
     uint32_t spins = 0;
     uint32_t rounds = 0, waits = 0;
@@ -206,152 +199,19 @@ __device__ bool look_back_pairs(const u32x4 *lb, int64_t tile, uint64_t epoch, W
 }
 
 
-// ---------------------------------------------------- look-back, flags
-// Slot: flag word (epoch << 2) | state and the two payloads; a payload is
-// written before its flag (release order) and read after it (acquire order).
-struct alignas(128) LbSlot {
-    uint64_t flag;
-    double agg[kMaxComp];
-    double inc[kMaxComp];
-};
-static_assert(sizeof(LbSlot) == 16 * kLbSlot, "both look-back variants use 128-byte slots");
-
-// Wave 0, lane 0: payload, then flag.
-template <int NC>
-__device__ __forceinline__ void publish_lb(LbSlot *slot, const double (&v)[NC], bool inclusive,
-                                           uint64_t epoch)
-{
-    double *dst = inclusive ? slot->inc : slot->agg;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) st_relaxed(dst + c, v[c]);
-    order_release();
-    st_flag(&slot->flag, (epoch << 2) | (inclusive ? kStateInc : kStateAgg));
-}
-
-// Wave 0 only; the exclusive prefix is returned in every lane.  Returns
-// false if the wait gave up (the error word is then set).
-//
-// One round covers 64 * kLbW predecessors: their flags are read once (one
-// round trip), the nearest inclusive prefix among them fixes which ones are
-// needed, only the needed ones that had not published yet are polled again,
-// and each needed payload is loaded once (aggregate, or the inclusive prefix
-// at the nearest one).  The states stay packed, two bits per predecessor.
-template <int NC>
-__device__ bool look_back_flags(const LbSlot *lb, int64_t tile, uint64_t epoch, WsHeader *hdr,
-                          double (&excl)[NC], uint64_t *lb_stats = nullptr)
-{
-    constexpr int kLbW = 4;  // windows of 64 per round (8 measured slower: registers)
-    constexpr int kBatch = NC > 3 ? 2 : 4;  // payload windows in flight per lane
-    const int lane = lane_id();
-#pragma unroll
-    for (int c = 0; c < NC; ++c) excl[c] = 0.0;
-    // tile indices fit in 32 bits (n < 2^31, tiles of at least 1024)
-    int32_t top = (int32_t)tile - 1;
-    uint32_t spins = 0;
-    // uniform base plus a 32-bit byte offset: one VGPR per address
-    const char *lbase = reinterpret_cast<const char *>(lb);
-    auto state_of = [&](int32_t t) -> uint32_t {
-        if (t < 0) return (uint32_t)kStateInc;  // before tile 0: an empty prefix
-        const uint32_t off = (uint32_t)t * (uint32_t)sizeof(LbSlot);
-        const uint64_t f = ld_flag(reinterpret_cast<const uint64_t *>(lbase + off));
-        return (f >> 2) == epoch ? (uint32_t)(f & 3u) : 0u;
-    };
-    uint32_t rounds = 0, waits = 0;
-    while (top >= 0) {
-        ++rounds;
-        uint32_t stb = 0;  // bits 2q, 2q+1: state of predecessor top - lane - 64 q
-#pragma unroll
-        for (int q = 0; q < kLbW; ++q) stb |= state_of(top - lane - kWave * q) << (2 * q);
-        // nearest inclusive prefix: first window holding one, lowest lane in it
-        int fq = -1, fl = 0;
-        auto nearest_inclusive = [&]() {
-            fq = -1;
-            fl = 0;
-#pragma unroll
-            for (int q = 0; q < kLbW; ++q) {
-                const uint64_t m = __ballot(((stb >> (2 * q)) & 3u) == kStateInc);
-                if (fq < 0 && m) {
-                    fq = q;
-                    fl = __ffsll((unsigned long long)m) - 1;
-                }
-            }
-        };
-        nearest_inclusive();
-        auto needed = [&](int q) {
-            return fq < 0 || q < fq || (q == fq && lane <= fl);
-        };
-        // wait for the needed predecessors that had not published
-        for (;;) {
-            bool pend = false;
-#pragma unroll
-            for (int q = 0; q < kLbW; ++q) {
-                if (needed(q) && ((stb >> (2 * q)) & 3u) == 0u) {
-                    const uint32_t s2 = state_of(top - lane - kWave * q);
-                    stb |= s2 << (2 * q);
-                    pend = pend || s2 == 0u;
-                }
-            }
-            if (!__any(pend)) break;
-            ++waits;
-            if (++spins > kSpinLimit) {
-                if (lane == 0)
-                    __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                return false;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-        // a predecessor polled again may have published its inclusive prefix
-        // meanwhile: the nearest one can only have moved closer, and every
-        // position before it is ready (tile 0 publishes no aggregate, so its
-        // inclusive prefix must be read when it is the nearest)
-        nearest_inclusive();
-        order_acquire();  // payload loads stay after the flag loads
-        double sum[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) sum[c] = 0.0;
-#pragma unroll
-        for (int q0 = 0; q0 < kLbW; q0 += kBatch) {
-            if (fq >= 0 && q0 > fq) break;  // wave-uniform: nothing needed beyond
-            // one batch of loads in flight at a time (bounds the registers)
-            asm volatile("" ::: "memory");
-            double pay[kBatch][NC];
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                const int q = q0 + k;
-                const int32_t t = top - lane - kWave * q;
-                const bool take = needed(q) && t >= 0;
-                const uint32_t off = (uint32_t)(take ? t : 0) * (uint32_t)sizeof(LbSlot) +
-                                     ((q == fq && lane == fl) ? (uint32_t)offsetof(LbSlot, inc)
-                                                              : (uint32_t)offsetof(LbSlot, agg));
-                const double *src = reinterpret_cast<const double *>(lbase + off);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) pay[k][c] = take ? ld_relaxed(src + c) : 0.0;
-            }
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k)
-#pragma unroll
-                for (int c = 0; c < NC; ++c) sum[c] += pay[k][c];
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) excl[c] += wave_sum(sum[c]);
-        if (fq >= 0) break;
-        top -= kWave * kLbW;
-    }
-    if (lb_stats && lane == 0) *lb_stats = ((uint64_t)rounds << 32) | waits;
-    return true;
-}
-
-// Polls three pairs until all carry `tag`; false if the wait gave up (then
-// the error word is set) or another wait already did.
-__device__ __forceinline__ bool poll_pairs3(const u32x4 *p, uint64_t tag, WsHeader *hdr,
-                                            u32x4 (&r)[3])
+// Polls NP pairs until all carry `tag`; false if the wait gave up (then the
+// error word is set) or another wait already did.
+template <int NP>
+__device__ __forceinline__ bool poll_pairs(const u32x4 *p, uint64_t tag, WsHeader *hdr,
+                                           u32x4 (&r)[NP])
 {
     uint32_t spins = 0;
     for (;;) {
-        ld_pairs<3>(p, r);
-        if (pair_tag(r[0]) == tag && pair_tag(r[1]) == tag && pair_tag(r[2]) == tag)
-            return true;
+        ld_pairs<NP>(p, r);
+        bool ok = true;
+#pragma unroll
+        for (int c = 0; c < NP; ++c) ok = ok && pair_tag(r[c]) == tag;
+        if (ok) return true;
         if (++spins > kSpinLimit || ((spins & 31u) == 0 && ld_relaxed_u32(&hdr->error))) {
             __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
@@ -362,50 +222,54 @@ __device__ __forceinline__ bool poll_pairs3(const u32x4 *p, uint64_t tag, WsHead
 
 // ------------------------------------------------------ partial sums
 // Two-level reduction of the per-tile partial sums, in a fixed order (so
-// the result does not depend on timing): every tile publishes its three
-// sums as pairs; the last tile of each group of kGroup tiles waits for its
-// group (wave 0, one tile per lane) and publishes the group's sums; the
-// last tile of the launch waits for the groups and adds them.  Only tiles
-// with smaller indices are ever waited for.
+// the result does not depend on timing): every tile publishes its NR sums
+// as pairs (slots of SLOT pairs); the last tile of each group of kGroup
+// tiles waits for its group (wave 0, one tile per lane) and publishes the
+// group's sums; the last tile of the launch waits for the groups and adds
+// them.  Only tiles with smaller indices are ever waited for.
 //
 // tile_sum: the calling tile's sums (valid in every thread).  In the last
 // tile, `total` (thread 0) receives the launch total; a wait that gives up
-// sets the error word and leaves its share out.
-template <int BLOCK>
+// sets the error word and leaves its share out.  s_red: NR + BLOCK/64 * NR
+// doubles of LDS.
+template <int BLOCK, int NR, int SLOT>
 __device__ void reduce_partials(u32x4 *part, u32x4 *gpart, int64_t tile, int64_t ntiles,
-                                uint64_t tag, WsHeader *hdr, const double (&tile_sum)[3],
-                                double (&total)[3], double *s_red)
+                                uint64_t tag, WsHeader *hdr, const double (&tile_sum)[NR],
+                                double (&total)[NR], double *s_red)
 {
+    static_assert(NR <= SLOT, "a slot holds the sums");
     const int lane = lane_id();
     const int tid = threadIdx.x;
     const bool last = tile == ntiles - 1;
     const bool leader = last || (tile % kGroup) == kGroup - 1;
     if (tid < kWave) {
         if (!leader) {
-            publish_pairs<3>(part + tile * 4, tile_sum, tag);
+            publish_pairs<NR>(part + tile * SLOT, tile_sum, tag);
         } else {
             // wave 0 of a group leader: tiles g0 .. tile, this tile's own
             // sums from registers
             const int64_t g0 = tile - tile % kGroup;
             const int64_t t = g0 + lane;
-            double v[3] = {0.0, 0.0, 0.0};
-            if (t < tile) {
-                u32x4 r[3];
-                if (poll_pairs3(part + t * 4, tag, hdr, r)) {
+            double v[NR];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) v[c] = pair_value(r[c]);
+            for (int c = 0; c < NR; ++c) v[c] = 0.0;
+            if (t < tile) {
+                u32x4 r[NR];
+                if (poll_pairs<NR>(part + t * SLOT, tag, hdr, r)) {
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) v[c] = pair_value(r[c]);
                 }
             } else if (t == tile) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v[c] = tile_sum[c];
+                for (int c = 0; c < NR; ++c) v[c] = tile_sum[c];
             }
-            double g[3];
+            double g[NR];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) g[c] = dpp_wave_sum(v[c]);
-            if (!last) publish_pairs<3>(gpart + (tile / kGroup) * 4, g, tag);
+            for (int c = 0; c < NR; ++c) g[c] = dpp_wave_sum(v[c]);
+            if (!last) publish_pairs<NR>(gpart + (tile / kGroup) * SLOT, g, tag);
             if (lane == 0) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) s_red[c] = g[c];
+                for (int c = 0; c < NR; ++c) s_red[c] = g[c];
             }
         }
     }
@@ -413,39 +277,62 @@ __device__ void reduce_partials(u32x4 *part, u32x4 *gpart, int64_t tile, int64_t
     __syncthreads();
     // the last tile: groups 0 .. ngroups-2 from memory, its own from LDS
     const int64_t ngroups = tile / kGroup + 1;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
     for (int64_t q = tid; q < ngroups - 1; q += BLOCK) {
-        u32x4 r[3];
-        if (!poll_pairs3(gpart + q * 4, tag, hdr, r)) break;
+        u32x4 r[NR];
+        if (!poll_pairs<NR>(gpart + q * SLOT, tag, hdr, r)) break;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] += pair_value(r[c]);
+        for (int c = 0; c < NR; ++c) acc[c] += pair_value(r[c]);
     }
-    double own[3];
+    double own[NR];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) own[c] = s_red[c];
-    block_sum<3, BLOCK>(acc, s_red + 4);
+    for (int c = 0; c < NR; ++c) own[c] = s_red[c];
+    block_sum<NR, BLOCK>(acc, s_red + NR);
     if (tid == 0) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) total[c] = acc[c] + own[c];
+        for (int c = 0; c < NR; ++c) total[c] = acc[c] + own[c];
     }
 }
 
 // Last tile: g', g'', the likelihood or the coordinate update from the
 // launch totals (thread 0), then the launch epoch moves on.
-template <int BLOCK>
+//
+// CARRY (Fine-Gray, 0/1 design): tot[3], tot[4] are sum e w x_next and
+// sum e w x_j x_next over the launch, fgw = (sum e w, sum e w x_j) its
+// totals; the coordinate's step s multiplies e by exp(s) where x_j = 1, so
+// the totals of column jnext over the updated e are sum e w + expm1(s)
+// sum e w x_j (m = 0) and tot[3] + expm1(s) tot[4] (m = 1, 2), stored for the
+// next launch.
+template <int BLOCK, int NR, bool CARRY>
 __device__ void finish(const FusedCall &a, const WsView &ws, uint64_t epoch,
-                       const double (&tot)[3], double *s_red)
+                       const double (&tot)[NR], const double *fgw, double *s_red)
 {
-    double btc = 0.0;
+    // beta' c and the penalty's sum (|beta_q| for l1, beta_q^2 for l2)
+    double all[2] = {0.0, 0.0};
     if (a.beta_ll) {
-        for (int64_t q = threadIdx.x; q < a.p; q += BLOCK) btc += a.beta_ll[q] * a.c[q];
+        for (int64_t q = threadIdx.x; q < a.p; q += BLOCK) {
+            const double b = a.beta_ll[q];
+            all[0] += b * a.c[q];
+            all[1] += a.obj_penalty == SS_PENALTY_L2 ? b * b : fabs(b);
+        }
     }
-    double all[1] = {btc};
-    block_sum<1, BLOCK>(all, s_red);
+    block_sum<2, BLOCK>(all, s_red);
     if (threadIdx.x == 0) {
         const double A = tot[0], B = tot[1], L = tot[2];
         if (a.beta_ll) {
-            a.out[0] = all[0] - L;
+            const double l = all[0] - L;
+            if (a.obj_penalty >= 0) {
+                double pi = 0.0;
+                if (a.obj_penalty == SS_PENALTY_L1) pi = -a.obj_lambda * all[1];
+                if (a.obj_penalty == SS_PENALTY_L2) pi = -all[1] / (2.0 * a.obj_lambda);
+                a.out[0] = l + pi;
+                a.out[1] = l;
+                a.out[2] = pi;
+            } else {
+                a.out[0] = l;
+            }
         } else {
             const double g1 = a.c[a.j] - A;
             const double g2 = -B;
@@ -456,7 +343,15 @@ __device__ void finish(const FusedCall &a, const WsView &ws, uint64_t epoch,
                 ccd_apply(g1, g2, a.penalty, a.lambda, a.beta + a.j,
                           a.delta + a.j, a.steps + a.j);
             }
+            if constexpr (CARRY) {
+                const double em = expm1(a.steps[a.j]);
+                const double t1 = tot[3] + em * tot[4];
+                ws.hdr->fg_tot[0] = fgw[0] + em * fgw[1];
+                ws.hdr->fg_tot[1] = t1;
+                ws.hdr->fg_tot[2] = t1;
+            }
         }
+        if (a.err_out) a.err_out[0] = ld_relaxed_u32(&ws.hdr->error) ? 1.0 : 0.0;
         // every tile has read the epoch (it published a partial tagged with it)
         st_relaxed_u64(&ws.hdr->epoch, epoch + 1);
     }
@@ -505,13 +400,17 @@ __device__ __forceinline__ int32_t lds_slot(int32_t r)
 // independent loads are issued together; the sparse column and the patch
 // travel through LDS flag bytes (position order).  s_flag must be zero and
 // visible on entry; ends after one workgroup barrier.
-template <int BLOCK, int IPT, bool WANT_W, bool VALS, bool PREV, bool WANT_D>
+// NEXT: the 0/1 column jnext also goes to the flags; its bits are returned
+// in *nbits.
+template <int BLOCK, int IPT, bool WANT_W, bool VALS, bool PREV, bool WANT_D,
+          bool NEXT = false>
 __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, int64_t cnt,
                                                int64_t chunk0, int64_t chunk1,
                                                uint8_t *s_flag, double *s_xv, double *s_ep,
                                                double (&ev)[IPT],
                                                double (&wv)[WANT_W ? IPT : 1],
-                                               uint32_t (&dw)[(IPT + 3) / 4])
+                                               uint32_t (&dw)[(IPT + 3) / 4],
+                                               uint32_t *nbits = nullptr)
 {
     static_assert(IPT <= 32 && (IPT & (IPT - 1)) == 0 && IPT >= 4,
                   "IPT: a power of two from 4 to 32");
@@ -521,6 +420,8 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
     const int tid = threadIdx.x;
     ColTile cj = {0, 0, 0};
     if (a.j >= 0) cj = col_tile(a.col, a.j, chunk0, chunk1);
+    ColTile cnext = {0, 0, 0};
+    if (NEXT) cnext = col_tile(a.col, a.jnext, chunk0, chunk1);
     ColTile cprev = {0, 0, 0};
     double step_prev = 0.0;
     if (PREV) {
@@ -599,6 +500,10 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
             lds_flag_or(s_flag, r, kFlagX);
         }
     }
+    if (NEXT) {
+        for (int32_t o = cnext.lo + tid; o < cnext.hi; o += BLOCK)
+            lds_flag_or(s_flag, (int32_t)(a.col.rows[cnext.cb + o] - t0), kFlagNext);
+    }
     if (PREV && step_prev != 0.0) {
         for (int32_t o = cprev.lo + tid; o < cprev.hi; o += BLOCK) {
             const int32_t k = a.col.rows[cprev.cb + o];
@@ -614,6 +519,7 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
     __syncthreads();
     uint32_t xbits = 0u;
     uint32_t pbits = 0u;
+    uint32_t qbits = 0u;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         uint8_t fl[C];
@@ -622,8 +528,10 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
         for (int k = 0; k < C; ++k) {
             xbits |= (uint32_t)(fl[k] & kFlagX) << (q * C + k);
             pbits |= (uint32_t)((fl[k] & kFlagPatch) ? 1u : 0u) << (q * C + k);
+            if (NEXT) qbits |= (uint32_t)((fl[k] & kFlagNext) ? 1u : 0u) << (q * C + k);
         }
     }
+    if (NEXT) *nbits = qbits;
     if (dense) xbits = IPT == 32 ? ~0u : (1u << IPT) - 1u;
     if (PREV) {
 #pragma unroll
@@ -645,21 +553,27 @@ __device__ __forceinline__ double x_at(uint32_t xbits, int i, const double *s_xv
 // The fused scan -> transform -> reduce kernel (one coordinate).
 // MODEL: SS_COX (3 tuple components) or SS_FINE_GRAY (6).  PREV: apply the
 // pending step of column jprev to eta and e first (step (1) of Sec. 2.7).
-template <int BLOCK, int IPT, int MODEL, bool VALS, bool PREV>
+// CARRY (Fine-Gray, 0/1 design): the weighted totals of column j were
+// carried by the previous launch, and this launch carries those of column
+// jnext (two more partial sums, see finish).
+template <int BLOCK, int IPT, int MODEL, bool VALS, bool PREV, bool CARRY = false>
 __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t ntiles)
 {
     constexpr int TILE = BLOCK * IPT;
     constexpr int NC = MODEL == SS_FINE_GRAY ? 6 : 3;
     constexpr int NW = BLOCK / kWave;
+    constexpr int NR = CARRY ? 5 : 3;  // partial sums per tile
     static_assert(TILE % SS_CHUNK == 0, "tile must be whole chunks");
+    static_assert(!CARRY || (MODEL == SS_FINE_GRAY && !VALS), "carry: Fine-Gray, 0/1 design");
 
     __shared__ __attribute__((aligned(16))) uint8_t s_flag[TILE];
     __shared__ double s_xv[VALS ? TILE : 1];
     __shared__ double s_ep[PREV ? TILE : 1];
     __shared__ double s_wsum[TileMap<IPT>::R][NW][NC];
     __shared__ double s_excl[NC];
-    __shared__ double s_red[NW * 4];
-    __shared__ double s_tsum[3];
+    __shared__ double s_red[NW * NR + NR];
+    __shared__ double s_tsum[NR];
+    __shared__ double s_fgw[2];
     __shared__ uint64_t s_epoch;
 
     const int tid = threadIdx.x;
@@ -670,7 +584,10 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     // order on each XCD, so every predecessor a tile waits for has started
     // (the waits are bounded all the same); clear the LDS flags meanwhile
     SS_TRACE(ws, (int64_t)blockIdx.x, 0);
-    if (tid == 0) s_epoch = ld_relaxed_u64(&ws.hdr->epoch);
+    if (tid == 0) {
+        s_epoch = ld_relaxed_u64(&ws.hdr->epoch);
+        if (a.clear_error && blockIdx.x == 0) st_relaxed_u32(&ws.hdr->error, 0u);
+    }
     {
         uint32_t *f32 = reinterpret_cast<uint32_t *>(s_flag);
         for (int i = tid; i < TILE / 4; i += BLOCK) f32[i] = 0u;
@@ -690,8 +607,10 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     double ev[IPT];
     double wv[MODEL == SS_FINE_GRAY ? IPT : 1];
     uint32_t dw[(IPT + 3) / 4];  // event counts, one byte per element
-    const uint32_t xbits = stage_tile<BLOCK, IPT, MODEL == SS_FINE_GRAY, VALS, PREV, true>(
-        a, t0, cnt, chunk0, chunk1, s_flag, s_xv, s_ep, ev, wv, dw);
+    uint32_t nbits = 0u;         // CARRY: column jnext, one bit per element
+    const uint32_t xbits =
+        stage_tile<BLOCK, IPT, MODEL == SS_FINE_GRAY, VALS, PREV, true, CARRY>(
+            a, t0, cnt, chunk0, chunk1, s_flag, s_xv, s_ep, ev, wv, dw, &nbits);
     SS_TRACE(ws, tile, 1);
 
     // ---- 5. the tile's aggregate: thread totals, then a block sum (the
@@ -735,9 +654,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     // ---- 6. decoupled look-back for the tile's exclusive prefix
     SS_TRACE(ws, tile, 2);
     if (w == 0) {
-        constexpr bool kPairs = IPT >= 8;  // see the look-back notes above
         u32x4 *slot = ws.lb + tile * kLbSlot;
-        LbSlot *fslot = reinterpret_cast<LbSlot *>(ws.lb) + tile;
         double ex[NC];
         uint64_t *lbs = nullptr;
 #ifdef SS_TRACE_TIMES
@@ -745,31 +662,30 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
             lbs = trace_base(ws) + tile * 8 + 5;
 #endif
         if (tile == 0) {
-            if (kPairs) publish_pairs<NC>(slot, agg, (epoch << 2) | kStateInc);
-            else if (lane == 0) publish_lb<NC>(fslot, agg, true, epoch);
+            publish_pairs<NC>(slot, agg, (epoch << 2) | kStateInc);
 #pragma unroll
             for (int c = 0; c < NC; ++c) ex[c] = 0.0;
         } else {
-            if (kPairs) publish_pairs<NC>(slot, agg, (epoch << 2) | kStateAgg);
-            else if (lane == 0) publish_lb<NC>(fslot, agg, false, epoch);
+            publish_pairs<NC>(slot, agg, (epoch << 2) | kStateAgg);
             SS_TRACE(ws, tile, 6);
             // a wait that gives up has set the error word; the launch still
             // runs to its end
-            if (kPairs)
-                (void)look_back_pairs<NC>(ws.lb, tile, epoch, ws.hdr, ex, lbs);
-            else
-                (void)look_back_flags<NC>(reinterpret_cast<const LbSlot *>(ws.lb), tile, epoch,
-                                          ws.hdr, ex, lbs);
+            (void)look_back_pairs<NC>(ws.lb, tile, epoch, ws.hdr, ex, lbs);
             SS_TRACE(ws, tile, 7);
             double inc[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) inc[c] = ex[c] + agg[c];
-            if (kPairs) publish_pairs<NC>(slot, inc, (epoch << 2) | kStateInc);
-            else if (lane == 0) publish_lb<NC>(fslot, inc, true, epoch);
+            publish_pairs<NC>(slot, inc, (epoch << 2) | kStateInc);
         }
         if (lane == 0) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) s_excl[c] = ex[c];
+            if constexpr (CARRY) {
+                if (tile == ntiles - 1) {
+                    s_fgw[0] = ex[3] + agg[3];
+                    s_fgw[1] = ex[4] + agg[4];
+                }
+            }
         }
     }
     __syncthreads();
@@ -840,7 +756,9 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     // ---- 8. running prefix, transform at run ends, reduction (the
     // products are formed again, not kept from step 7)
     asm volatile("" : "+v"(xb));
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
     LogSum lsum;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -861,6 +779,12 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
                 S[3] += ew;
                 S[4] += exw;
                 S[5] += exw * x;
+                if constexpr (CARRY) {
+                    if ((nbits >> i) & 1u) {
+                        acc[3] += ew;
+                        acc[4] += exw;
+                    }
+                }
             }
             int d = (int)((dw[i / 4] >> (8 * (i % 4))) & 255u);
             if (d != 0) {
@@ -884,19 +808,21 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
         }
     }
     if (a.want_log) acc[2] = lsum.value();
-    block_sum<3, BLOCK>(acc, s_red);
+    block_sum<NR, BLOCK>(acc, s_red);
     if (tid == 0) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) s_tsum[c] = acc[c];
+        for (int c = 0; c < NR; ++c) s_tsum[c] = acc[c];
     }
     __syncthreads();
-    const double tsum[3] = {s_tsum[0], s_tsum[1], s_tsum[2]};
-    double total[3];
-    reduce_partials<BLOCK>(ws.part, ws.gpart, tile, ntiles, (epoch << 1) | 1u, ws.hdr, tsum,
-                           total, s_red);
+    double tsum[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) tsum[c] = s_tsum[c];
+    double total[NR];
+    reduce_partials<BLOCK, NR, 8>(ws.part, ws.gpart, tile, ntiles, (epoch << 1) | 1u, ws.hdr,
+                                  tsum, total, s_red);
     SS_TRACE(ws, tile, 4);
     if (tile == ntiles - 1) {
-        finish<BLOCK>(a, ws, epoch, total, s_red);
+        finish<BLOCK, NR, CARRY>(a, ws, epoch, total, s_fgw, s_red);
         SS_TRACE(ws, tile, 5);
     }
 }
@@ -916,7 +842,10 @@ __global__ __launch_bounds__(BLOCK) void k_fg_totals(FusedCall a, WsView ws,
     __shared__ double s_tsum[3];
     __shared__ uint64_t s_epoch;
     const int tid = threadIdx.x;
-    if (tid == 0) s_epoch = ld_relaxed_u64(&ws.hdr->fg_epoch);
+    if (tid == 0) {
+        s_epoch = ld_relaxed_u64(&ws.hdr->fg_epoch);
+        if (a.clear_error && blockIdx.x == 0) st_relaxed_u32(&ws.hdr->error, 0u);
+    }
     {
         uint32_t *f32 = reinterpret_cast<uint32_t *>(s_flag);
         for (int i = tid; i < TILE / 4; i += BLOCK) f32[i] = 0u;
@@ -951,7 +880,8 @@ __global__ __launch_bounds__(BLOCK) void k_fg_totals(FusedCall a, WsView ws,
     __syncthreads();
     const double tsum[3] = {s_tsum[0], s_tsum[1], s_tsum[2]};
     double t[3];
-    reduce_partials<BLOCK>(ws.fg_part, ws.fg_gpart, tile, ntiles, tag, ws.hdr, tsum, t, s_red);
+    reduce_partials<BLOCK, 3, 4>(ws.fg_part, ws.fg_gpart, tile, ntiles, tag, ws.hdr, tsum, t,
+                                 s_red);
     if (tile == ntiles - 1) {
         if (tid == 0) {
 #pragma unroll
@@ -1025,28 +955,6 @@ int grid_for(int64_t work, int per_block, int cap)
 
 }  // namespace
 
-size_t fused_ws_bytes(int64_t n)
-{
-    const int64_t tiles = ceil_div(n, SS_CHUNK) + 1;
-    const int64_t groups = ceil_div(tiles, kGroup) + 1;
-    size_t b = sizeof(WsHeader);
-    b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // lb
-    b = align_up(b + 16 * 4 * (size_t)tiles, 256);   // part
-    b = align_up(b + 16 * 4 * (size_t)tiles, 256);   // fg_part
-    b = align_up(b + 16 * 4 * (size_t)groups, 256);  // gpart
-    b = align_up(b + 16 * 4 * (size_t)groups, 256);  // fg_gpart
-    b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // sw_agg
-    b = align_up(b + 16 * 4 * (size_t)tiles, 256);   // sw_part
-    b = align_up(b + 16 * (size_t)tiles, 256);       // sw_step
-    b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // sw_pre
-    b = align_up(b + 16 * 16 * (size_t)std::max<int64_t>(tiles, 2 * kMaxSweepBlocks),
-                 256);                                // sw_pub
-#ifdef SS_TRACE_TIMES
-    b = align_up(b + sizeof(uint64_t) * 64 * (size_t)tiles, 256);
-#endif
-    return b;
-}
-
 bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v)
 {
     if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < fused_ws_bytes(n)) return false;
@@ -1062,9 +970,9 @@ bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v)
     v->hdr = (WsHeader *)p;
     off = sizeof(WsHeader);
     v->lb = take(16 * 8 * (size_t)tiles);
-    v->part = take(16 * 4 * (size_t)tiles);
+    v->part = take(16 * 8 * (size_t)tiles);
     v->fg_part = take(16 * 4 * (size_t)tiles);
-    v->gpart = take(16 * 4 * (size_t)groups);
+    v->gpart = take(16 * 8 * (size_t)groups);
     v->fg_gpart = take(16 * 4 * (size_t)groups);
     v->sw_agg = take(16 * 8 * (size_t)tiles);
     v->sw_part = take(16 * 4 * (size_t)tiles);
@@ -1079,19 +987,18 @@ namespace {
 
 // Items per thread by problem size: tiles of 2048 positions up to 1.5 M
 // positions, of 4096 above (measured with the one-window look-back: at
-// N = 1e6 15.9 us against 27.4 us for the 1024-position tiles with flag
-// look-back and 16.7 us for 4096; at N = 4e6 32 us against 82 and 36 us).
-// The flag look-back of 1024-position tiles is no longer dispatched.
+// N = 1e6 15.9 us against 16.7 us for 4096; at N = 4e6 32 us against
+// 36 us).
 int pick_ipt(int64_t n)
 {
     if (n <= (int64_t)3 << 19) return 8;
     return 16;
 }
 
-template <int IPT, int MODEL, bool VALS, bool PREV>
+template <int IPT, int MODEL, bool VALS, bool PREV, bool CARRY = false>
 void launch_fused_t(const FusedCall &a, const WsView &ws, int64_t ntiles, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_fused<kBlock, IPT, MODEL, VALS, PREV>), dim3((unsigned)ntiles),
+    hipLaunchKernelGGL((k_fused<kBlock, IPT, MODEL, VALS, PREV, CARRY>), dim3((unsigned)ntiles),
                        dim3(kBlock), 0, s, a, ws, ntiles);
 }
 
@@ -1118,12 +1025,27 @@ int32_t launch_fused_ipt(const FusedCall &a, const WsView &ws, hipStream_t s)
     const bool prev = a.jprev >= 0;
     FusedCall b = a;
     if (a.model == SS_FINE_GRAY) {
-        // totals pass (and the pending a1 update), then the scan pass
-        launch_fg_totals_t<IPT>(a, ws, ntiles, vals, prev, s);
-        SS_LAUNCH_CHECK();
-        b.jprev = -1;
-        if (vals) launch_fused_t<IPT, SS_FINE_GRAY, true, false>(b, ws, ntiles, s);
-        else      launch_fused_t<IPT, SS_FINE_GRAY, false, false>(b, ws, ntiles, s);
+        // the carry of the weighted totals needs a 0/1 design
+        const bool carry = a.jnext >= 0;
+        if ((carry || a.fg_have_totals) && vals) return SS_EUNSUPPORTED;
+        bool prev_scan = prev;
+        if (!a.fg_have_totals) {
+            // totals pass (and the pending a1 update), then the scan pass
+            launch_fg_totals_t<IPT>(a, ws, ntiles, vals, prev, s);
+            SS_LAUNCH_CHECK();
+            b.jprev = -1;
+            b.clear_error = 0;
+            prev_scan = false;
+        }
+        if (vals) {
+            launch_fused_t<IPT, SS_FINE_GRAY, true, false>(b, ws, ntiles, s);
+        } else if (carry) {
+            if (prev_scan) launch_fused_t<IPT, SS_FINE_GRAY, false, true, true>(b, ws, ntiles, s);
+            else           launch_fused_t<IPT, SS_FINE_GRAY, false, false, true>(b, ws, ntiles, s);
+        } else {
+            if (prev_scan) launch_fused_t<IPT, SS_FINE_GRAY, false, true>(b, ws, ntiles, s);
+            else           launch_fused_t<IPT, SS_FINE_GRAY, false, false>(b, ws, ntiles, s);
+        }
     } else {
         if (vals) {
             if (prev) launch_fused_t<IPT, SS_COX, true, true>(b, ws, ntiles, s);

@@ -150,6 +150,7 @@ __device__ __forceinline__ void lds_bytes(const uint8_t *p, uint8_t (&b)[IPT])
 // LDS flag bits per tile position.
 constexpr uint8_t kFlagX = 1;      // column j has a non-zero here
 constexpr uint8_t kFlagPatch = 2;  // the pending step changed e here
+constexpr uint8_t kFlagNext = 4;   // the next column has a non-zero here
 
 __device__ __forceinline__ void lds_flag_or(uint8_t *s_flag, int32_t r, uint8_t bit)
 {

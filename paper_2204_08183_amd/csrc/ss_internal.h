@@ -21,8 +21,8 @@ int32_t record_hip_error(hipError_t err);
     } while (0)
 #define SS_LAUNCH_CHECK() SS_HIP_CHECK(hipGetLastError())
 
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ------------------------------------------------------------ device helpers
 // Cross-workgroup exchange on gfx950.  The eight XCDs of an MI355X each have
@@ -92,7 +92,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Layout of the workspace (every region 256-byte aligned), T = max_tiles
 // and U = ceil(T / kGroup) + 1 tile groups:
-//   WsHeader | lb[T][8] | part[T][4] | fg_part[T][4] | gpart[U][4] |
+//   WsHeader | lb[T][8] | part[T][8] | fg_part[T][4] | gpart[U][8] |
 //   fg_gpart[U][4] | sw_agg[T][8] | sw_part[T][4] | sw_step[T] |
 //   sw_pre[T][8] | sw_pub[max(T, 2 kMaxSweepBlocks)][16]
 struct alignas(256) WsHeader {
@@ -124,9 +124,9 @@ constexpr uint32_t kSpinLimit = 1u << 20;
 struct WsView {
     WsHeader *hdr;
     u32x4 *lb;        // [max_tiles][8]  look-back (aggregate / inclusive prefix)
-    u32x4 *part;      // [max_tiles][4]  per-tile partial sums
+    u32x4 *part;      // [max_tiles][8]  per-tile partial sums
     u32x4 *fg_part;   // [max_tiles][4]  Fine-Gray totals pass, per tile
-    u32x4 *gpart;     // [groups][4]     per-group partial sums
+    u32x4 *gpart;     // [groups][8]     per-group partial sums
     u32x4 *fg_gpart;  // [groups][4]
     // persistent sweep
     u32x4 *sw_agg;    // [max_tiles][8]
@@ -147,8 +147,49 @@ __device__ __forceinline__ uint64_t *trace_base(const WsView &ws)
 }
 #endif
 
-size_t fused_ws_bytes(int64_t n);
+// Bytes of the workspace for problems of up to n positions (the layout
+// above; tiles are at least SS_CHUNK positions).
+constexpr size_t fused_ws_bytes(int64_t n)
+{
+    const int64_t tiles = ceil_div(n, SS_CHUNK) + 1;
+    const int64_t groups = ceil_div(tiles, kGroup) + 1;
+    const int64_t npub = tiles > 2 * kMaxSweepBlocks ? tiles : 2 * kMaxSweepBlocks;
+    size_t b = sizeof(WsHeader);
+    b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // lb
+    b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // part
+    b = align_up(b + 16 * 4 * (size_t)tiles, 256);   // fg_part
+    b = align_up(b + 16 * 8 * (size_t)groups, 256);  // gpart
+    b = align_up(b + 16 * 4 * (size_t)groups, 256);  // fg_gpart
+    b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // sw_agg
+    b = align_up(b + 16 * 4 * (size_t)tiles, 256);   // sw_part
+    b = align_up(b + 16 * (size_t)tiles, 256);       // sw_step
+    b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // sw_pre
+    b = align_up(b + 16 * 16 * (size_t)npub, 256);   // sw_pub
+#ifdef SS_TRACE_TIMES
+    b = align_up(b + sizeof(uint64_t) * 64 * (size_t)tiles, 256);
+#endif
+    return b;
+}
 bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v);
+
+// ------------------------------------------------------------ argument checks
+inline bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+// The fused kernels read e, w_comp and g_end with 16-byte loads and d8 with
+// 8-byte loads.
+inline bool model_arrays_ok(int32_t model, const double *e, const uint8_t *d8,
+                            const int32_t *d32, const double *w_comp,
+                            const double *g_end)
+{
+    if (!e || !d8 || !d32) return false;
+    if (!aligned(e, 16) || !aligned(d8, 8)) return false;
+    if (model == SS_FINE_GRAY) {
+        if (!w_comp || !g_end) return false;
+        if (!aligned(w_comp, 16) || !aligned(g_end, 16)) return false;
+    }
+    return true;
+}
+
 
 // ------------------------------------------------------------ launchers
 struct Column {
@@ -185,6 +226,22 @@ struct FusedCall {
     // likelihood mode: out[0] = beta' c - sum d log S0
     const double *beta_ll;
     int32_t want_log;
+    // objective mode (with beta_ll): obj_penalty >= 0 writes out[0] = l + pi,
+    // out[1] = l, out[2] = pi with pi the penalty of Sec. 2.3 at beta_ll
+    int32_t obj_penalty;
+    double obj_lambda;
+    // Fine-Gray with a 0/1 design inside a sweep: the totals
+    // sum e w x^m over column j are in hdr->fg_tot already (fg_have_totals,
+    // carried by the previous launch), and jnext >= 0 asks the last tile to
+    // carry the totals of column jnext over the e this coordinate's step
+    // leaves behind
+    int32_t fg_have_totals;
+    int32_t jnext;
+    // error reporting of calls without a caller-owned workspace: the first
+    // tile of the call's first launch clears the error word, the last tile
+    // of its last launch copies it to *err_out (0.0 or 1.0)
+    int32_t clear_error;
+    double *err_out;
 };
 
 int32_t launch_fused(const FusedCall &call, const WsView &ws,
@@ -255,6 +312,8 @@ int32_t launch_cv_loglik(int32_t model, int64_t n, int32_t reps, const int32_t *
                          const int8_t *status, const double *eta, const double *e,
                          const uint8_t *train_s, const uint8_t *d8, const int32_t *d32,
                          const uint8_t *d8_r, const int32_t *d32_r, double *out, hipStream_t s);
+int32_t launch_cv_select(int32_t n_gamma, int32_t reps, const double *scores, double *mean,
+                         int32_t *best, hipStream_t s);
 int32_t launch_mixed(int32_t acc, int32_t model, int64_t n, int64_t p, int32_t j,
                      const float *e32, const uint8_t *d8, const int32_t *d32,
                      const double *w_comp, const double *g_end, const Column &col,

@@ -1,5 +1,5 @@
 // Persistent cyclic-coordinate-descent sweep for gfx950: the workflow of
-// Fig. 4 (sparse update -> fused gradient/Hessian -> conditional update,
+// Fig. 3 (sparse update -> fused gradient/Hessian -> conditional update,
 // for j = 1..P) in ONE cooperative launch, with no host round trip and no
 // per-coordinate launch.
 //

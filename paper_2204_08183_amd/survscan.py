@@ -74,6 +74,9 @@ SIGNATURES = {
                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_cv_loglik": (_i32, [_i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                             _vp, _vp]),
+    "ss_objective": (_i32, [_i32, _i32, _f64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                            _vp, _vp, _sz, _vp]),
+    "ss_cv_select": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp]),
     "ss_gather_u8": (_i32, [_i64, _vp, _vp, _vp, _vp]),
     "ss_eta_gradient_workspace_bytes": (_sz, [_i64]),
     "ss_eta_gradient": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -296,27 +299,29 @@ class Problem:
                                         _stream(self.device)), "ss_workspace_error")
         return int(flag.value)
 
-    def objective(self, penalty="none", lam=0.0):
-        """l(beta) + pi(beta) at the current state (Sec. 2.3), with eta = X beta;
-        l from ss_loglik, the penalty of the P coefficients on the host."""
-        l = float(self.loglik().cpu()[0])
-        b = self.beta.cpu()
-        if penalty == "l1":
-            return l - lam * float(b.abs().sum())
-        if penalty == "l2":
-            return l - float((b * b).sum()) / (2.0 * lam)
-        return l
+    def objective(self, penalty="none", lam=0.0, out=None):
+        """(l + pi, l, pi) at the current state (Secs. 2.3-2.4), with
+        eta = X beta, as a device tensor [3] (ss_objective)."""
+        out = torch.empty(3, dtype=torch.float64, device=self.device) if out is None else out
+        rc = load().ss_objective(self.model, PENALTIES[penalty], float(lam), self.n, self.p,
+                                 _p(self.e), _p(self.d8), _p(self.d32), _p(self.w_comp),
+                                 _p(self.g_end), _p(self.beta), _p(self.c), _p(out),
+                                 self.ws.ptr, self.ws.nbytes, _stream(self.device))
+        check(rc, "ss_objective")
+        return out
 
-    def fit(self, penalty="l1", lam=0.0, max_sweeps=100, tol=1e-10):
+    def fit(self, penalty="none", lam=0.0, max_sweeps=100, tol=1e-10):
         """Cyclic coordinate descent to convergence (Secs. 2.3-2.4, the
         GPU-resident workflow of the Sec. 2.7 figure): whole sweeps on the
         device until the relative change of the penalised log-likelihood,
         |f - f_prev| / (|f| + 1), falls below `tol` (the stopping rule is
         not fixed by the paper).  Returns the number of sweeps taken."""
-        f_prev = self.objective(penalty, lam)
+        f_prev = float(self.objective(penalty, lam)[0])
         for k in range(1, max_sweeps + 1):
             self.sweep(penalty, lam)
-            f = self.objective(penalty, lam)
+            f = float(self.objective(penalty, lam)[0])
+            if self.workspace_error():
+                raise SurvScanError("fit: a bounded wait of the sweep gave up")
             if abs(f - f_prev) / (abs(f) + 1.0) < tol:
                 return k
             f_prev = f
@@ -422,16 +427,23 @@ def cv_path(prob, train, gammas, sweeps=5, penalty="l1"):
     gamma with the largest mean (reading: larger predictive likelihood is
     better)."""
     cvp = CrossValidation(prob, train)
-    rows = []
-    for g in gammas:
+    dev = prob.device
+    ng = len(gammas)
+    table = torch.empty(ng, 2 * cvp.reps, dtype=torch.float64, device=dev)
+    for k, g in enumerate(gammas):
         for _ in range(sweeps):
             cvp.sweep(penalty, float(g))
-        rows.append(cvp.loglik()[:, 1].cpu())
+        cvp.loglik(out=table[k])
     if cvp.workspace_error():
         raise SurvScanError("cross-validation: a bounded wait gave up")
-    scores = torch.stack(rows).numpy()
-    best = gammas[int(scores.mean(axis=1).argmax())]
-    return scores, best
+    mean = torch.empty(ng, dtype=torch.float64, device=dev)
+    best = torch.empty(1, dtype=torch.int32, device=dev)
+    check(load().ss_cv_select(ng, cvp.reps, _p(table), _p(mean), _p(best), _stream(dev)),
+          "ss_cv_select")
+    b = int(best.cpu()[0])
+    if b < 0:
+        raise SurvScanError("cross-validation: every mean held-out score is NaN")
+    return table[:, 1::2].cpu().numpy(), gammas[b]
 
 
 class LogLikEta(torch.autograd.Function):

@@ -133,7 +133,10 @@ def test_new_entry_points_validate_on_the_host(lib):
     sw = [f] * 9 + [None, f, big, None]
     assert lib.ss_cv_sweep(1, 0, 0.0, 1000, 5, 10, 0, 5, *sw) == ss.SS_EUNSUPPORTED
     assert lib.ss_cv_sweep(0, 0, 0.0, 1000, 5, 10, 0, 6, *sw) == ss.SS_EINVAL
-    assert lib.ss_cv_sweep(0, 3, 0.0, 1000, 5, 10, 0, 5, *sw) == ss.SS_EINVAL
+    assert lib.ss_cv_sweep(0, 3, 0.0, 1000, 5, 10, 0, 5, *sw) == ss.SS_EUNSUPPORTED
+    # a penalty needs a positive strength (l2: the prior variance; l1: gamma)
+    assert lib.ss_cv_sweep(0, 2, 0.0, 1000, 5, 10, 0, 5, *sw) == ss.SS_EINVAL
+    assert lib.ss_cv_sweep(0, 1, -1.0, 1000, 5, 10, 0, 5, *sw) == ss.SS_EINVAL
     assert lib.ss_cv_sweep(0, 0, 0.0, 1000, 5, 70000, 0, 5, *sw) == ss.SS_EINVAL
     small = sw[:-2] + [16, None]
     assert lib.ss_cv_sweep(0, 0, 0.0, 1000, 5, 10, 0, 5, *small) == ss.SS_EWORKSPACE

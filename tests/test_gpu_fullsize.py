@@ -58,6 +58,7 @@ def test_ipt16_fine_gray_matches_oracle():
     want = pr.coordinate(eta, x)
     assert abs(got[0] - want["g1"]) <= TOL * want["scale_g1"], (got[0], want["g1"])
     assert abs(got[1] - want["g2"]) <= TOL * want["scale_g2"], (got[1], want["g2"])
+    assert abs(got[2] - want["L"]) <= TOL * want["scale_L"], (got[2], want["L"])
     assert prob.workspace_error() == 0
 
 

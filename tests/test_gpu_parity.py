@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import gen
-from oracle import ccd as occd, km as okm, prep as oprep, risk, scan as oscan
+from oracle import ccd as occd, cv as ocv, km as okm, prep as oprep, risk, scan as oscan
 
 pytestmark = pytest.mark.gpu
 
@@ -156,6 +156,32 @@ def test_grad_hess_matches_oracle(model, n, p, seed, ties, density, valued, stat
     assert prob.workspace_error() == 0
 
 
+# Above 1,572,864 positions the fused kernel runs tiles of 4096 positions
+# (16 per thread).  Tie runs of every length cross those tile boundaries, and
+# with 3000 distinct times most runs hold more than 255 events, so the event
+# counts of a run end take the 32-bit escape.
+LARGE_TIE_CASES = [
+    # n, p, seed, ties, density, valued
+    (2_000_003, 3, 24, 3000, 0.05, False),
+    (1_900_000, 2, 25, 400_000, 0.3, True),
+]
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+@pytest.mark.parametrize("n,p,seed,ties,density,valued", LARGE_TIE_CASES)
+def test_grad_hess_large_tiles_with_ties(model, n, p, seed, ties, density, valued):
+    c = make_case(model, n, p, seed, ties, density, valued)
+    prob = gpu_problem(model, c)
+    d32 = prob.d32.cpu().numpy()
+    if ties == 3000:
+        assert np.count_nonzero(d32 >= 255) > 100
+    pr = oscan.Prepared(model, c["y"], c["status"])
+    for j in range(p):
+        got = prob.grad_hess(j).cpu().numpy()
+        assert_coord(got, oracle_coord(model, c, j, pr), (model, n, j))
+    assert prob.workspace_error() == 0
+
+
 @pytest.mark.parametrize("model", ["cox", "fg"])
 def test_empty_column(model):
     c = make_case(model, 3000, 2, 30, 0, 0.05)
@@ -200,6 +226,52 @@ def test_loglik_matches_oracle(model, n, ties):
     assert abs(got - want) <= TOL * scale
 
 
+@pytest.mark.parametrize("model", ["cox", "fg"])
+@pytest.mark.parametrize("penalty,lam", [("none", 0.0), ("l1", 1.5), ("l2", 0.7)])
+def test_objective_matches_oracle(model, penalty, lam):
+    """ss_objective: l + pi on the device against the oracle's likelihood
+    (O(N^2) definition) and penalty (Sec. 2.3)."""
+    n, p = 1800, 6
+    c = make_case(model, n, p, 41, 20, 0.1, valued=True)
+    rng = np.random.default_rng(2)
+    beta = rng.normal(0, 0.4, p)
+    beta[2] = 0.0
+    c["eta"] = gen.linear_predictor(n, c["col_ptr"], c["rows"], c["vals"], beta)
+    prob = gpu_problem(model, c)
+    prob.beta.copy_(torch.as_tensor(beta))
+    got = prob.objective(penalty, lam).cpu().numpy()
+    pen = {"none": occd.PENALTY_NONE, "l1": occd.PENALTY_L1, "l2": occd.PENALTY_L2}[penalty]
+    want_l = float(risk.loglik(model, c["y"], c["status"], c["eta"]))
+    want_pi = occd.penalty_value(beta, pen, lam)
+    r = risk.brute(model, c["y"], c["status"], c["eta"], np.zeros(n))
+    scale = float(np.sum(np.abs(np.log(r["S0"])))) + abs(want_l) + abs(want_pi)
+    assert abs(got[1] - want_l) <= TOL * scale, (got[1], want_l)
+    assert abs(got[2] - want_pi) <= 1e-14 * (abs(want_pi) + 1.0), (got[2], want_pi)
+    assert abs(got[0] - (want_l + want_pi)) <= TOL * scale
+    assert prob.workspace_error() == 0
+
+
+def test_cv_select_by_hand():
+    """ss_cv_select: per-strength means of the held-out scores (the odd
+    entries of each row) and the first strength with the largest mean."""
+    lib = ss.load()
+    reps = 3
+    # rows: (train, held-out) pairs per replicate; held-out means -2, -1, -1, NaN
+    table = np.array([[9.0, -1.0, 9.0, -2.0, 9.0, -3.0],
+                      [0.0, -1.0, 0.0, -1.0, 0.0, -1.0],
+                      [5.0, -0.5, 5.0, -1.5, 5.0, -1.0],
+                      [0.0, float("nan"), 0.0, 1.0, 0.0, 1.0]])
+    t = torch.as_tensor(table, device=DEV)
+    mean = torch.empty(4, dtype=torch.float64, device=DEV)
+    best = torch.full((1,), 7, dtype=torch.int32, device=DEV)
+    s = ss._stream(torch.device(DEV))
+    assert lib.ss_cv_select(4, reps, ss._p(t), ss._p(mean), ss._p(best), s) == ss.SS_OK
+    m = mean.cpu().numpy()
+    np.testing.assert_array_equal(m[:3], [-2.0, -1.0, -1.0])
+    assert np.isnan(m[3])
+    assert int(best.cpu()[0]) == 1
+
+
 # ------------------------------------------------------------------ a3 + a1
 @pytest.mark.parametrize("penalty,lam,g1,g2,b,dj", [
     ("none", 0.0, 3.0, -2.0, 0.1, 1.0), ("none", 0.0, 3.0, -2.0, 0.1, 0.25),
@@ -230,20 +302,10 @@ def test_ccd_update_matches_oracle(penalty, lam, g1, g2, b, dj):
 
 # ------------------------------------------------------------------ fused sweep
 def oracle_sweeps(model, c, penalty, lam, sweeps):
-    pr = oscan.Prepared(model, c["y"], c["status"])
-    eta = c["eta"].copy()
-    beta = np.zeros(c["p"])
-    delta = np.ones(c["p"])
-    hist = []
-    for _ in range(sweeps):
-        for j in range(c["p"]):
-            x = xcol(c, j)
-            r = pr.coordinate(eta, x)
-            beta[j], delta[j], step = occd.update(r["g1"], r["g2"], beta[j], delta[j],
-                                                 penalty, lam)
-            eta = eta + step * x
-            hist.append((r["g1"], r["g2"], r["scale_g1"], r["scale_g2"]))
-    return beta, delta, eta, hist
+    """The oracle's CCD loop (oracle.cv.ccd_sweeps, pinned on the CPU) from
+    beta = 0 at the case's eta."""
+    return ocv.ccd_sweeps(model, c["y"], c["status"], c["col_ptr"], c["rows"], c["vals"],
+                          c["eta"], penalty, lam, sweeps)
 
 
 SWEEP_PATHS = ["persistent", "launch"]
@@ -290,6 +352,7 @@ def test_sweep_matches_oracle_ccd(model, penalty, lam, path, monkeypatch):
     (2_500_003, 4, 0, True),      # segments of 8192, ragged last segment
     (300_001, 5, 40, False),      # tie runs across segment boundaries
     (4_300_000, 3, 0, False),     # above the persistent limit: launch per coordinate
+    (2_000_003, 3, 3000, False),  # 4096-position tiles, runs of 255+ events
 ])
 def test_sweep_large(model, n, p, ties, valued, path, monkeypatch):
     _sweep_env(monkeypatch, path)
@@ -348,6 +411,7 @@ def test_fit_reaches_kkt(model, penalty, lam):
     prob = gpu_problem(model, c)
     sweeps = prob.fit(penalty, lam, max_sweeps=300, tol=1e-15)
     assert sweeps < 300
+    assert prob.workspace_error() == 0
     beta = prob.beta.cpu().numpy()
     pen = {"l1": occd.PENALTY_L1, "l2": occd.PENALTY_L2}[penalty]
     b_or, _, _, _ = oracle_sweeps(model, c, pen, lam, sweeps)
