@@ -252,7 +252,9 @@ def test_cv_rejects_unsupported():
                            *args) == ss.SS_EUNSUPPORTED
     assert lib.ss_cv_sweep(ss.COX, 0, 0.0, prob.n, prob.p, 3, 0, 3, *args) == ss.SS_EINVAL
     assert lib.ss_cv_sweep(ss.COX, 0, 0.0, prob.n, prob.p, 0, 0, 2, *args) == ss.SS_EINVAL
-    assert lib.ss_cv_sweep(ss.COX, 9, 0.0, prob.n, prob.p, 3, 0, 2, *args) == ss.SS_EINVAL
+    assert lib.ss_cv_sweep(ss.COX, 9, 0.0, prob.n, prob.p, 3, 0, 2, *args) == ss.SS_EUNSUPPORTED
+    assert lib.ss_cv_sweep(ss.COX, 1, 0.0, prob.n, prob.p, 3, 0, 2, *args) == ss.SS_EINVAL
+    assert lib.ss_cv_sweep(ss.COX, 2, -1.0, prob.n, prob.p, 3, 0, 2, *args) == ss.SS_EINVAL
     # an empty coordinate range is a no-op that still resynchronises e
     assert lib.ss_cv_sweep(ss.COX, 0, 0.0, prob.n, prob.p, 3, 1, 1, *args) == ss.SS_OK
     short = args[:-3] + [cvp.ws.ptr, cvp.ws.nbytes - 1, None]
