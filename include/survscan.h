@@ -400,6 +400,33 @@ int32_t ss_cv_loglik(int32_t model, int64_t n, int32_t reps,
 int32_t ss_cv_select(int32_t n_gamma, int32_t reps, const double *scores,
                      double *mean, int32_t *best, void *stream);
 
+/* ---------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as ss_grad_hess, with the fused kernels' scratch (look-back
+ * pairs, per-tile partial sums, launch counters) in a file-scope device
+ * array of ss_noalloc_scratch_bytes() bytes instead of a caller workspace.
+ * Each GPU the library runs on holds its own copy until the process ends;
+ * the first call on a device looks up its address and clears it (a fill
+ * kernel on `stream`).  No allocation happens in any call.
+ *   n at most SS_NOALLOC_MAX_N (larger: SS_EINVAL); `stream` must belong
+ *   to the current device (else SS_EINVAL); other arguments and out[0..2]
+ *   as ss_grad_hess; out[3] (device) = 1.0 if a bounded wait of this call
+ *   gave up (results invalid), else 0.0.
+ * Every call on one GPU shares that GPU's array, which keeps the last
+ * call's contents: calls that overlap on one GPU (several streams, several
+ * host threads) race and must be serialised by the caller. */
+#define SS_NOALLOC_MAX_N ((int64_t)1 << 25)
+size_t ss_noalloc_scratch_bytes(void);
+int32_t ss_grad_hess_noalloc(int32_t model, int64_t n, int64_t p, int64_t j,
+                             const double *e, const uint8_t *d8,
+                             const int32_t *d32, const double *w_comp,
+                             const double *g_end, const int64_t *col_ptr,
+                             const int32_t *rows_sorted,
+                             const double *vals_sorted,
+                             const int32_t *chunk_ptr, const double *c,
+                             double *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

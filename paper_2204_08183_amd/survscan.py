@@ -78,6 +78,9 @@ SIGNATURES = {
                             _vp, _vp, _sz, _vp]),
     "ss_cv_select": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp]),
     "ss_gather_u8": (_i32, [_i64, _vp, _vp, _vp, _vp]),
+    "ss_noalloc_scratch_bytes": (_sz, []),
+    "ss_grad_hess_noalloc": (_i32, [_i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    _vp, _vp, _vp, _vp, _vp, _vp]),
     "ss_eta_gradient_workspace_bytes": (_sz, [_i64]),
     "ss_eta_gradient": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                _vp, _sz, _vp]),
