@@ -19,6 +19,8 @@ One JSON line is printed.  Besides the throughput it carries
   paper_sizes   the fused kernel at N = 1e5 ... 1e6 and the sweeps at
                 N = 1e5 (latency-bound sizes, not an HBM fraction);
   eta_gradient  the full gradient in eta at N = 1e6 and 2^27;
+  fit           the l1 fits of both models to convergence at N = 1e6, with
+                the largest violation of the optimality conditions;
   cv            10-fold x 10-repetition cross-validation (100 replicates) at
                 N = 1e5, P = 1000: one l1 sweep of every replicate in one
                 launch, next to one replicate-sized problem swept alone
@@ -59,7 +61,7 @@ def parse():
     ap.add_argument("--no-cv", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--only", choices=["cv", "eta_gradient"],
+    ap.add_argument("--only", choices=["cv", "eta_gradient", "fit"],
                     help="only run one of the secondary measurements (for profiling)")
     return ap.parse_args()
 
@@ -237,6 +239,40 @@ def cross_validation(torch, ss, gen):
             "speedup_vs_one_at_a_time": round(100 * us_one / us_cv, 2)}
 
 
+def fit_to_convergence(torch, ss, cox, fg, tol=1e-15):
+    """Sec. 3.2 / Fig. 5 at the paper's largest size: the l1 fit (gamma =
+    sqrt 2) of both models from beta = 0 to convergence (relative change of
+    the penalised log-likelihood below `tol` over a sweep), whole sweeps on
+    the GPU; then the largest violation of the optimality conditions over
+    all coordinates, in units of |g''_j| (what is left of a Newton step)."""
+    import numpy as np
+    gamma = math.sqrt(2.0)
+    res = {}
+    for model, d in (("cox", cox), ("fg", fg)):
+        prob = ss.Problem(model, d["y"], d["status"], d["col_ptr"], d["rows"], None,
+                          "cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sweeps = prob.fit("l1", gamma, max_sweeps=400, tol=tol)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        beta = prob.beta.cpu().numpy()
+        g = torch.empty((d["p"], 3), dtype=torch.float64, device="cuda:0")
+        for j in range(d["p"]):
+            prob.grad_hess(j, out=g[j])
+        g = g.cpu().numpy()
+        zero = beta == 0.0
+        viol = np.where(zero, np.abs(g[:, 0]) - gamma,
+                        np.abs(g[:, 0] - gamma * np.sign(beta))) / np.abs(g[:, 1])
+        res[model] = {"sweeps": int(sweeps), "seconds": round(secs, 4),
+                      "nonzero_coefficients": int(np.count_nonzero(~zero)),
+                      "kkt_max_violation_over_abs_g2": float(np.max(viol)),
+                      "wait_errors": prob.workspace_error()}
+        del prob
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(gen, cox, fg, coords):
     """The oracle as it stands: serial C scan per coordinate + CCD update."""
     import numpy as np
@@ -348,6 +384,9 @@ def main():
                                                                    args.density))
     cox = gen.cox_data(0, args.n, args.p, args.density)
     fg = gen.fg_data(0, args.n, args.p, args.density)
+    if args.only == "fit":
+        print(json.dumps({"fit": fit_to_convergence(torch, ss, cox, fg)}), flush=True)
+        return
     t0 = time.perf_counter()
     pc = ss.Problem("cox", cox["y"], cox["status"], cox["col_ptr"], cox["rows"], None,
                     "cuda:0")
@@ -424,9 +463,18 @@ def main():
     if not args.no_cv:
         log("cross-validation: 100 replicates, N=1e5, P=1000")
         line["cv"] = cross_validation(torch, ss, gen)
+    if not args.no_context:
+        log("l1 fits to convergence, N=%d, P=%d" % (args.n, args.p))
+        line["fit"] = fit_to_convergence(torch, ss, cox, fg)
     if not args.no_cpu:
         log("cpu baseline (oracle) on %d coordinates per model" % args.cpu_coords)
         line["cpu_baseline"] = cpu_baseline(gen, cox, fg, args.cpu_coords)
+        if "fit" in line:
+            # the oracle's coordinate rate times the fits' coordinate count
+            cps = line["cpu_baseline"]["value"]
+            for m in ("cox", "fg"):
+                f = line["fit"][m]
+                f["oracle_seconds_extrapolated_1_core"] = round(f["sweeps"] * args.p / cps, 1)
         log("cpu baseline (oracle) on all host cores")
         line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(gen, cox)
         host = host_cpu()
