@@ -15,6 +15,7 @@ One JSON line is printed.  Besides the throughput it carries
   cpu_baseline  the FP64 oracle (serial C scan) on a bounded sample, one
                 thread; cpu_baseline_all_cores: the same scan on every host
                 core, coordinates in parallel;
+  precision     FP32 storage of e in the same single-pass kernel at N = 2^27;
   context       our fused kernel at N = 1e5 next to the paper's GV100 time;
   paper_sizes   the fused kernel at N = 1e5 ... 1e6 and the sweeps at
                 N = 1e5 (latency-bound sizes, not an HBM fraction);
@@ -61,7 +62,7 @@ def parse():
     ap.add_argument("--no-cv", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--only", choices=["cv", "eta_gradient", "fit"],
+    ap.add_argument("--only", choices=["cv", "eta_gradient", "fit", "precision"],
                     help="only run one of the secondary measurements (for profiling)")
     return ap.parse_args()
 
@@ -123,6 +124,45 @@ def roofline(torch, ss, gen, n, reps):
             "algo_bytes_per_launch": algo, "avg_us": round(us, 2), "reps": reps,
             "copy_peak_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
             "wait_errors": err}
+
+
+def precision(torch, ss, gen, n, reps):
+    """FP32 storage of e in the single-pass fused kernel against the FP64
+    kernel at N = 2^27, on a 0/1 column at 5% density (the Sec. 3.2
+    design's column; e ~ U(1,2), delta ~ Bernoulli(0.5)) and on the dense
+    valued column of the roofline workload.  Algorithmic bytes per launch:
+    e (8 or 4) and the event count (1) per subject, plus 4 per non-zero
+    (+ 8 for a value)."""
+    res = {}
+    for label, density, valued in (("01_col_5pct", 0.05, False), ("dense_valued", 1.0, True)):
+        u = gen.uniform_tuple_data(1, n, density)
+        prob = ss.Problem("cox", u["y"], u["status"], u["col_ptr"], u["rows"],
+                          u["vals"] if valued else None, "cuda:0")
+        prob.set_eta(u["eta"])
+        nnz = int(u["rows"].size)
+        del u
+        e32, _ = prob.make_e32()
+        out = torch.empty(3, dtype=torch.float64, device="cuda:0")
+        col = nnz * (4 + (8 if valued else 0))
+        row = {}
+        for name, fn, se in (("f64", lambda: prob.grad_hess(0, out=out), 8),
+                             ("f32_storage_f64_sums",
+                              lambda: prob.grad_hess_f32(0, e32, "f64", out), 4),
+                             ("f32_storage_f32_tile_sums_f64_carry",
+                              lambda: prob.grad_hess_f32(0, e32, "f32x64", out), 4)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            us = event_time_us(torch, fn, reps)
+            algo = n * (se + 1) + col
+            row[name] = {"avg_us": round(us, 2), "algo_bytes_per_launch": algo,
+                         "achieved_gbs": round(algo / (us * 1e-6) / 1e9, 1),
+                         "frac": round(algo / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+        row["wait_errors"] = prob.workspace_error()
+        res[label] = row
+        del prob, e32
+        torch.cuda.empty_cache()
+    return res
 
 
 def copy_peak_gbs(torch):
@@ -376,6 +416,10 @@ def main():
     if args.only == "cv":
         print(json.dumps({"cv": cross_validation(torch, ss, gen)}), flush=True)
         return
+    if args.only == "precision":
+        print(json.dumps({"precision": precision(torch, ss, gen, args.roof_n, args.roof_reps)}),
+              flush=True)
+        return
     if args.only == "eta_gradient":
         print(json.dumps({"eta_gradient": eta_gradient(torch, ss, gen)}), flush=True)
         return
@@ -452,6 +496,9 @@ def main():
     }
     if not args.no_roofline:
         line["roofline"] = roofline(torch, ss, gen, args.roof_n, args.roof_reps)
+    if not args.no_roofline:
+        log("FP32 storage of e at N=%d" % args.roof_n)
+        line["precision"] = precision(torch, ss, gen, args.roof_n, args.roof_reps)
     if not args.no_context:
         line["context"] = context(torch, ss, gen)
     if not args.no_context:

@@ -255,6 +255,31 @@ int32_t ss_gather(int64_t n, const int32_t *perm, const double *src,
  * SS_EWORKSPACE as ss_grad_hess. */
 int32_t ss_exp_f32(int64_t n, const double *eta, float *e32, double *shift,
                    void *ws, size_t ws_bytes, void *stream);
+
+/* ss_grad_hess_f32: FP32 storage of e inside the single-pass fused kernel
+ * of ss_grad_hess (Sec. 2.7, Fig. 2: one pass with decoupled look-back), so
+ * that a coordinate streams 4 instead of 8 bytes of e per subject.  Same
+ * outputs as ss_grad_hess_mixed (S0 as e32 gives it, i.e. shifted), with
+ * `acc`:
+ *   SS_ACC_F64      every sum, the transform and the reduction in FP64
+ *                   (only the storage of e is FP32);
+ *   SS_ACC_F32_C64  the sums inside a tile (thread-serial and wave scans),
+ *                   the transform and each thread's share of the reduction
+ *                   in FP32; the tile aggregates, the look-back prefix each
+ *                   tile starts from (its carry), the Fine-Gray totals and
+ *                   the sum of the tile partials in FP64 (Sec. 2.7 step (4)
+ *                   accumulates in double; the paper fixes no other
+ *                   precision).
+ * Other modes: SS_EINVAL (see ss_grad_hess_mixed).  e32 must be 16-byte
+ * aligned (SS_EINVAL otherwise); other arguments, the workspace and the
+ * non-determinism in the last bits as for ss_grad_hess. */
+int32_t ss_grad_hess_f32(int32_t model, int32_t acc, int64_t n, int64_t p,
+                         int64_t j, const float *e32, const uint8_t *d8,
+                         const int32_t *d32, const double *w_comp,
+                         const double *g_end, const int64_t *col_ptr,
+                         const int32_t *rows_sorted, const double *vals_sorted,
+                         const int32_t *chunk_ptr, const double *c,
+                         double *out, void *ws, size_t ws_bytes, void *stream);
 int32_t ss_grad_hess_mixed(int32_t model, int32_t acc, int64_t n, int64_t p,
                            int64_t j, const float *e32, const uint8_t *d8,
                            const int32_t *d32, const double *w_comp,

@@ -348,6 +348,44 @@ int32_t ss_grad_hess_mixed(int32_t model, int32_t acc, int64_t n, int64_t p, int
                         (hipStream_t)stream);
 }
 
+int32_t ss_grad_hess_f32(int32_t model, int32_t acc, int64_t n, int64_t p, int64_t j,
+                         const float *e32, const uint8_t *d8, const int32_t *d32,
+                         const double *w_comp, const double *g_end, const int64_t *col_ptr,
+                         const int32_t *rows_sorted, const double *vals_sorted,
+                         const int32_t *chunk_ptr, const double *c, double *out, void *ws,
+                         size_t ws_bytes, void *stream)
+{
+    if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
+    if (acc != SS_ACC_F64 && acc != SS_ACC_F32_C64) return SS_EINVAL;
+    if (bad_size(n, p) || j < 0 || j >= p) return SS_EINVAL;
+    if (!e32 || !aligned(e32, 16) || !d8 || !aligned(d8, 8) || !d32) return SS_EINVAL;
+    if (model == SS_FINE_GRAY &&
+        (!w_comp || !g_end || !aligned(w_comp, 16) || !aligned(g_end, 16)))
+        return SS_EINVAL;
+    if (!col_ptr || !rows_sorted || !chunk_ptr || !c || !out) return SS_EINVAL;
+    WsView v;
+    if (!fused_ws_view(ws, ws_bytes, n, &v)) return SS_EWORKSPACE;
+    FusedCall a = {};
+    a.model = model;
+    a.n = n;
+    a.p = p;
+    a.j = (int32_t)j;
+    a.jprev = -1;
+    a.jnext = -1;
+    a.e32 = e32;
+    a.f32_sums = acc == SS_ACC_F32_C64;
+    a.d8 = d8;
+    a.d32 = d32;
+    a.w_comp = w_comp;
+    a.g_end = g_end;
+    a.col = column(col_ptr, rows_sorted, vals_sorted, chunk_ptr, n);
+    a.c = c;
+    a.out = out;
+    a.want_log = 1;
+    a.obj_penalty = -1;
+    return launch_fused(a, v, (hipStream_t)stream);
+}
+
 size_t ss_eta_gradient_workspace_bytes(int64_t n)
 {
     if (n < 1 || n > INT32_MAX) return 0;

@@ -20,6 +20,7 @@
 // grand total minus the inclusive prefix of the weighted components; the
 // totals come from a short reduction pass launched just before.
 #include <algorithm>
+#include <type_traits>
 
 #include "ss_device.h"
 
@@ -403,17 +404,19 @@ __device__ __forceinline__ int32_t lds_slot(int32_t r)
 // NEXT: the 0/1 column jnext also goes to the flags; its bits are returned
 // in *nbits.
 template <int BLOCK, int IPT, bool WANT_W, bool VALS, bool PREV, bool WANT_D,
-          bool NEXT = false>
+          bool NEXT = false, typename ET = double>
 __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, int64_t cnt,
                                                int64_t chunk0, int64_t chunk1,
                                                uint8_t *s_flag, double *s_xv, double *s_ep,
-                                               double (&ev)[IPT],
+                                               ET (&ev)[IPT],
                                                double (&wv)[WANT_W ? IPT : 1],
                                                uint32_t (&dw)[(IPT + 3) / 4],
                                                uint32_t *nbits = nullptr)
 {
     static_assert(IPT <= 32 && (IPT & (IPT - 1)) == 0 && IPT >= 4,
                   "IPT: a power of two from 4 to 32");
+    constexpr bool E32 = std::is_same<ET, float>::value;
+    static_assert(!E32 || (!PREV && !NEXT), "FP32 e: gradient and Hessian only");
     constexpr int TILE = BLOCK * IPT;
     constexpr int C = TileMap<IPT>::CONSEC;
     constexpr int R = TileMap<IPT>::R;
@@ -433,12 +436,24 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const int64_t rb = t0 + (int64_t)q * BLOCK * C + (int64_t)tid * C;
-            const double2 *ep = reinterpret_cast<const double2 *>(a.e + rb);
+            if constexpr (E32) {
+                const float4 *ep = reinterpret_cast<const float4 *>(a.e32 + rb);
 #pragma unroll
-            for (int h = 0; h < C / 2; ++h) {
-                const double2 v = ep[h];
-                ev[q * C + 2 * h] = v.x;
-                ev[q * C + 2 * h + 1] = v.y;
+                for (int h = 0; h < C / 4; ++h) {
+                    const float4 v = ep[h];
+                    ev[q * C + 4 * h] = v.x;
+                    ev[q * C + 4 * h + 1] = v.y;
+                    ev[q * C + 4 * h + 2] = v.z;
+                    ev[q * C + 4 * h + 3] = v.w;
+                }
+            } else {
+                const double2 *ep = reinterpret_cast<const double2 *>(a.e + rb);
+#pragma unroll
+                for (int h = 0; h < C / 2; ++h) {
+                    const double2 v = ep[h];
+                    ev[q * C + 2 * h] = v.x;
+                    ev[q * C + 2 * h + 1] = v.y;
+                }
             }
             if (WANT_D) {
                 if (C >= 8) {
@@ -470,7 +485,8 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
         for (int i = 0; i < IPT; ++i) {
             const int64_t k = t0 + tile_pos<BLOCK, IPT>(i, tid);
             const bool ok = k < a.n;
-            ev[i] = ok ? a.e[k] : 0.0;
+            if constexpr (E32) ev[i] = ok ? a.e32[k] : 0.f;
+            else ev[i] = ok ? a.e[k] : 0.0;
             if (WANT_D && ok) dw[i / 4] |= (uint32_t)a.d8[k] << (8 * (i % 4));
             if (WANT_W) wv[i] = ok ? a.w_comp[k] : 0.0;
         }
@@ -556,7 +572,15 @@ __device__ __forceinline__ double x_at(uint32_t xbits, int i, const double *s_xv
 // CARRY (Fine-Gray, 0/1 design): the weighted totals of column j were
 // carried by the previous launch, and this launch carries those of column
 // jnext (two more partial sums, see finish).
-template <int BLOCK, int IPT, int MODEL, bool VALS, bool PREV, bool CARRY = false>
+//
+// ET: storage type of e (float: FP32 storage, read from a.e32).  F32S (with
+// float storage): the sums inside a tile (thread-serial and wave scans), the
+// transform and the per-thread sums of the reduction in FP32; what crosses a
+// tile boundary (aggregates, the look-back prefix, the tile partial sums)
+// in FP64, and each run end's prefix is the FP64 carry plus the FP32
+// in-tile prefix.  Without F32S every sum is FP64.
+template <int BLOCK, int IPT, int MODEL, bool VALS, bool PREV, bool CARRY = false,
+          typename ET = double, bool F32S = false>
 __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t ntiles)
 {
     constexpr int TILE = BLOCK * IPT;
@@ -565,6 +589,9 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     constexpr int NR = CARRY ? 5 : 3;  // partial sums per tile
     static_assert(TILE % SS_CHUNK == 0, "tile must be whole chunks");
     static_assert(!CARRY || (MODEL == SS_FINE_GRAY && !VALS), "carry: Fine-Gray, 0/1 design");
+    static_assert(!F32S || std::is_same<ET, float>::value, "FP32 sums need FP32 storage");
+    // arithmetic type of the sums inside a tile
+    using AT = typename std::conditional<F32S, float, double>::type;
 
     __shared__ __attribute__((aligned(16))) uint8_t s_flag[TILE];
     __shared__ double s_xv[VALS ? TILE : 1];
@@ -604,12 +631,12 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     // ---- 2-4. tile data, column j and the pending update into registers
     constexpr int C = TileMap<IPT>::CONSEC;
     constexpr int R = TileMap<IPT>::R;
-    double ev[IPT];
+    ET ev[IPT];
     double wv[MODEL == SS_FINE_GRAY ? IPT : 1];
     uint32_t dw[(IPT + 3) / 4];  // event counts, one byte per element
     uint32_t nbits = 0u;         // CARRY: column jnext, one bit per element
     const uint32_t xbits =
-        stage_tile<BLOCK, IPT, MODEL == SS_FINE_GRAY, VALS, PREV, true, CARRY>(
+        stage_tile<BLOCK, IPT, MODEL == SS_FINE_GRAY, VALS, PREV, true, CARRY, ET>(
             a, t0, cnt, chunk0, chunk1, s_flag, s_xv, s_ep, ev, wv, dw, &nbits);
     SS_TRACE(ws, tile, 1);
 
@@ -618,19 +645,20 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     // per-row prefixes are held while the tile waits)
     double agg[NC];
     {
-        double run[NC];
+        AT run[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) run[c] = 0.0;
+        for (int c = 0; c < NC; ++c) run[c] = (AT)0;
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-            const double x = x_at<BLOCK, VALS>(xbits, i, s_xv);
-            const double ex = ev[i] * x;
-            run[0] += ev[i];
+            const AT x = (AT)x_at<BLOCK, VALS>(xbits, i, s_xv);
+            const AT ei = (AT)ev[i];
+            const AT ex = ei * x;
+            run[0] += ei;
             run[1] += ex;
             run[2] += ex * x;
             if (MODEL == SS_FINE_GRAY) {
-                const double ew = ev[i] * wv[i];
-                const double exw = ew * x;
+                const AT ew = ei * (AT)wv[i];
+                const AT exw = ew * x;
                 run[3] += ew;
                 run[4] += exw;
                 run[5] += exw * x;
@@ -638,8 +666,8 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double t = dpp_wave_sum(run[c]);
-            if (lane == 0) s_wsum[0][w][c] = t;
+            const AT t = dpp_wave_sum(run[c]);
+            if (lane == 0) s_wsum[0][w][c] = (double)t;
         }
         __syncthreads();
 #pragma unroll
@@ -701,23 +729,27 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
 
     // ---- 7. scan inside the tile, row by row: thread-serial over the row
     // segment, DPP across the wave, one barrier across the waves
-    double texcl[R][NC];  // exclusive prefix of this thread's segment of row q
+    // exclusive prefix of this thread's segment of row q: from the start of
+    // the launch (FP64 sums) or of the tile (F32S; the carry is added at run
+    // ends)
+    AT texcl[R][NC];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        double run[NC];
+        AT run[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) run[c] = 0.0;
+        for (int c = 0; c < NC; ++c) run[c] = (AT)0;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             const int i = q * C + k;
-            const double x = x_at<BLOCK, VALS>(xb, i, s_xv);
-            const double ex = ev[i] * x;
-            run[0] += ev[i];
+            const AT x = (AT)x_at<BLOCK, VALS>(xb, i, s_xv);
+            const AT ei = (AT)ev[i];
+            const AT ex = ei * x;
+            run[0] += ei;
             run[1] += ex;
             run[2] += ex * x;
             if (MODEL == SS_FINE_GRAY) {
-                const double ew = ev[i] * wv[i];
-                const double exw = ew * x;
+                const AT ew = ei * (AT)wv[i];
+                const AT exw = ew * x;
                 run[3] += ew;
                 run[4] += exw;
                 run[5] += exw * x;
@@ -725,22 +757,23 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double inc = dpp_incl_scan(run[c]);
+            const AT inc = dpp_incl_scan(run[c]);
             texcl[q][c] = inc - run[c];
-            if (lane == kWave - 1) s_wsum[q][w][c] = inc;
+            if (lane == kWave - 1) s_wsum[q][w][c] = (double)inc;
         }
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        double done = s_excl[c];  // the tile's prefix plus rows before q
+        // the tile's prefix (FP64 sums only) plus rows before q
+        AT done = F32S ? (AT)0 : (AT)s_excl[c];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            double before = 0.0, row = 0.0;
+            AT before = (AT)0, row = (AT)0;
 #pragma unroll
             for (int v = 0; v < NW; ++v) {
-                if (v < w) before += s_wsum[q][v][c];
-                row += s_wsum[q][v][c];
+                if (v < w) before += (AT)s_wsum[q][v][c];
+                row += (AT)s_wsum[q][v][c];
             }
             texcl[q][c] += done + before;
             done += row;
@@ -756,26 +789,31 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     // ---- 8. running prefix, transform at run ends, reduction (the
     // products are formed again, not kept from step 7)
     asm volatile("" : "+v"(xb));
+    double carry[NC];  // F32S: the tile's FP64 prefix, added at run ends
+#pragma unroll
+    for (int c = 0; c < NC; ++c) carry[c] = F32S ? s_excl[c] : 0.0;
+    AT acc_t[2] = {(AT)0, (AT)0};  // sum d G, sum d (H - G^2) of this thread
     double acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0.0;
     LogSum lsum;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        double S[NC];
+        AT S[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) S[c] = texcl[q][c];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             const int i = q * C + k;
-            const double x = x_at<BLOCK, VALS>(xb, i, s_xv);
-            const double ex = ev[i] * x;
-            S[0] += ev[i];
+            const AT x = (AT)x_at<BLOCK, VALS>(xb, i, s_xv);
+            const AT ei = (AT)ev[i];
+            const AT ex = ei * x;
+            S[0] += ei;
             S[1] += ex;
             S[2] += ex * x;
             if (MODEL == SS_FINE_GRAY) {
-                const double ew = ev[i] * wv[i];
-                const double exw = ew * x;
+                const AT ew = ei * (AT)wv[i];
+                const AT exw = ew * x;
                 S[3] += ew;
                 S[4] += exw;
                 S[5] += exw * x;
@@ -790,23 +828,30 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
             if (d != 0) {
                 const int64_t kk = t0 + tile_pos<BLOCK, IPT>(i, tid);
                 if (d == 255) d = a.d32[kk];
-                double S0 = S[0], S1 = S[1], S2 = S[2];
+                // the run end's prefix; Fine-Gray adds G(Y) times the weighted
+                // suffix (the totals minus the inclusive prefix)
+                double Sd[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) Sd[c] = F32S ? carry[c] + (double)S[c] : S[c];
+                double S0 = Sd[0], S1 = Sd[1], S2 = Sd[2];
                 if (MODEL == SS_FINE_GRAY) {
                     const double g = a.g_end[kk];
-                    S0 += g * (tot[0] - S[3]);
-                    S1 += g * (tot[1] - S[4]);
-                    S2 += g * (tot[2] - S[5]);
+                    S0 += g * (tot[0] - Sd[3]);
+                    S1 += g * (tot[1] - Sd[4]);
+                    S2 += g * (tot[2] - Sd[5]);
                 }
-                const double r = 1.0 / S0;
-                const double G = S1 * r;
-                const double H = S2 * r;
-                const double dd = (double)d;
-                acc[0] += dd * G;
-                acc[1] += dd * (H - G * G);
+                const AT r = (AT)1 / (AT)S0;
+                const AT G = (AT)S1 * r;
+                const AT H = (AT)S2 * r;
+                const AT dd = (AT)d;
+                acc_t[0] += dd * G;
+                acc_t[1] += dd * (H - G * G);
                 if (a.want_log) lsum.add(S0, d);
             }
         }
     }
+    acc[0] = (double)acc_t[0];
+    acc[1] = (double)acc_t[1];
     if (a.want_log) acc[2] = lsum.value();
     block_sum<NR, BLOCK>(acc, s_red);
     if (tid == 0) {
@@ -829,7 +874,8 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
 
 // Fine-Gray totals pass: applies the pending step (a1) and reduces
 // sum_r e_r x_r^m w_comp_r (m = 0, 1, 2) into hdr->fg_tot.
-template <int BLOCK, int IPT, bool VALS, bool PREV>
+// With FP32 storage of e (ET = float) the sums are still FP64.
+template <int BLOCK, int IPT, bool VALS, bool PREV, typename ET = double>
 __global__ __launch_bounds__(BLOCK) void k_fg_totals(FusedCall a, WsView ws,
                                                      int64_t ntiles)
 {
@@ -859,15 +905,16 @@ __global__ __launch_bounds__(BLOCK) void k_fg_totals(FusedCall a, WsView ws,
     const int64_t chunk0 = t0 / SS_CHUNK;
     const int64_t chunk1 = min(chunk0 + TILE / SS_CHUNK, nchunk);
     const int64_t cnt = min((int64_t)TILE, a.n - t0);
-    double ev[IPT], wv[IPT];
+    ET ev[IPT];
+    double wv[IPT];
     uint32_t dw[(IPT + 3) / 4];
-    const uint32_t xbits = stage_tile<BLOCK, IPT, true, VALS, PREV, false>(
+    const uint32_t xbits = stage_tile<BLOCK, IPT, true, VALS, PREV, false, false, ET>(
         a, t0, cnt, chunk0, chunk1, s_flag, s_xv, s_ep, ev, wv, dw);
     double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
         const double x = x_at<BLOCK, VALS>(xbits, i, s_xv);
-        const double ew = ev[i] * wv[i];
+        const double ew = (double)ev[i] * wv[i];
         acc[0] += ew;
         acc[1] += ew * x;
         acc[2] += ew * x * x;
@@ -1016,11 +1063,48 @@ void launch_fg_totals_t(const FusedCall &a, const WsView &ws, int64_t ntiles, bo
     }
 }
 
+// FP32 storage of e: gradient and Hessian only (no pending update, no carry).
+template <int IPT, int MODEL, bool VALS>
+void launch_fused_f32_t(const FusedCall &a, const WsView &ws, int64_t ntiles, hipStream_t s)
+{
+    const dim3 g((unsigned)ntiles), b(kBlock);
+    if (a.f32_sums)
+        hipLaunchKernelGGL((k_fused<kBlock, IPT, MODEL, VALS, false, false, float, true>), g, b,
+                           0, s, a, ws, ntiles);
+    else
+        hipLaunchKernelGGL((k_fused<kBlock, IPT, MODEL, VALS, false, false, float, false>), g,
+                           b, 0, s, a, ws, ntiles);
+}
+
+template <int IPT>
+int32_t launch_fused_f32_ipt(const FusedCall &a, const WsView &ws, int64_t ntiles,
+                             hipStream_t s)
+{
+    const bool vals = a.col.vals != nullptr;
+    if (a.jprev >= 0 || a.jnext >= 0 || a.ccd || a.fg_have_totals) return SS_EUNSUPPORTED;
+    const dim3 g((unsigned)ntiles), b(kBlock);
+    if (a.model == SS_FINE_GRAY) {
+        if (vals) hipLaunchKernelGGL((k_fg_totals<kBlock, IPT, true, false, float>), g, b, 0, s, a, ws, ntiles);
+        else      hipLaunchKernelGGL((k_fg_totals<kBlock, IPT, false, false, float>), g, b, 0, s, a, ws, ntiles);
+        SS_LAUNCH_CHECK();
+        FusedCall c = a;
+        c.clear_error = 0;
+        if (vals) launch_fused_f32_t<IPT, SS_FINE_GRAY, true>(c, ws, ntiles, s);
+        else      launch_fused_f32_t<IPT, SS_FINE_GRAY, false>(c, ws, ntiles, s);
+    } else {
+        if (vals) launch_fused_f32_t<IPT, SS_COX, true>(a, ws, ntiles, s);
+        else      launch_fused_f32_t<IPT, SS_COX, false>(a, ws, ntiles, s);
+    }
+    SS_LAUNCH_CHECK();
+    return SS_OK;
+}
+
 template <int IPT>
 int32_t launch_fused_ipt(const FusedCall &a, const WsView &ws, hipStream_t s)
 {
     const int64_t ntiles = ceil_div(a.n, (int64_t)kBlock * IPT);
     if (ntiles > ws.max_tiles) return SS_EWORKSPACE;
+    if (a.e32) return launch_fused_f32_ipt<IPT>(a, ws, ntiles, s);
     const bool vals = a.col.vals != nullptr;
     const bool prev = a.jprev >= 0;
     FusedCall b = a;

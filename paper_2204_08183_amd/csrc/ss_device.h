@@ -58,6 +58,29 @@ __device__ __forceinline__ void wave_inclusive_scan(double (&x)[NC])
 
 __device__ __forceinline__ double wave_sum(double x) { return dpp_wave_sum(x); }
 
+// The same for floats (one DPP move per step).
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ float dpp_float(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK,
+                                                      0xF, BOUND_ZERO));
+}
+__device__ __forceinline__ float dpp_incl_scan(float x)
+{
+    x += dpp_float<0x111, 0xF, true>(x);
+    x += dpp_float<0x112, 0xF, true>(x);
+    x += dpp_float<0x114, 0xF, true>(x);
+    x += dpp_float<0x118, 0xF, true>(x);
+    x += dpp_float<0x142, 0xA, false>(x);
+    x += dpp_float<0x143, 0xC, false>(x);
+    return x;
+}
+__device__ __forceinline__ float dpp_wave_sum(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dpp_incl_scan(x)),
+                                                    kWave - 1));
+}
+
 // Block-wide sum of NC doubles in a fixed order; result valid in thread 0.
 template <int NC, int BLOCK>
 __device__ __forceinline__ void block_sum(double (&x)[NC], double *s_red)

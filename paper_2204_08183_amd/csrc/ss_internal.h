@@ -209,6 +209,10 @@ struct FusedCall {
     const double *step_prev; // device scalar: pending step of jprev
     double *eta;             // written only when jprev >= 0
     double *e;
+    // FP32 storage of e (ss_grad_hess_f32): e32 replaces e; f32_sums selects
+    // FP32 in-tile sums and transform with the FP64 carry between tiles
+    const float *e32;
+    int32_t f32_sums;
     const uint8_t *d8;
     const int32_t *d32;
     const double *w_comp;

@@ -64,6 +64,8 @@ SIGNATURES = {
     "ss_exp_f32": (_i32, [_i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_grad_hess_mixed": (_i32, [_i32, _i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp,
                                   _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ss_grad_hess_f32": (_i32, [_i32, _i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
+                                _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_cv_stride": (_i64, [_i64]),
     "ss_cv_prepare_workspace_bytes": (_sz, [_i64, _i32]),
     "ss_cv_prepare": (_i32, [_i32, _i64, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -242,6 +244,20 @@ class Problem:
                                        _p(out), self.ws.ptr, self.ws.nbytes,
                                        _stream(self.device))
         check(rc, "ss_grad_hess_mixed")
+        return out
+
+    def grad_hess_f32(self, j, e32, acc="f64", out=None):
+        """(g', g'', sum d log S0 of the shifted e) of coordinate j from FP32 e
+        in the single-pass fused kernel, sums in FP64 ("f64") or FP32 inside
+        a tile with an FP64 carry ("f32x64")."""
+        out = torch.empty(3, dtype=torch.float64, device=self.device) if out is None else out
+        rc = load().ss_grad_hess_f32(self.model, ACCUMULATIONS[acc], self.n, self.p, int(j),
+                                     _p(e32), _p(self.d8), _p(self.d32), _p(self.w_comp),
+                                     _p(self.g_end), _p(self.col_ptr), _p(self.rows_sorted),
+                                     _p(self.vals_sorted), _p(self.chunk_ptr), _p(self.c),
+                                     _p(out), self.ws.ptr, self.ws.nbytes,
+                                     _stream(self.device))
+        check(rc, "ss_grad_hess_f32")
         return out
 
     def eta_gradient(self, grad=None, loglik=None):
