@@ -90,6 +90,22 @@ def event_time_us(torch, fn, reps):
     return a.elapsed_time(b) * 1e3 / reps
 
 
+def tuned(prob, **kw):
+    """Runs the library's autotuner on a problem (launch shapes only; the
+    results do not depend on them) and returns what it picked."""
+    res = prob.autotune(**kw)
+    out = {}
+    if res["grad_hess"]:
+        out["grad_hess_ipt"] = res["grad_hess"][0]
+        out["grad_hess_us_by_ipt"] = dict(zip(("4", "8", "16", "32"),
+                                              [round(t, 2) for t in res["grad_hess"][1]]))
+    if res.get("sweep"):
+        out["sweep_shape"] = res["sweep"][0]
+        out["sweep_us_by_shape"] = dict(zip(("256x16", "512x8", "256x8", "512x16"),
+                                            [round(t, 1) for t in res["sweep"][1]]))
+    return out
+
+
 def roofline(torch, ss, gen, n, reps):
     log("roofline workload: uniform(1,2) tuple, dense valued column, N=%d" % n)
     u = gen.uniform_tuple_data(1, n)
@@ -98,6 +114,7 @@ def roofline(torch, ss, gen, n, reps):
     prob.set_eta(u["eta"])
     nnz = int(u["rows"].size)
     del u
+    tune = tuned(prob, j=0, reps=5, sweep=False)
     out = torch.empty(3, dtype=torch.float64, device="cuda:0")
     for _ in range(3):
         prob.grad_hess(0, out=out)
@@ -115,7 +132,7 @@ def roofline(torch, ss, gen, n, reps):
             traffic = t.get("bytes_per_launch")
     err = prob.workspace_error()
     copy_gbs = copy_peak_gbs(torch)
-    ipt = 8 if n <= 3 << 19 else 16  # tile shape the library picks
+    ipt = ss.tune_get(ss.TUNE_GRAD_HESS, "cox", "f64", True, n)  # the tile shape launched
     del prob
     torch.cuda.empty_cache()
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -123,7 +140,7 @@ def roofline(torch, ss, gen, n, reps):
             "kernel": "k_fused<256,%d,cox,vals>" % ipt, "n": n, "nnz": nnz,
             "algo_bytes_per_launch": algo, "avg_us": round(us, 2), "reps": reps,
             "copy_peak_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
-            "wait_errors": err}
+            "wait_errors": err, "tuning": tune}
 
 
 def precision(torch, ss, gen, n, reps):
@@ -144,7 +161,10 @@ def precision(torch, ss, gen, n, reps):
         e32, _ = prob.make_e32()
         out = torch.empty(3, dtype=torch.float64, device="cuda:0")
         col = nnz * (4 + (8 if valued else 0))
-        row = {}
+        row = {"tuned_ipt": {}}
+        for storage in ("f64", "f32", "f32x64"):
+            t = tuned(prob, j=0, reps=5, sweep=False, storage=storage, e32=e32)
+            row["tuned_ipt"][storage] = t["grad_hess_ipt"]
         for name, fn, se in (("f64", lambda: prob.grad_hess(0, out=out), 8),
                              ("f32_storage_f64_sums",
                               lambda: prob.grad_hess_f32(0, e32, "f64", out), 4),
@@ -185,13 +205,14 @@ def context(torch, ss, gen):
     prob = ss.Problem("cox", u["y"], u["status"], u["col_ptr"], u["rows"], u["vals"],
                       "cuda:0")
     prob.set_eta(u["eta"])
+    tune = tuned(prob, j=0, reps=20, sweep=False)
     out = torch.empty(3, dtype=torch.float64, device="cuda:0")
     for _ in range(5):
         prob.grad_hess(0, out=out)
     torch.cuda.synchronize()
     us = event_time_us(torch, lambda: prob.grad_hess(0, out=out), 200)
     return {"fused_us_n1e5_ours_back_to_back": round(us, 2),
-            "fused_us_n1e5_paper_gv100": 5.2,
+            "fused_us_n1e5_paper_gv100": 5.2, "tuned_ipt": tune["grad_hess_ipt"],
             "note": "paper Table 1, steps (2)-(4) fused, N=1e5, Uniform(1,2); other GPU"}
 
 
@@ -206,6 +227,7 @@ def paper_sizes(torch, ss, gen):
         prob = ss.Problem("cox", u["y"], u["status"], u["col_ptr"], u["rows"], u["vals"],
                           "cuda:0")
         prob.set_eta(u["eta"])
+        tuned(prob, j=0, reps=20, sweep=False)
         out = torch.empty(3, dtype=torch.float64, device="cuda:0")
         for _ in range(5):
             prob.grad_hess(0, out=out)
@@ -217,6 +239,7 @@ def paper_sizes(torch, ss, gen):
         d = gen.cox_data(0, 100_000, 1000, 0.05) if model == "cox" else \
             gen.fg_data(0, 100_000, 1000, 0.05)
         prob = ss.Problem(model, d["y"], d["status"], d["col_ptr"], d["rows"], None, "cuda:0")
+        tuned(prob, j=0, reps=10, sweep=True, penalty="l1", lam=gamma)
         prob.sweep("l1", gamma)
         torch.cuda.synchronize()
         us = event_time_us(torch, lambda: prob.sweep("l1", gamma), 5)
@@ -438,6 +461,9 @@ def main():
     torch.cuda.synchronize()
     prepare_s = time.perf_counter() - t0
     gamma = math.sqrt(2.0)
+    log("autotuning launch shapes")
+    tuning = {"cox": tuned(pc, j=0, reps=10, sweep=True, penalty="l1", lam=gamma),
+              "fg": tuned(pf, j=0, reps=10, sweep=True, penalty="l1", lam=gamma)}
 
     def step():
         pc.sweep("l1", gamma)
@@ -493,6 +519,7 @@ def main():
         "us_per_coordinate_fg": round(fg_us / args.p, 3),
         "prepare_s_both_models": round(prepare_s, 3),
         "wait_errors": wait_errors,
+        "tuning": tuning,
     }
     if not args.no_roofline:
         line["roofline"] = roofline(torch, ss, gen, args.roof_n, args.roof_reps)

@@ -426,6 +426,91 @@ int32_t ss_cv_select(int32_t n_gamma, int32_t reps, const double *scores,
                      double *mean, int32_t *best, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Launch shapes and their autotuning.  Sec. 2.7 leaves the block size and
+ * the items per thread of the fused scan kernel as tunable constants; here
+ * two choices are tuned:
+ *   SS_TUNE_GRAD_HESS  positions per thread of the single-pass fused kernel
+ *                      of ss_grad_hess, ss_loglik, ss_objective,
+ *                      ss_grad_hess_f32 and ss_grad_hess_noalloc: 4, 8, 16
+ *                      or 32 (tiles of 1024 ... 8192 positions; the
+ *                      per-coordinate launches inside ss_ccd_sweep use 8
+ *                      or 16 only);
+ *   SS_TUNE_SWEEP      segment shape of the persistent sweep of
+ *                      ss_ccd_sweep, block * 100 + positions per thread:
+ *                      25608, 25616, 51208 or 51216 (Cox only).
+ * A choice is kept per (kind, model, storage of e, valued design or not,
+ * size bucket ceil(log2 n)) in a process-wide table that every launch
+ * consults; without an entry a launch uses the built-in rule (tiles of
+ * 2048 positions up to 1.5 M positions, 4096 above; the first sweep shape
+ * whose workgroups all fit on the device).
+ *   storage: SS_STORAGE_F64 (FP64 e), SS_STORAGE_F32 (FP32 e, FP64 sums),
+ *   SS_STORAGE_F32_SUMS32 (FP32 e, FP32 in-tile sums); the sweep is FP64.
+ * ss_tune_get: the choice a launch would use now (the built-in rule's IPT
+ * for SS_TUNE_GRAD_HESS, 0 for an untuned sweep); ss_tune_has: 1 if the
+ * table holds an entry for the key, else 0.  ss_tune_set: pins a
+ * choice (0 removes the entry; SS_EINVAL for an impossible one).
+ * ss_tune_clear: empties the table.  ss_tune_save / ss_tune_load [host
+ * path]: write the table to a text file / add the entries of a file that
+ * were measured on the current device's GPU architecture (*loaded [host]
+ * receives their number); SS_EINVAL if the file cannot be opened.  These
+ * calls take a mutex and launch nothing. */
+#define SS_TUNE_GRAD_HESS       0
+#define SS_TUNE_SWEEP           1
+#define SS_STORAGE_F64          0
+#define SS_STORAGE_F32          1
+#define SS_STORAGE_F32_SUMS32   2
+int32_t ss_tune_get(int32_t kind, int32_t model, int32_t storage,
+                    int32_t valued, int64_t n);
+int32_t ss_tune_has(int32_t kind, int32_t model, int32_t storage,
+                    int32_t valued, int64_t n);
+int32_t ss_tune_set(int32_t kind, int32_t model, int32_t storage,
+                    int32_t valued, int64_t n, int32_t choice);
+int32_t ss_tune_clear(void);
+int32_t ss_tune_save(const char *path);
+int32_t ss_tune_load(const char *path, int32_t *loaded);
+
+/* ss_autotune_grad_hess: times every SS_TUNE_GRAD_HESS candidate on the
+ * caller's prepared problem and coordinate j (arguments as ss_grad_hess, or
+ * as ss_grad_hess_f32 for FP32 storage, with e pointing at the FP64 or FP32
+ * vector), `reps` back-to-back launches each between two HIP events on
+ * `stream` (synchronises it), and stores the fastest in the table.
+ * *choice [host] receives it; us [host, 4 floats, may be NULL] the average
+ * microseconds per call of IPT 4, 8, 16, 32.  `out` is overwritten.
+ *
+ * ss_autotune_sweep: the same for the persistent sweep's segment shapes,
+ * over coordinates [j_begin, j_end) of the caller's problem.  The state
+ * (eta, e, beta, delta) is only read: before every timed sweep it is copied
+ * into the caller's scratch vectors (eta_s, e_s: n doubles; beta_s,
+ * delta_s, steps_s: p doubles), which the sweep then updates.  Shapes whose
+ * workgroups do not all fit on the device are skipped (us = -1); with none
+ * left, SS_EUNSUPPORTED.  us [host, 4 floats, may be NULL]: 25616, 51208,
+ * 25608, 51216 in that order.
+ * Errors as the calls they time; reps outside [1, 1000]: SS_EINVAL. */
+int32_t ss_autotune_grad_hess(int32_t model, int32_t storage, int64_t n,
+                              int64_t p, int64_t j, const void *e,
+                              const uint8_t *d8, const int32_t *d32,
+                              const double *w_comp, const double *g_end,
+                              const int64_t *col_ptr,
+                              const int32_t *rows_sorted,
+                              const double *vals_sorted,
+                              const int32_t *chunk_ptr, const double *c,
+                              double *out, void *ws, size_t ws_bytes,
+                              int32_t reps, int32_t *choice, float *us,
+                              void *stream);
+int32_t ss_autotune_sweep(int32_t model, int32_t penalty, double lambda,
+                          int64_t n, int64_t p, int64_t j_begin, int64_t j_end,
+                          const double *eta, const double *e,
+                          const uint8_t *d8, const int32_t *d32,
+                          const double *w_comp, const double *g_end,
+                          const int64_t *col_ptr, const int32_t *rows_sorted,
+                          const double *vals_sorted, const int32_t *chunk_ptr,
+                          const double *c, const double *beta,
+                          const double *delta, double *eta_s, double *e_s,
+                          double *beta_s, double *delta_s, double *steps_s,
+                          void *ws, size_t ws_bytes, int32_t reps,
+                          int32_t *choice, float *us, void *stream);
+
+/* ---------------------------------------------------------------------
  * For callers that cannot allocate device memory (code under graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * computation as ss_grad_hess, with the fused kernels' scratch (look-back

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsurvscan.so")
-SOURCES = ["adjoint.hip", "api.hip", "cv.hip", "fused.hip", "mixed.hip", "noalloc.hip", "prepare.hip", "sweep.hip"]
+SOURCES = ["adjoint.hip", "api.hip", "cv.hip", "fused.hip", "mixed.hip", "noalloc.hip", "prepare.hip", "sweep.hip", "tune.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -25,6 +25,54 @@ static bool bad_size(int64_t n, int64_t p)
 }
 
 static Column column(const int64_t *col_ptr, const int32_t *rows, const double *vals,
+                     const int32_t *chunk_ptr, int64_t n);
+
+// The whole sweep as one persistent launch (SS_EUNSUPPORTED when it does
+// not fit on the device).
+static int32_t sweep_persistent(int32_t model, int32_t penalty, double lambda, int64_t n,
+                                int64_t j_begin, int64_t j_end, double *eta, double *e,
+                                const uint8_t *d8, const int32_t *d32, const double *w_comp,
+                                const double *g_end, const Column &col, const double *c,
+                                double *beta, double *delta, double *steps, double *g12_out,
+                                const WsView &v, hipStream_t s)
+{
+    SweepCall sc = {};
+    sc.model = model;
+    sc.n = n;
+    sc.j_begin = (int32_t)j_begin;
+    sc.j_end = (int32_t)j_end;
+    sc.eta = eta;
+    sc.e = e;
+    sc.d8 = d8;
+    sc.d32 = d32;
+    sc.w_comp = w_comp;
+    sc.g_end = g_end;
+    sc.col = col;
+    sc.c = c;
+    sc.beta = beta;
+    sc.delta = delta;
+    sc.steps = steps;
+    sc.g12_out = g12_out;
+    sc.penalty = penalty;
+    sc.lambda = lambda;
+    return launch_sweep_persistent(sc, v, s);
+}
+
+// RAII helpers of the tuning calls.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+struct ForceScope {
+    ForceScope(int32_t kind, int32_t choice) { tune_force() = TuneForce{kind, choice}; }
+    ~ForceScope() { tune_force() = TuneForce{-1, 0}; }
+};
+
+static Column column(const int64_t *col_ptr, const int32_t *rows, const double *vals,
                      const int32_t *chunk_ptr, int64_t n)
 {
     Column c;
@@ -244,26 +292,10 @@ int32_t ss_ccd_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, i
     // tests); by default the sweep is one cooperative launch when it fits.
     const char *mode = getenv("SURVSCAN_SWEEP");
     if (!(mode && strcmp(mode, "launch") == 0)) {
-        SweepCall sc = {};
-        sc.model = model;
-        sc.n = n;
-        sc.j_begin = (int32_t)j_begin;
-        sc.j_end = (int32_t)j_end;
-        sc.eta = eta;
-        sc.e = e;
-        sc.d8 = d8;
-        sc.d32 = d32;
-        sc.w_comp = w_comp;
-        sc.g_end = g_end;
-        sc.col = column(col_ptr, rows_sorted, vals_sorted, chunk_ptr, n);
-        sc.c = c;
-        sc.beta = beta;
-        sc.delta = delta;
-        sc.steps = steps;
-        sc.g12_out = g12_out;
-        sc.penalty = penalty;
-        sc.lambda = lambda;
-        const int32_t rc = launch_sweep_persistent(sc, v, s);
+        const int32_t rc = sweep_persistent(
+            model, penalty, lambda, n, j_begin, j_end, eta, e, d8, d32, w_comp, g_end,
+            column(col_ptr, rows_sorted, vals_sorted, chunk_ptr, n), c, beta, delta, steps,
+            g12_out, v, s);
         if (rc != SS_EUNSUPPORTED) return rc;
     }
     FusedCall a = {};
@@ -384,6 +416,132 @@ int32_t ss_grad_hess_f32(int32_t model, int32_t acc, int64_t n, int64_t p, int64
     a.want_log = 1;
     a.obj_penalty = -1;
     return launch_fused(a, v, (hipStream_t)stream);
+}
+
+int32_t ss_autotune_grad_hess(int32_t model, int32_t storage, int64_t n, int64_t p, int64_t j,
+                              const void *e, const uint8_t *d8, const int32_t *d32,
+                              const double *w_comp, const double *g_end,
+                              const int64_t *col_ptr, const int32_t *rows_sorted,
+                              const double *vals_sorted, const int32_t *chunk_ptr,
+                              const double *c, double *out, void *ws, size_t ws_bytes,
+                              int32_t reps, int32_t *choice, float *us, void *stream)
+{
+    if (reps < 1 || reps > 1000 || !choice) return SS_EINVAL;
+    if (storage != SS_STORAGE_F64 && storage != SS_STORAGE_F32 &&
+        storage != SS_STORAGE_F32_SUMS32)
+        return SS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    auto call = [&]() -> int32_t {
+        if (storage == SS_STORAGE_F64)
+            return ss_grad_hess(model, n, p, j, (const double *)e, d8, d32, w_comp, g_end,
+                                col_ptr, rows_sorted, vals_sorted, chunk_ptr, c, out, ws,
+                                ws_bytes, stream);
+        return ss_grad_hess_f32(model, storage == SS_STORAGE_F32 ? SS_ACC_F64 : SS_ACC_F32_C64,
+                                n, p, j, (const float *)e, d8, d32, w_comp, g_end, col_ptr,
+                                rows_sorted, vals_sorted, chunk_ptr, c, out, ws, ws_bytes,
+                                stream);
+    };
+    // the arguments are checked by a first call with the current choice
+    int32_t rc = call();
+    if (rc != SS_OK) return rc;
+    EventPair ev;
+    SS_HIP_CHECK(hipEventCreate(&ev.a));
+    SS_HIP_CHECK(hipEventCreate(&ev.b));
+    static const int32_t cands[4] = {4, 8, 16, 32};
+    float t[4];
+    int32_t best = 0;
+    for (int i = 0; i < 4; ++i) {
+        ForceScope force(SS_TUNE_GRAD_HESS, cands[i]);
+        for (int w = 0; w < 2; ++w)
+            if ((rc = call()) != SS_OK) return rc;
+        SS_HIP_CHECK(hipEventRecord(ev.a, s));
+        for (int r = 0; r < reps; ++r)
+            if ((rc = call()) != SS_OK) return rc;
+        SS_HIP_CHECK(hipEventRecord(ev.b, s));
+        SS_HIP_CHECK(hipEventSynchronize(ev.b));
+        float ms = 0.f;
+        SS_HIP_CHECK(hipEventElapsedTime(&ms, ev.a, ev.b));
+        t[i] = ms * 1000.f / (float)reps;
+        if (!best || t[i] < t[best - 1]) best = i + 1;
+    }
+    *choice = cands[best - 1];
+    if (us)
+        for (int i = 0; i < 4; ++i) us[i] = t[i];
+    return ss_tune_set(SS_TUNE_GRAD_HESS, model, storage, vals_sorted != nullptr, n, *choice);
+}
+
+int32_t ss_autotune_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, int64_t p,
+                          int64_t j_begin, int64_t j_end, const double *eta, const double *e,
+                          const uint8_t *d8, const int32_t *d32, const double *w_comp,
+                          const double *g_end, const int64_t *col_ptr,
+                          const int32_t *rows_sorted, const double *vals_sorted,
+                          const int32_t *chunk_ptr, const double *c, const double *beta,
+                          const double *delta, double *eta_s, double *e_s, double *beta_s,
+                          double *delta_s, double *steps_s, void *ws, size_t ws_bytes,
+                          int32_t reps, int32_t *choice, float *us, void *stream)
+{
+    if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
+    if (penalty != SS_PENALTY_NONE && penalty != SS_PENALTY_L1 && penalty != SS_PENALTY_L2)
+        return SS_EUNSUPPORTED;
+    if (penalty != SS_PENALTY_NONE && !(lambda > 0.0)) return SS_EINVAL;
+    if (bad_size(n, p) || j_begin < 0 || j_end > p || j_begin >= j_end) return SS_EINVAL;
+    if (reps < 1 || reps > 1000 || !choice) return SS_EINVAL;
+    if (!model_arrays_ok(model, e, d8, d32, w_comp, g_end) || !eta) return SS_EINVAL;
+    if (!model_arrays_ok(model, e_s, d8, d32, w_comp, g_end) || !eta_s) return SS_EINVAL;
+    if (!col_ptr || !rows_sorted || !chunk_ptr || !c || !beta || !delta || !beta_s ||
+        !delta_s || !steps_s)
+        return SS_EINVAL;
+    WsView v;
+    if (!fused_ws_view(ws, ws_bytes, n, &v)) return SS_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const Column col = column(col_ptr, rows_sorted, vals_sorted, chunk_ptr, n);
+    auto restore = [&]() -> int32_t {
+        SS_HIP_CHECK(hipMemcpyAsync(eta_s, eta, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        SS_HIP_CHECK(hipMemcpyAsync(e_s, e, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        SS_HIP_CHECK(hipMemcpyAsync(beta_s, beta, p * sizeof(double), hipMemcpyDeviceToDevice, s));
+        SS_HIP_CHECK(hipMemcpyAsync(delta_s, delta, p * sizeof(double), hipMemcpyDeviceToDevice,
+                                    s));
+        return SS_OK;
+    };
+    auto sweep = [&]() {
+        return sweep_persistent(model, penalty, lambda, n, j_begin, j_end, eta_s, e_s, d8, d32,
+                                w_comp, g_end, col, c, beta_s, delta_s, steps_s, nullptr, v, s);
+    };
+    EventPair ev;
+    SS_HIP_CHECK(hipEventCreate(&ev.a));
+    SS_HIP_CHECK(hipEventCreate(&ev.b));
+    static const int32_t cands[4] = {25616, 51208, 25608, 51216};
+    float t[4];
+    int32_t best = 0;
+    for (int i = 0; i < 4; ++i) {
+        t[i] = -1.f;
+        if (model == SS_FINE_GRAY && cands[i] == 51216) continue;
+        ForceScope force(SS_TUNE_SWEEP, cands[i]);
+        int32_t rc = restore();
+        if (rc != SS_OK) return rc;
+        rc = sweep();
+        if (rc == SS_EUNSUPPORTED) continue;  // does not fit on the device
+        if (rc != SS_OK) return rc;
+        float total = 0.f;
+        for (int r = 0; r < reps; ++r) {
+            if ((rc = restore()) != SS_OK) return rc;
+            SS_HIP_CHECK(hipEventRecord(ev.a, s));
+            if ((rc = sweep()) != SS_OK) return rc;
+            SS_HIP_CHECK(hipEventRecord(ev.b, s));
+            SS_HIP_CHECK(hipEventSynchronize(ev.b));
+            float ms = 0.f;
+            SS_HIP_CHECK(hipEventElapsedTime(&ms, ev.a, ev.b));
+            total += ms;
+        }
+        t[i] = total * 1000.f / (float)reps;
+        if (!best || t[i] < t[best - 1]) best = i + 1;
+    }
+    if (us)
+        for (int i = 0; i < 4; ++i) us[i] = t[i];
+    if (!best) return SS_EUNSUPPORTED;
+    *choice = cands[best - 1];
+    return ss_tune_set(SS_TUNE_SWEEP, model, SS_STORAGE_F64, vals_sorted != nullptr, n,
+                       *choice);
 }
 
 size_t ss_eta_gradient_workspace_bytes(int64_t n)

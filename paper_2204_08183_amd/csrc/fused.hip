@@ -1032,16 +1032,6 @@ bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v)
 
 namespace {
 
-// Items per thread by problem size: tiles of 2048 positions up to 1.5 M
-// positions, of 4096 above (measured with the one-window look-back: at
-// N = 1e6 15.9 us against 16.7 us for 4096; at N = 4e6 32 us against
-// 36 us).
-int pick_ipt(int64_t n)
-{
-    if (n <= (int64_t)3 << 19) return 8;
-    return 16;
-}
-
 template <int IPT, int MODEL, bool VALS, bool PREV, bool CARRY = false>
 void launch_fused_t(const FusedCall &a, const WsView &ws, int64_t ntiles, hipStream_t s)
 {
@@ -1143,11 +1133,53 @@ int32_t launch_fused_ipt(const FusedCall &a, const WsView &ws, hipStream_t s)
     return SS_OK;
 }
 
+// Gradient and Hessian, likelihood or objective alone (no pending update,
+// no carry, no coordinate update): any tile shape.
+template <int IPT>
+int32_t launch_plain_ipt(const FusedCall &a, const WsView &ws, hipStream_t s)
+{
+    const int64_t ntiles = ceil_div(a.n, (int64_t)kBlock * IPT);
+    if (ntiles > ws.max_tiles) return SS_EWORKSPACE;
+    if (a.e32) return launch_fused_f32_ipt<IPT>(a, ws, ntiles, s);
+    const bool vals = a.col.vals != nullptr;
+    if (a.model == SS_FINE_GRAY) {
+        launch_fg_totals_t<IPT>(a, ws, ntiles, vals, false, s);
+        SS_LAUNCH_CHECK();
+        FusedCall b = a;
+        b.clear_error = 0;
+        if (vals) launch_fused_t<IPT, SS_FINE_GRAY, true, false>(b, ws, ntiles, s);
+        else      launch_fused_t<IPT, SS_FINE_GRAY, false, false>(b, ws, ntiles, s);
+    } else {
+        if (vals) launch_fused_t<IPT, SS_COX, true, false>(a, ws, ntiles, s);
+        else      launch_fused_t<IPT, SS_COX, false, false>(a, ws, ntiles, s);
+    }
+    SS_LAUNCH_CHECK();
+    return SS_OK;
+}
+
 }  // namespace
 
 int32_t launch_fused(const FusedCall &a, const WsView &ws, hipStream_t s)
 {
-    return pick_ipt(a.n) == 8 ? launch_fused_ipt<8>(a, ws, s) : launch_fused_ipt<16>(a, ws, s);
+    const bool plain = a.jprev < 0 && a.jnext < 0 && !a.ccd && !a.fg_have_totals;
+    if (plain) {
+        const int32_t storage = !a.e32 ? SS_STORAGE_F64
+                                : a.f32_sums ? SS_STORAGE_F32_SUMS32 : SS_STORAGE_F32;
+        int32_t ipt = tune_lookup(SS_TUNE_GRAD_HESS, a.model, storage,
+                                  a.col.vals != nullptr, a.n);
+        if (!ipt) ipt = default_ipt(a.n);
+        switch (ipt) {
+        case 4: return launch_plain_ipt<4>(a, ws, s);
+        case 8: return launch_plain_ipt<8>(a, ws, s);
+        case 16: return launch_plain_ipt<16>(a, ws, s);
+        case 32: return launch_plain_ipt<32>(a, ws, s);
+        default: return SS_EINVAL;
+        }
+    }
+    // the per-coordinate launches of a sweep (pending update, carry,
+    // coordinate update): tiles of 2048 or 4096 positions
+    if (a.e32) return SS_EUNSUPPORTED;
+    return default_ipt(a.n) == 8 ? launch_fused_ipt<8>(a, ws, s) : launch_fused_ipt<16>(a, ws, s);
 }
 
 int32_t launch_apply(int64_t n, int32_t j, const double *step, double *eta,

@@ -251,6 +251,20 @@ struct FusedCall {
 int32_t launch_fused(const FusedCall &call, const WsView &ws,
                      hipStream_t stream);
 
+// ------------------------------------------------------------ launch shapes
+// Positions per thread of the single-pass fused kernel when nothing is
+// tuned: tiles of 2048 positions up to 1.5 M positions, of 4096 above.
+inline int32_t default_ipt(int64_t n) { return n <= ((int64_t)3 << 19) ? 8 : 16; }
+// The tuned choice for a launch (0: none); see tune.hip.
+int32_t tune_lookup(int32_t kind, int32_t model, int32_t storage, int32_t valued, int64_t n);
+// A choice forced on the calling thread's launches of one kind while a
+// tuning call times its candidates (choice 0: none).
+struct TuneForce {
+    int32_t kind;
+    int32_t choice;
+};
+TuneForce &tune_force();
+
 // The whole sweep j_begin..j_end-1 as one cooperative launch; returns
 // SS_EUNSUPPORTED (launching nothing) when the problem does not fit on the
 // device at once, and the caller then launches per coordinate.

@@ -1004,7 +1004,18 @@ int32_t launch_sweep_persistent(const SweepCall &call, const WsView &ws, hipStre
     SS_HIP_CHECK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     if (!coop) return SS_EUNSUPPORTED;
     const bool vals = call.col.vals != nullptr;
-    for (const Shape &sh : vals ? shapes_valued : shapes_01) {
+    // a tuned shape first, then the built-in order; a shape forced by a
+    // tuning call alone
+    Shape order[5];
+    int m = 0;
+    const int32_t want = tune_lookup(SS_TUNE_SWEEP, call.model, SS_STORAGE_F64, vals, call.n);
+    if (want) order[m++] = Shape{want / 100, want % 100};
+    if (!(tune_force().choice && tune_force().kind == SS_TUNE_SWEEP)) {
+        for (const Shape &sh : vals ? shapes_valued : shapes_01)
+            if (sh.block * 100 + sh.ipt != want) order[m++] = sh;
+    }
+    for (int o = 0; o < m; ++o) {
+        const Shape &sh = order[o];
         const int64_t seg = (int64_t)sh.block * sh.ipt;
         const int64_t G = ceil_div(call.n, seg);
         // a few hundred segments at most: the all-to-all exchange reads G

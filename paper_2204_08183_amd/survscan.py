@@ -66,6 +66,20 @@ SIGNATURES = {
                                   _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_grad_hess_f32": (_i32, [_i32, _i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ss_tune_get": (_i32, [_i32, _i32, _i32, _i32, _i64]),
+    "ss_tune_has": (_i32, [_i32, _i32, _i32, _i32, _i64]),
+    "ss_tune_set": (_i32, [_i32, _i32, _i32, _i32, _i64, _i32]),
+    "ss_tune_clear": (_i32, []),
+    "ss_tune_save": (_i32, [ctypes.c_char_p]),
+    "ss_tune_load": (_i32, [ctypes.c_char_p, ctypes.POINTER(_i32)]),
+    "ss_autotune_grad_hess": (_i32, [_i32, _i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
+                                     _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32,
+                                     ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float),
+                                     _vp]),
+    "ss_autotune_sweep": (_i32, [_i32, _i32, _f64, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp,
+                                 _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                 _vp, _vp, _vp, _sz, _i32, ctypes.POINTER(_i32),
+                                 ctypes.POINTER(ctypes.c_float), _vp]),
     "ss_cv_stride": (_i64, [_i64]),
     "ss_cv_prepare_workspace_bytes": (_sz, [_i64, _i32]),
     "ss_cv_prepare": (_i32, [_i32, _i64, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -87,6 +101,16 @@ SIGNATURES = {
     "ss_eta_gradient": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                _vp, _sz, _vp]),
 }
+
+
+TUNE_GRAD_HESS = 0
+TUNE_SWEEP = 1
+STORAGE_F64 = 0
+STORAGE_F32 = 1
+STORAGE_F32_SUMS32 = 2
+STORAGES = {"f64": STORAGE_F64, "f32": STORAGE_F32, "f32x64": STORAGE_F32_SUMS32}
+GRAD_HESS_IPTS = (4, 8, 16, 32)
+SWEEP_SHAPES = (25616, 51208, 25608, 51216)
 
 
 class SurvScanError(RuntimeError):
@@ -132,6 +156,42 @@ def _stream(device):
 
 def chunk_count(n):
     return int(load().ss_chunk_count(n))
+
+
+def tune_get(kind, model, storage, valued, n):
+    """The launch shape in effect for a key (see ss_tune_get)."""
+    r = load().ss_tune_get(kind, MODELS[model], STORAGES[storage], int(bool(valued)), n)
+    if r < 0:
+        check(r, "ss_tune_get")
+    return r
+
+
+def tune_has(kind, model, storage, valued, n):
+    r = load().ss_tune_has(kind, MODELS[model], STORAGES[storage], int(bool(valued)), n)
+    if r < 0:
+        check(r, "ss_tune_has")
+    return bool(r)
+
+
+def tune_set(kind, model, storage, valued, n, choice):
+    check(load().ss_tune_set(kind, MODELS[model], STORAGES[storage], int(bool(valued)), n,
+                             int(choice)), "ss_tune_set")
+
+
+def tune_clear():
+    check(load().ss_tune_clear(), "ss_tune_clear")
+
+
+def tune_save(path):
+    check(load().ss_tune_save(os.fsencode(path)), "ss_tune_save")
+
+
+def tune_load(path):
+    """Adds the entries of a saved table measured on this GPU architecture;
+    returns how many were taken."""
+    count = ctypes.c_int32(0)
+    check(load().ss_tune_load(os.fsencode(path), ctypes.byref(count)), "ss_tune_load")
+    return int(count.value)
 
 
 class Workspace:
@@ -312,6 +372,63 @@ class Problem:
                                  _stream(self.device))
         check(rc, "ss_ccd_sweep")
 
+    def autotune(self, j=0, reps=20, e32=None, storage="f64", sweep=True, sweep_coords=64,
+                 penalty="l1", lam=1.0, sweep_reps=3, cache=None):
+        """Times the launch-shape candidates on this problem and stores the
+        fastest in the library's table (ss_autotune_grad_hess for coordinate
+        j; with `sweep`, ss_autotune_sweep over the first `sweep_coords`
+        coordinates on scratch copies of the state).  With `cache` (a file
+        path) entries measured earlier on this GPU architecture are loaded
+        first and keys already present are not timed again; the table is
+        saved there afterwards.  Returns {"grad_hess": (choice, us per
+        candidate), "sweep": (choice, us per candidate) or None}."""
+        lib = load()
+        valued = self.vals_sorted is not None
+        if cache and os.path.exists(cache):
+            tune_load(cache)
+        res = {"grad_hess": None, "sweep": None}
+        e = self.e if storage == "f64" else e32
+        if e is None:
+            raise SurvScanError("autotune: FP32 storage needs e32 (make_e32)")
+        if not (cache and tune_has(TUNE_GRAD_HESS, self.model_name, storage, valued, self.n)):
+            choice = ctypes.c_int32(0)
+            us = (ctypes.c_float * 4)()
+            out = torch.empty(3, dtype=torch.float64, device=self.device)
+            rc = lib.ss_autotune_grad_hess(
+                self.model, STORAGES[storage], self.n, self.p, int(j), _p(e), _p(self.d8),
+                _p(self.d32), _p(self.w_comp), _p(self.g_end), _p(self.col_ptr),
+                _p(self.rows_sorted), _p(self.vals_sorted), _p(self.chunk_ptr), _p(self.c),
+                _p(out), self.ws.ptr, self.ws.nbytes, int(reps), ctypes.byref(choice), us,
+                _stream(self.device))
+            check(rc, "ss_autotune_grad_hess")
+            res["grad_hess"] = (int(choice.value), [float(x) for x in us])
+        if sweep and storage == "f64" and not (
+                cache and tune_has(TUNE_SWEEP, self.model_name, "f64", valued, self.n)):
+            jb, je = 0, min(self.p, int(sweep_coords))
+            eta_s = torch.empty_like(self.eta)
+            e_s = torch.empty_like(self.e)
+            beta_s = torch.empty_like(self.beta)
+            delta_s = torch.empty_like(self.delta)
+            steps_s = torch.empty_like(self.steps)
+            choice = ctypes.c_int32(0)
+            us = (ctypes.c_float * 4)()
+            rc = lib.ss_autotune_sweep(
+                self.model, PENALTIES[penalty], float(lam), self.n, self.p, jb, je,
+                _p(self.eta), _p(self.e), _p(self.d8), _p(self.d32), _p(self.w_comp),
+                _p(self.g_end), _p(self.col_ptr), _p(self.rows_sorted), _p(self.vals_sorted),
+                _p(self.chunk_ptr), _p(self.c), _p(self.beta), _p(self.delta), _p(eta_s),
+                _p(e_s), _p(beta_s), _p(delta_s), _p(steps_s), self.ws.ptr, self.ws.nbytes,
+                int(sweep_reps), ctypes.byref(choice), us, _stream(self.device))
+            if rc != SS_EUNSUPPORTED:  # too large for any persistent shape
+                check(rc, "ss_autotune_sweep")
+                res["sweep"] = (int(choice.value), [float(x) for x in us])
+        if cache:
+            d = os.path.dirname(cache)
+            if d:
+                os.makedirs(d, exist_ok=True)
+            tune_save(cache)
+        return res
+
     def workspace_error(self):
         flag = ctypes.c_int32(0)
         check(load().ss_workspace_error(self.ws.ptr, ctypes.byref(flag),
@@ -410,6 +527,63 @@ class CrossValidation:
                                  _p(self.delta), _p(g12_out), self.ws.ptr, self.ws.nbytes,
                                  _stream(self.prob.device)),
               "ss_cv_sweep")
+
+    def autotune(self, j=0, reps=20, e32=None, storage="f64", sweep=True, sweep_coords=64,
+                 penalty="l1", lam=1.0, sweep_reps=3, cache=None):
+        """Times the launch-shape candidates on this problem and stores the
+        fastest in the library's table (ss_autotune_grad_hess for coordinate
+        j; with `sweep`, ss_autotune_sweep over the first `sweep_coords`
+        coordinates on scratch copies of the state).  With `cache` (a file
+        path) entries measured earlier on this GPU architecture are loaded
+        first and keys already present are not timed again; the table is
+        saved there afterwards.  Returns {"grad_hess": (choice, us per
+        candidate), "sweep": (choice, us per candidate) or None}."""
+        lib = load()
+        valued = self.vals_sorted is not None
+        if cache and os.path.exists(cache):
+            tune_load(cache)
+        res = {"grad_hess": None, "sweep": None}
+        e = self.e if storage == "f64" else e32
+        if e is None:
+            raise SurvScanError("autotune: FP32 storage needs e32 (make_e32)")
+        if not (cache and tune_has(TUNE_GRAD_HESS, self.model_name, storage, valued, self.n)):
+            choice = ctypes.c_int32(0)
+            us = (ctypes.c_float * 4)()
+            out = torch.empty(3, dtype=torch.float64, device=self.device)
+            rc = lib.ss_autotune_grad_hess(
+                self.model, STORAGES[storage], self.n, self.p, int(j), _p(e), _p(self.d8),
+                _p(self.d32), _p(self.w_comp), _p(self.g_end), _p(self.col_ptr),
+                _p(self.rows_sorted), _p(self.vals_sorted), _p(self.chunk_ptr), _p(self.c),
+                _p(out), self.ws.ptr, self.ws.nbytes, int(reps), ctypes.byref(choice), us,
+                _stream(self.device))
+            check(rc, "ss_autotune_grad_hess")
+            res["grad_hess"] = (int(choice.value), [float(x) for x in us])
+        if sweep and storage == "f64" and not (
+                cache and tune_has(TUNE_SWEEP, self.model_name, "f64", valued, self.n)):
+            jb, je = 0, min(self.p, int(sweep_coords))
+            eta_s = torch.empty_like(self.eta)
+            e_s = torch.empty_like(self.e)
+            beta_s = torch.empty_like(self.beta)
+            delta_s = torch.empty_like(self.delta)
+            steps_s = torch.empty_like(self.steps)
+            choice = ctypes.c_int32(0)
+            us = (ctypes.c_float * 4)()
+            rc = lib.ss_autotune_sweep(
+                self.model, PENALTIES[penalty], float(lam), self.n, self.p, jb, je,
+                _p(self.eta), _p(self.e), _p(self.d8), _p(self.d32), _p(self.w_comp),
+                _p(self.g_end), _p(self.col_ptr), _p(self.rows_sorted), _p(self.vals_sorted),
+                _p(self.chunk_ptr), _p(self.c), _p(self.beta), _p(self.delta), _p(eta_s),
+                _p(e_s), _p(beta_s), _p(delta_s), _p(steps_s), self.ws.ptr, self.ws.nbytes,
+                int(sweep_reps), ctypes.byref(choice), us, _stream(self.device))
+            if rc != SS_EUNSUPPORTED:  # too large for any persistent shape
+                check(rc, "ss_autotune_sweep")
+                res["sweep"] = (int(choice.value), [float(x) for x in us])
+        if cache:
+            d = os.path.dirname(cache)
+            if d:
+                os.makedirs(d, exist_ok=True)
+            tune_save(cache)
+        return res
 
     def workspace_error(self):
         """Non-zero if a bounded wait of a two-half launch gave up."""

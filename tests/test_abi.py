@@ -156,3 +156,58 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
         ss.load()
     with pytest.raises(ss.SurvScanError):
         ss.Problem("cox", [1.0, 2.0], [1, 0], [0, 1], [0], None, "cpu")
+
+
+def test_tune_table_host_logic(lib):
+    """The launch-shape table (no launch, no GPU): built-in rule, pinning,
+    size buckets of ceil(log2 n), impossible choices, clearing."""
+    G, S = ss.TUNE_GRAD_HESS, ss.TUNE_SWEEP
+    ss.tune_clear()
+    try:
+        # the built-in rule: tiles of 2048 positions up to 1.5 M, 4096 above
+        assert ss.tune_get(G, "cox", "f64", False, 1_000_000) == 8
+        assert ss.tune_get(G, "cox", "f64", False, 3 << 19) == 8
+        assert ss.tune_get(G, "cox", "f64", False, (3 << 19) + 1) == 16
+        assert ss.tune_get(S, "fg", "f64", True, 1000) == 0
+        assert not ss.tune_has(G, "cox", "f64", False, 1000)
+        ss.tune_set(G, "cox", "f64", False, 1000, 32)
+        # 513 ... 1024 share the bucket ceil(log2 n) = 10
+        for n in (513, 1000, 1024):
+            assert ss.tune_get(G, "cox", "f64", False, n) == 32
+            assert ss.tune_has(G, "cox", "f64", False, n)
+        assert ss.tune_get(G, "cox", "f64", False, 1025) == 8
+        assert ss.tune_get(G, "cox", "f64", False, 512) == 8
+        # other models, storages and designs are separate keys
+        assert ss.tune_get(G, "fg", "f64", False, 1000) == 8
+        assert ss.tune_get(G, "cox", "f32", False, 1000) == 8
+        assert ss.tune_get(G, "cox", "f64", True, 1000) == 8
+        ss.tune_set(S, "cox", "f64", False, 1000, 51208)
+        assert ss.tune_get(S, "cox", "f64", False, 1000) == 51208
+        for kind, model, storage, choice in ((G, "cox", "f64", 12), (S, "cox", "f64", 25612),
+                                             (S, "fg", "f64", 51216), (S, "cox", "f32", 25616)):
+            assert lib.ss_tune_set(kind, ss.MODELS[model], ss.STORAGES[storage], 0, 1000,
+                                   choice) == ss.SS_EINVAL
+        assert lib.ss_tune_set(7, 0, 0, 0, 1000, 8) == ss.SS_EINVAL
+        assert lib.ss_tune_get(0, 5, 0, 0, 1000) == ss.SS_EINVAL
+        assert lib.ss_tune_get(0, 0, 3, 0, 1000) == ss.SS_EINVAL
+        assert lib.ss_tune_get(0, 0, 0, 0, 0) == ss.SS_EINVAL
+        ss.tune_set(G, "cox", "f64", False, 1000, 0)   # removes the entry
+        assert not ss.tune_has(G, "cox", "f64", False, 1000)
+        ss.tune_clear()
+        assert not ss.tune_has(S, "cox", "f64", False, 1000)
+    finally:
+        ss.tune_clear()
+
+
+def test_autotune_rejects_bad_arguments(lib):
+    choice = ctypes.c_int32(0)
+    args = [None] * 11 + [None, 0]
+    assert lib.ss_autotune_grad_hess(0, 0, 100, 1, 0, *args, 0, ctypes.byref(choice), None,
+                                     None) == ss.SS_EINVAL
+    assert lib.ss_autotune_grad_hess(0, 5, 100, 1, 0, *args, 10, ctypes.byref(choice), None,
+                                     None) == ss.SS_EINVAL
+    sargs = [None] * 18 + [None, 0]
+    assert lib.ss_autotune_sweep(0, 1, 1.0, 100, 4, 2, 2, *sargs, 3, ctypes.byref(choice),
+                                 None, None) == ss.SS_EINVAL
+    assert lib.ss_autotune_sweep(0, 1, 0.0, 100, 4, 0, 2, *sargs, 3, ctypes.byref(choice),
+                                 None, None) == ss.SS_EINVAL

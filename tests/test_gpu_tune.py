@@ -1,0 +1,166 @@
+"""GPU: every launch shape the autotuner may pick computes the same results.
+
+  * ss_grad_hess at every positions-per-thread choice (tiles of 1024 ...
+    8192 positions), both models, 0/1 and valued columns, tie runs across
+    tile boundaries and runs of more than 255 events, FP64 and both FP32
+    storages, against the oracle (1e-10 condition-scaled; FP32 sums 1e-5).
+  * ss_ccd_sweep at every persistent segment shape against the oracle's
+    coordinate descent.
+  * The tuning calls themselves: a valid choice, stored in the table, and
+    a save/load round trip of the table.
+The table is process-wide: every test leaves it empty.
+"""
+import numpy as np
+import pytest
+
+from oracle import ccd as occd, cv as ocv, prep as oprep, scan as oscan
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2204_08183_amd import survscan as ss  # noqa: E402
+
+from test_gpu_parity import assert_coord, gpu_problem, make_case, xcol  # noqa: E402
+
+G, S = ss.TUNE_GRAD_HESS, ss.TUNE_SWEEP
+
+
+@pytest.fixture(autouse=True)
+def _empty_table():
+    ss.tune_clear()
+    yield
+    ss.tune_clear()
+
+
+SHAPE_CASES = [
+    # model, n, p, seed, ties, density, valued
+    ("cox", 1, 2, 70, 0, 1.0, False),
+    ("fg", 3000, 3, 71, 0, 0.1, True),
+    ("cox", 20_000, 3, 72, 3, 0.2, False),       # runs of more than 255 events
+    ("fg", 65_537, 3, 73, 700, 0.05, False),
+    ("cox", 100_001, 2, 74, 50, 0.05, True),
+    ("fg", 1_000_003, 2, 75, 1500, 0.05, False),  # 255+ event runs across tiles
+    ("cox", 2_000_003, 2, 76, 1500, 0.05, True),
+]
+
+
+@pytest.mark.parametrize("ipt", ss.GRAD_HESS_IPTS)
+@pytest.mark.parametrize("model,n,p,seed,ties,density,valued", SHAPE_CASES)
+def test_every_tile_shape_matches_oracle(ipt, model, n, p, seed, ties, density, valued):
+    c = make_case(model, n, p, seed, ties, density, valued)
+    prob = gpu_problem(model, c)
+    ss.tune_set(G, model, "f64", valued, n, ipt)
+    assert ss.tune_get(G, model, "f64", valued, n) == ipt
+    pr = oscan.Prepared(model, c["y"], c["status"])
+    for j in range(p):
+        got = prob.grad_hess(j).cpu().numpy()
+        assert_coord(got, pr.coordinate(c["eta"], xcol(c, j)), (ipt, model, n, j))
+    # the likelihood goes through the same kernel
+    beta = np.zeros(p)
+    ll = float(prob.loglik(beta).cpu()[0])
+    want = pr.coordinate(c["eta"], np.zeros(n))
+    assert abs(-ll - want["L"]) <= 1e-10 * want["scale_L"] + 1e-300
+    assert prob.workspace_error() == 0
+
+
+@pytest.mark.parametrize("ipt", ss.GRAD_HESS_IPTS)
+@pytest.mark.parametrize("model,n,valued", [("cox", 300_001, False), ("fg", 70_001, True),
+                                            ("cox", 1_700_001, True)])
+def test_every_tile_shape_fp32_storage(ipt, model, n, valued):
+    c = make_case(model, n, 2, 80 + ipt, 400, 0.1, valued)
+    prob = gpu_problem(model, c)
+    e32, shift = prob.make_e32()
+    m = float(shift.cpu()[0])
+    nev = float(np.sum(oprep.event_indicator(model, c["status"])))
+    # the oracle on the rounded e (FP64 sums) and on the FP64 e (FP32 sums)
+    e_sorted = e32.double().cpu().numpy()
+    eta_r = np.empty(n)
+    eta_r[prob.perm.cpu().numpy()] = np.log(e_sorted)
+    pr = oscan.Prepared(model, c["y"], c["status"])
+    for storage in ("f32", "f32x64"):
+        ss.tune_set(G, model, storage, valued, n, ipt)
+    for j in range(2):
+        x = xcol(c, j)
+        got = prob.grad_hess_f32(j, e32, "f64").cpu().numpy()
+        assert_coord(got, pr.coordinate(eta_r, x), (ipt, model, n, j, "f32"))
+        got = prob.grad_hess_f32(j, e32, "f32x64").cpu().numpy()
+        want = pr.coordinate(c["eta"], x)
+        got[2] += m * nev
+        for k, key in enumerate(("g1", "g2", "L")):
+            assert abs(got[k] - want[key]) <= 1e-5 * want["scale_" + key] + 1e-300, \
+                (ipt, model, n, j, key)
+    assert prob.workspace_error() == 0
+
+
+@pytest.mark.parametrize("shape", ss.SWEEP_SHAPES)
+@pytest.mark.parametrize("model,valued", [("cox", False), ("fg", False), ("cox", True),
+                                          ("fg", True)])
+def test_every_sweep_shape_matches_oracle(shape, model, valued):
+    if model == "fg" and shape == 51216:
+        pytest.skip("no Fine-Gray kernel with 8192-position segments")
+    c = make_case(model, 7000, 10, 60, 20, 0.2, valued)
+    c["eta"] = np.zeros(c["n"])
+    prob = gpu_problem(model, c)
+    ss.tune_set(S, model, "f64", valued, c["n"], shape)
+    g12 = torch.zeros(3 * c["p"], dtype=torch.float64, device="cuda:0")
+    prob.sweep("l1", 2.0, g12_out=g12)
+    beta, _, eta, hist = ocv.ccd_sweeps(model, c["y"], c["status"], c["col_ptr"], c["rows"],
+                                        c["vals"], c["eta"], occd.PENALTY_L1, 2.0, 1)
+    got = g12.view(-1, 3).cpu().numpy()
+    for j in range(c["p"]):
+        g1, g2, s1, s2 = hist[j]
+        assert abs(got[j, 0] - g1) <= 1e-10 * s1, (shape, j)
+        assert abs(got[j, 1] - g2) <= 1e-10 * s2, (shape, j)
+    np.testing.assert_allclose(prob.beta.cpu().numpy(), beta, rtol=1e-9, atol=1e-13)
+    assert prob.workspace_error() == 0
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+def test_autotune_picks_and_stores_a_shape(model, tmp_path):
+    c = make_case(model, 200_000, 70, 90, 0, 0.05)
+    c["eta"] = np.zeros(c["n"])
+    prob = gpu_problem(model, c)
+    before = prob.beta.clone(), prob.eta.clone(), prob.delta.clone()
+    res = prob.autotune(j=1, reps=5, sweep=True, sweep_coords=16, sweep_reps=2)
+    choice, us = res["grad_hess"]
+    assert choice in ss.GRAD_HESS_IPTS and all(t > 0 for t in us)
+    assert us[ss.GRAD_HESS_IPTS.index(choice)] == min(us)
+    assert ss.tune_has(G, model, "f64", False, c["n"])
+    assert ss.tune_get(G, model, "f64", False, c["n"]) == choice
+    shape, sus = res["sweep"]
+    assert shape in ss.SWEEP_SHAPES
+    assert ss.tune_get(S, model, "f64", False, c["n"]) == shape
+    # tuning the sweep works on scratch copies: the problem's state is intact
+    for a, b in zip(before, (prob.beta, prob.eta, prob.delta)):
+        assert torch.equal(a, b)
+    # the tuned launch still matches the oracle
+    pr = oscan.Prepared(model, c["y"], c["status"])
+    assert_coord(prob.grad_hess(3).cpu().numpy(), pr.coordinate(c["eta"], xcol(c, 3)))
+    # save, clear, load: the same entries come back
+    path = str(tmp_path / "tune.txt")
+    ss.tune_save(path)
+    ss.tune_clear()
+    assert not ss.tune_has(G, model, "f64", False, c["n"])
+    assert ss.tune_load(path) == 2
+    assert ss.tune_get(G, model, "f64", False, c["n"]) == choice
+    assert ss.tune_get(S, model, "f64", False, c["n"]) == shape
+    # entries of another architecture are ignored
+    with open(path) as f:
+        lines = f.read().splitlines()
+    other = [lines[0]] + ["gfx000" + ln[ln.index(" "):] for ln in lines[1:]]
+    with open(path, "w") as f:
+        f.write("\n".join(other) + "\n")
+    ss.tune_clear()
+    assert ss.tune_load(path) == 0
+    # a cached autotune loads instead of timing again
+    ss.tune_clear()
+    cache = str(tmp_path / "cache" / "tune.txt")
+    first = prob.autotune(j=1, reps=3, sweep=False, cache=cache)
+    assert first["grad_hess"] is not None
+    ss.tune_clear()
+    again = prob.autotune(j=1, reps=3, sweep=False, cache=cache)
+    assert again["grad_hess"] is None
+    assert ss.tune_get(G, model, "f64", False, c["n"]) == first["grad_hess"][0]
