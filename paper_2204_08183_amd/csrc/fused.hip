@@ -56,13 +56,24 @@ using namespace dev;
 // one round trip instead of two (flags, then payloads) took the look-back
 // from 11 to 5 us per tile at N = 2^27.
 //
-// Wave 0 looks back over a window of 64 predecessors per round: one load
-// round trip for a round, the nearest inclusive prefix fixes which
-// predecessors are needed, and only the needed ones that were not ready are
-// polled again.  Every predecessor started earlier (workgroups start in
-// index order on each XCD) and publishes its aggregate without waiting on
-// anyone, so the wait ends; it is bounded all the same.
-constexpr int kLbSlot = 8;  // pairs per tile slot (128 bytes)
+// Two levels.  Tiles form groups of kLbGroup = 64; the last tile of a full
+// group also publishes the group's aggregate (as soon as its members'
+// aggregates are visible) and later the group's inclusive prefix (its own).
+// A tile's look-back runs over the sequence: its predecessors in its own
+// group, then whole groups g-1, g-2, ...  With one level the inclusive
+// prefixes advance by at most one window of tiles per round trip, which
+// bounded the whole launch at large N; with groups one round reaches back
+// up to 64 groups.
+//
+// Wave 0 looks back over 64 elements of that sequence per round: one load
+// round trip for a round, the nearest inclusive prefix fixes which elements
+// are needed, and only the needed ones that were not ready are polled
+// again.  Every tile started earlier than its successors (workgroups start
+// in index order on each XCD) and publishes its aggregate without waiting on
+// anyone, and a group's aggregate waits only on its members, so every wait
+// ends; it is bounded all the same.
+constexpr int kLbSlot = 8;     // pairs per tile or group slot (128 bytes)
+constexpr int kLbGroup = 64;   // tiles per look-back group
 
 // Lanes 0 .. NC-1 of the calling wave store one pair each.
 template <int NC>
@@ -83,91 +94,67 @@ __device__ __forceinline__ void publish_pairs(u32x4 *slot, const double (&v)[NC]
     if (lane < NC) st_pair(slot + lane, x, tag);
 }
 
-// Wave 0 only; the exclusive prefix is returned in every lane.  Returns
-// false if the wait gave up (the error word is then set).
+// State of a snapshot of NC pairs: all tags equal and of this launch, else 0.
 template <int NC>
-__device__ bool look_back_pairs(const u32x4 *lb, int64_t tile, uint64_t epoch, WsHeader *hdr,
-                          double (&excl)[NC], uint64_t *lb_stats = nullptr)
+__device__ __forceinline__ uint32_t pairs_state(const u32x4 (&r)[NC], uint64_t epoch)
 {
-    // one window of 64 predecessors per round: the nearest inclusive prefix
-    // is almost always within it, and wider first rounds (128 or 256
-    // predecessors) only add polling traffic beside the data stream
-    // (N = 2^27, Cox: 686 us against 719 and 763 us)
-    constexpr int kLbW = 1;
-    const int lane = lane_id();
+    const uint64_t t0 = pair_tag(r[0]);
+    bool same = (t0 >> 2) == epoch;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) excl[c] = 0.0;
-    // tile indices fit in 32 bits (n < 2^31, tiles of at least 2048)
-    int32_t top = (int32_t)tile - 1;
+    for (int c = 1; c < NC; ++c) same = same && pair_tag(r[c]) == t0;
+    return same ? (uint32_t)(t0 & 3u) : 0u;
+}
+
+// Wave 0 only; the sum over the look-back sequence of `tile` is added to
+// excl in every lane.  The sequence: tiles tile-1 .. tile-nin (nin tiles of
+// the own group still to be summed), then groups g-1, g-2, ...; before group
+// 0 the sequence ends in an empty inclusive prefix.  Returns false if the
+// wait gave up (the error word is then set).
+template <int NC>
+__device__ bool look_back_seq(const u32x4 *lb, const u32x4 *glb, int32_t tile, int32_t nin,
+                              int32_t g, uint64_t epoch, WsHeader *hdr, double (&excl)[NC],
+                              uint64_t *lb_stats = nullptr)
+{
+    const int lane = lane_id();
+    int32_t base = 0;  // sequence index of lane 0 in this round
     uint32_t spins = 0;
     uint32_t rounds = 0, waits = 0;
-    // state of a snapshot: all tags equal and of this launch, else 0
-    auto state_of = [&](const u32x4 (&r)[NC]) -> uint32_t {
-        const uint64_t t0 = pair_tag(r[0]);
-        bool same = (t0 >> 2) == epoch;
-#pragma unroll
-        for (int c = 1; c < NC; ++c) same = same && pair_tag(r[c]) == t0;
-        return same ? (uint32_t)(t0 & 3u) : 0u;
-    };
-    while (top >= 0) {
+    for (;;) {
         ++rounds;
-        // lanes before tile 0 read the tile's own slot instead (one request
-        // per wave; a shared dummy address would be hammered by every tile)
-        const u32x4 *ptr[kLbW];
-#pragma unroll
-        for (int q = 0; q < kLbW; ++q) {
-            const int32_t t = top - lane - kWave * q;
-            ptr[q] = lb + (int64_t)(t >= 0 ? t : (int32_t)tile) * kLbSlot;
-        }
-        double val[kLbW][NC];
-        uint32_t stb = 0;  // bits 2q, 2q+1: state of predecessor top - lane - 64 q
+        // element base + lane: a tile of the own group, a group, or before
+        // the start (then the lane reads its own tile's slot: one request per
+        // wave, not a shared address every tile would hammer)
+        const int32_t el = base + lane;
+        const int32_t grp = g - 1 - (el - nin);
+        const bool is_tile = el < nin;
+        const bool before = !is_tile && grp < 0;
+        const u32x4 *ptr = is_tile ? lb + (int64_t)(tile - 1 - el) * kLbSlot
+                           : before ? lb + (int64_t)tile * kLbSlot
+                                    : glb + (int64_t)grp * kLbSlot;
+        double val[NC];
+        uint32_t st;
         {
-            u32x4 r[kLbW][NC];
-            ld_lb<kLbW, NC>(ptr, r);
+            u32x4 r[1][NC];
+            const u32x4 *pp[1] = {ptr};
+            ld_lb<1, NC>(pp, r);
+            st = before ? (uint32_t)kStateInc : pairs_state<NC>(r[0], epoch);
 #pragma unroll
-            for (int q = 0; q < kLbW; ++q) {
-                const int32_t t = top - lane - kWave * q;
-                // before tile 0: an empty inclusive prefix
-                const uint32_t st = t < 0 ? (uint32_t)kStateInc : state_of(r[q]);
-                stb |= st << (2 * q);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) val[q][c] = t < 0 ? 0.0 : pair_value(r[q][c]);
-            }
+            for (int c = 0; c < NC; ++c) val[c] = before ? 0.0 : pair_value(r[0][c]);
         }
-        // nearest inclusive prefix: first window holding one, lowest lane in it
-        int fq = -1, fl = 0;
-        auto nearest_inclusive = [&]() {
-            fq = -1;
-            fl = 0;
-#pragma unroll
-            for (int q = 0; q < kLbW; ++q) {
-                const uint64_t m = __ballot(((stb >> (2 * q)) & 3u) == kStateInc);
-                if (fq < 0 && m) {
-                    fq = q;
-                    fl = __ffsll((unsigned long long)m) - 1;
-                }
-            }
-        };
-        nearest_inclusive();
-        auto needed = [&](int q) {
-            return fq < 0 || q < fq || (q == fq && lane <= fl);
-        };
-        // poll again only the needed predecessors that were not ready
+        // nearest inclusive prefix: lowest lane holding one
+        uint64_t m = __ballot(st == kStateInc);
+        int fl = m ? __ffsll((unsigned long long)m) - 1 : kWave;
+        // poll again only the needed elements that were not ready
         for (;;) {
-            bool pend = false;
-#pragma unroll
-            for (int q = 0; q < kLbW; ++q) {
-                if (needed(q) && ((stb >> (2 * q)) & 3u) == 0u) {
-                    u32x4 r[NC];
-                    ld_pairs<NC>(ptr[q], r);
-                    const uint32_t st = state_of(r);
-                    stb |= st << (2 * q);
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) val[q][c] = pair_value(r[c]);
-                    pend = pend || st == 0u;
-                }
-            }
+            const bool pend = lane <= fl && st == 0u;
             if (!__any(pend)) break;
+            if (pend) {
+                u32x4 r[NC];
+                ld_pairs<NC>(ptr, r);
+                st = pairs_state<NC>(r, epoch);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) val[c] = pair_value(r[c]);
+            }
             ++waits;
             if (++spins > kSpinLimit) {
                 if (lane == 0)
@@ -175,30 +162,70 @@ __device__ bool look_back_pairs(const u32x4 *lb, int64_t tile, uint64_t epoch, W
                                        __HIP_MEMORY_SCOPE_AGENT);
                 return false;
             }
+            // an element polled again may now hold its inclusive prefix: the
+            // nearest one can only move closer
+            m = __ballot(st == kStateInc);
+            fl = m ? __ffsll((unsigned long long)m) - 1 : kWave;
             __builtin_amdgcn_s_sleep(2);
         }
-        // a predecessor polled again may now hold its inclusive prefix: the
-        // nearest one can only have moved closer, and every position before it
-        // is ready
-        nearest_inclusive();
-        double sum[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sum[c] = 0.0;
-#pragma unroll
-        for (int q = 0; q < kLbW; ++q) {
-            const bool take = needed(q);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) sum[c] += take ? val[q][c] : 0.0;
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) excl[c] += wave_sum(sum[c]);
-        if (fq >= 0) break;
-        top -= kWave * kLbW;
+        for (int c = 0; c < NC; ++c) excl[c] += wave_sum(lane <= fl ? val[c] : 0.0);
+        if (fl < kWave) break;
+        base += kWave;
     }
     if (lb_stats && lane == 0) *lb_stats = ((uint64_t)rounds << 32) | waits;
     return true;
 }
 
+// Wave 0 of a group's last tile: the sum of its group's other members
+// (tiles tile-1 .. tile-nin, nin < 64) once all are visible, back to the
+// nearest one holding its inclusive prefix if any; returns true in that
+// case (sum is then the tile's whole exclusive prefix).  `ok` is cleared if
+// the wait gave up (the error word is then set).
+template <int NC>
+__device__ bool group_members(const u32x4 *lb, int32_t tile, int32_t nin, uint64_t epoch,
+                              WsHeader *hdr, double (&sum)[NC], bool &ok)
+{
+    const int lane = lane_id();
+    const bool mine = lane < nin;
+    const u32x4 *ptr = lb + (int64_t)(mine ? tile - 1 - lane : tile) * kLbSlot;
+    double val[NC];
+    uint32_t st;
+    {
+        u32x4 r[1][NC];
+        const u32x4 *pp[1] = {ptr};
+        ld_lb<1, NC>(pp, r);
+        st = mine ? pairs_state<NC>(r[0], epoch) : (uint32_t)kStateAgg;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) val[c] = mine ? pair_value(r[0][c]) : 0.0;
+    }
+    uint64_t m = __ballot(st == kStateInc);
+    int fl = m ? __ffsll((unsigned long long)m) - 1 : kWave;
+    uint32_t spins = 0;
+    for (;;) {
+        const bool pend = lane <= fl && st == 0u;
+        if (!__any(pend)) break;
+        if (pend) {
+            u32x4 r[NC];
+            ld_pairs<NC>(ptr, r);
+            st = pairs_state<NC>(r, epoch);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) val[c] = pair_value(r[c]);
+        }
+        if (++spins > kSpinLimit) {
+            if (lane == 0)
+                __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+            return false;
+        }
+        m = __ballot(st == kStateInc);
+        fl = m ? __ffsll((unsigned long long)m) - 1 : kWave;
+        __builtin_amdgcn_s_sleep(2);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sum[c] += wave_sum(lane <= fl ? val[c] : 0.0);
+    return fl < kWave;
+}
 
 // Polls NP pairs until all carry `tag`; false if the wait gave up (then the
 // error word is set) or another wait already did.
@@ -369,7 +396,10 @@ __device__ void finish(const FusedCall &a, const WsView &ws, uint64_t epoch,
 // CU instead of 4) and the tile waits on its look-back far longer than on
 // its loads, so one row of 16 measured faster (0.89 ms against 0.93 ms at
 // N = 2^27).  kConsecMax keeps the choice in one place.
-constexpr int kConsecMax = 16;
+#ifndef SS_CONSEC_MAX
+#define SS_CONSEC_MAX 16
+#endif
+constexpr int kConsecMax = SS_CONSEC_MAX;
 template <int IPT>
 struct TileMap {
     static constexpr int CONSEC = IPT < kConsecMax ? IPT : kConsecMax;
@@ -566,6 +596,67 @@ __device__ __forceinline__ double x_at(uint32_t xbits, int i, const double *s_xv
     return nz ? 1.0 : 0.0;
 }
 
+// The tuple of Sec. 2.7 at one position, added to running sums S.  Cox:
+// (e, e x, e x^2); Fine-Gray adds (e w, e x w, e x^2 w).  With a 0/1 column
+// e x^2 = e x, so only the distinct components are carried (NX of them):
+// Cox 2 or 3, Fine-Gray 4 or 6; EX, EXX, EW, EXW, EXXW index them (EXX and
+// EXXW fall back on EX and EXW for 0/1 columns).
+template <int BLOCK, int MODEL, bool VALS>
+struct Tuple {
+    static constexpr bool FG = MODEL == SS_FINE_GRAY;
+    static constexpr int NX = (VALS ? 3 : 2) * (FG ? 2 : 1);
+    static constexpr int EX = 1;
+    static constexpr int EXX = VALS ? 2 : 1;
+    static constexpr int EW = VALS ? 3 : 2;
+    static constexpr int EXW = VALS ? 4 : 3;
+    static constexpr int EXXW = VALS ? 5 : 3;
+    template <typename AT>
+    __device__ static __forceinline__ void add(AT (&S)[NX], AT e, uint32_t xbits, int i,
+                                               const double *s_xv, double w)
+    {
+        const bool nz = (xbits >> i) & 1u;
+        if constexpr (VALS) {
+            const AT x = nz ? (AT)s_xv[i * BLOCK + threadIdx.x] : (AT)0;
+            const AT ex = e * x;
+            S[0] += e;
+            S[1] += ex;
+            S[2] += ex * x;
+            if constexpr (FG) {
+                const AT ew = e * (AT)w;
+                const AT exw = ew * x;
+                S[3] += ew;
+                S[4] += exw;
+                S[5] += exw * x;
+            }
+        } else {
+            S[0] += e;
+            S[1] += nz ? e : (AT)0;
+            if constexpr (FG) {
+                const AT ew = e * (AT)w;
+                S[2] += ew;
+                S[3] += nz ? ew : (AT)0;
+            }
+        }
+    }
+};
+
+// 1/x by the hardware's reciprocal estimate refined with Newton's iteration
+// r <- r + r (1 - x r) (two steps in FP64, one in FP32): within a unit or two
+// of the last place for the positive normal x of the transform.
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // The fused scan -> transform -> reduce kernel (one coordinate).
 // MODEL: SS_COX (3 tuple components) or SS_FINE_GRAY (6).  PREV: apply the
 // pending step of column jprev to eta and e first (step (1) of Sec. 2.7).
@@ -584,7 +675,6 @@ template <int BLOCK, int IPT, int MODEL, bool VALS, bool PREV, bool CARRY = fals
 __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t ntiles)
 {
     constexpr int TILE = BLOCK * IPT;
-    constexpr int NC = MODEL == SS_FINE_GRAY ? 6 : 3;
     constexpr int NW = BLOCK / kWave;
     constexpr int NR = CARRY ? 5 : 3;  // partial sums per tile
     static_assert(TILE % SS_CHUNK == 0, "tile must be whole chunks");
@@ -592,12 +682,14 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     static_assert(!F32S || std::is_same<ET, float>::value, "FP32 sums need FP32 storage");
     // arithmetic type of the sums inside a tile
     using AT = typename std::conditional<F32S, float, double>::type;
+    using Tx = Tuple<BLOCK, MODEL, VALS>;
+    constexpr int NX = Tx::NX;  // distinct tuple components
 
     __shared__ __attribute__((aligned(16))) uint8_t s_flag[TILE];
     __shared__ double s_xv[VALS ? TILE : 1];
     __shared__ double s_ep[PREV ? TILE : 1];
-    __shared__ double s_wsum[TileMap<IPT>::R][NW][NC];
-    __shared__ double s_excl[NC];
+    __shared__ double s_wsum[TileMap<IPT>::R][NW][NX];
+    __shared__ double s_excl[NX];
     __shared__ double s_red[NW * NR + NR];
     __shared__ double s_tsum[NR];
     __shared__ double s_fgw[2];
@@ -640,41 +732,47 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
             a, t0, cnt, chunk0, chunk1, s_flag, s_xv, s_ep, ev, wv, dw, &nbits);
     SS_TRACE(ws, tile, 1);
 
-    // ---- 5. the tile's aggregate: thread totals, then a block sum (the
-    // scan inside the tile waits until after the look-back, so that no
-    // per-row prefixes are held while the tile waits)
-    double agg[NC];
+    // ---- 5. thread totals per row and their wave scans (which are also the
+    // scan inside the tile: the thread's exclusive prefix within the tile is
+    // kept across the look-back, NX values per row), the tile's aggregate
+    AT texcl[R][NX];
+    double agg[NX];
     {
-        AT run[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) run[c] = (AT)0;
+        for (int q = 0; q < R; ++q) {
+            AT run[NX];
 #pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            const AT x = (AT)x_at<BLOCK, VALS>(xbits, i, s_xv);
-            const AT ei = (AT)ev[i];
-            const AT ex = ei * x;
-            run[0] += ei;
-            run[1] += ex;
-            run[2] += ex * x;
-            if (MODEL == SS_FINE_GRAY) {
-                const AT ew = ei * (AT)wv[i];
-                const AT exw = ew * x;
-                run[3] += ew;
-                run[4] += exw;
-                run[5] += exw * x;
+            for (int c = 0; c < NX; ++c) run[c] = (AT)0;
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                const int i = q * C + k;
+                Tx::add(run, (AT)ev[i], xbits, i, s_xv, wv[MODEL == SS_FINE_GRAY ? i : 0]);
             }
-        }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const AT t = dpp_wave_sum(run[c]);
-            if (lane == 0) s_wsum[0][w][c] = (double)t;
+            for (int c = 0; c < NX; ++c) {
+                const AT inc = dpp_incl_scan(run[c]);
+                texcl[q][c] = inc - run[c];
+                if (lane == kWave - 1) s_wsum[q][w][c] = (double)inc;
+            }
         }
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+        for (int c = 0; c < NX; ++c) {
             double t = 0.0;
+            AT done = (AT)0;  // rows before q
 #pragma unroll
-            for (int v = 0; v < NW; ++v) t += s_wsum[0][v][c];
+            for (int q = 0; q < R; ++q) {
+                AT before = (AT)0, row = (AT)0;
+#pragma unroll
+                for (int v = 0; v < NW; ++v) {
+                    const double sv = s_wsum[q][v][c];
+                    if (v < w) before += (AT)sv;
+                    row += (AT)sv;
+                    t += sv;
+                }
+                texcl[q][c] += done + before;
+                done += row;
+            }
             agg[c] = t;
         }
     }
@@ -683,42 +781,61 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     SS_TRACE(ws, tile, 2);
     if (w == 0) {
         u32x4 *slot = ws.lb + tile * kLbSlot;
-        double ex[NC];
+        double ex[NX];
         uint64_t *lbs = nullptr;
 #ifdef SS_TRACE_TIMES
         if (tile != ntiles - 1)
             lbs = trace_base(ws) + tile * 8 + 5;
 #endif
-        if (tile == 0) {
-            publish_pairs<NC>(slot, agg, (epoch << 2) | kStateInc);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) ex[c] = 0.0;
+        for (int c = 0; c < NX; ++c) ex[c] = 0.0;
+        const int32_t ti = (int32_t)tile;
+        const int32_t g = ti / kLbGroup, pos = ti % kLbGroup;
+        // the last tile of a full group publishes the group's slot (the last
+        // tile of the launch has no reader)
+        const bool leader = pos == kLbGroup - 1 && tile != ntiles - 1;
+        if (tile == 0) {
+            publish_pairs<NX>(slot, agg, (epoch << 2) | kStateInc);
         } else {
-            publish_pairs<NC>(slot, agg, (epoch << 2) | kStateAgg);
+            publish_pairs<NX>(slot, agg, (epoch << 2) | kStateAgg);
             SS_TRACE(ws, tile, 6);
             // a wait that gives up has set the error word; the launch still
             // runs to its end
-            (void)look_back_pairs<NC>(ws.lb, tile, epoch, ws.hdr, ex, lbs);
-            SS_TRACE(ws, tile, 7);
-            double inc[NC];
+            if (!leader) {
+                (void)look_back_seq<NX>(ws.lb, ws.glb, ti, pos, g, epoch, ws.hdr, ex, lbs);
+            } else {
+                bool ok = true;
+                if (!group_members<NX>(ws.lb, ti, pos, epoch, ws.hdr, ex, ok) && ok) {
+                    double gagg[NX];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) inc[c] = ex[c] + agg[c];
-            publish_pairs<NC>(slot, inc, (epoch << 2) | kStateInc);
+                    for (int c = 0; c < NX; ++c) gagg[c] = ex[c] + agg[c];
+                    publish_pairs<NX>(ws.glb + (int64_t)g * kLbSlot, gagg,
+                                      (epoch << 2) | kStateAgg);
+                    (void)look_back_seq<NX>(ws.lb, ws.glb, ti, 0, g, epoch, ws.hdr, ex, lbs);
+                }
+            }
+            SS_TRACE(ws, tile, 7);
+            double inc[NX];
+#pragma unroll
+            for (int c = 0; c < NX; ++c) inc[c] = ex[c] + agg[c];
+            publish_pairs<NX>(slot, inc, (epoch << 2) | kStateInc);
+            if (leader)
+                publish_pairs<NX>(ws.glb + (int64_t)g * kLbSlot, inc, (epoch << 2) | kStateInc);
         }
         if (lane == 0) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) s_excl[c] = ex[c];
+            for (int c = 0; c < NX; ++c) s_excl[c] = ex[c];
             if constexpr (CARRY) {
                 if (tile == ntiles - 1) {
-                    s_fgw[0] = ex[3] + agg[3];
-                    s_fgw[1] = ex[4] + agg[4];
+                    s_fgw[0] = ex[Tx::EW] + agg[Tx::EW];
+                    s_fgw[1] = ex[Tx::EXW] + agg[Tx::EXW];
                 }
             }
         }
     }
     __syncthreads();
     SS_TRACE(ws, tile, 3);
-    // the products of step 5 are recomputed below rather than kept live
+    // the products of step 5 are formed again below rather than kept live
     // across the look-back (registers bound how many tiles a CU holds)
     uint32_t xb = xbits;
     asm volatile("" : "+v"(xb));
@@ -726,58 +843,16 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
 #pragma unroll
         for (int i = 0; i < IPT; ++i) asm volatile("" : "+v"(wv[i]));
     }
-
-    // ---- 7. scan inside the tile, row by row: thread-serial over the row
-    // segment, DPP across the wave, one barrier across the waves
-    // exclusive prefix of this thread's segment of row q: from the start of
-    // the launch (FP64 sums) or of the tile (F32S; the carry is added at run
-    // ends)
-    AT texcl[R][NC];
+    // the tile's prefix: added to the FP64 in-tile prefixes now, or (F32S)
+    // to each run end's FP32 in-tile prefix in FP64
+    double carry[NX];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        AT run[NC];
+    for (int c = 0; c < NX; ++c) carry[c] = s_excl[c];
+    if constexpr (!F32S) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) run[c] = (AT)0;
+        for (int q = 0; q < R; ++q)
 #pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const int i = q * C + k;
-            const AT x = (AT)x_at<BLOCK, VALS>(xb, i, s_xv);
-            const AT ei = (AT)ev[i];
-            const AT ex = ei * x;
-            run[0] += ei;
-            run[1] += ex;
-            run[2] += ex * x;
-            if (MODEL == SS_FINE_GRAY) {
-                const AT ew = ei * (AT)wv[i];
-                const AT exw = ew * x;
-                run[3] += ew;
-                run[4] += exw;
-                run[5] += exw * x;
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const AT inc = dpp_incl_scan(run[c]);
-            texcl[q][c] = inc - run[c];
-            if (lane == kWave - 1) s_wsum[q][w][c] = (double)inc;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        // the tile's prefix (FP64 sums only) plus rows before q
-        AT done = F32S ? (AT)0 : (AT)s_excl[c];
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            AT before = (AT)0, row = (AT)0;
-#pragma unroll
-            for (int v = 0; v < NW; ++v) {
-                if (v < w) before += (AT)s_wsum[q][v][c];
-                row += (AT)s_wsum[q][v][c];
-            }
-            texcl[q][c] += done + before;
-            done += row;
-        }
+            for (int c = 0; c < NX; ++c) texcl[q][c] += carry[c];
     }
 
     double tot[3] = {0.0, 0.0, 0.0};
@@ -786,12 +861,8 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
         for (int c = 0; c < 3; ++c) tot[c] = ws.hdr->fg_tot[c];
     }
 
-    // ---- 8. running prefix, transform at run ends, reduction (the
-    // products are formed again, not kept from step 7)
+    // ---- 7. running prefix, transform at run ends, reduction
     asm volatile("" : "+v"(xb));
-    double carry[NC];  // F32S: the tile's FP64 prefix, added at run ends
-#pragma unroll
-    for (int c = 0; c < NC; ++c) carry[c] = F32S ? s_excl[c] : 0.0;
     AT acc_t[2] = {(AT)0, (AT)0};  // sum d G, sum d (H - G^2) of this thread
     double acc[NR];
 #pragma unroll
@@ -799,56 +870,53 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     LogSum lsum;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        AT S[NC];
+        AT S[NX];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) S[c] = texcl[q][c];
+        for (int c = 0; c < NX; ++c) S[c] = texcl[q][c];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             const int i = q * C + k;
-            const AT x = (AT)x_at<BLOCK, VALS>(xb, i, s_xv);
             const AT ei = (AT)ev[i];
-            const AT ex = ei * x;
-            S[0] += ei;
-            S[1] += ex;
-            S[2] += ex * x;
-            if (MODEL == SS_FINE_GRAY) {
+            Tx::add(S, ei, xb, i, s_xv, wv[MODEL == SS_FINE_GRAY ? i : 0]);
+            if constexpr (CARRY) {
+                // sum e w and sum e w x_j over column jnext's positions
+                const bool nb = (nbits >> i) & 1u;
                 const AT ew = ei * (AT)wv[i];
-                const AT exw = ew * x;
-                S[3] += ew;
-                S[4] += exw;
-                S[5] += exw * x;
-                if constexpr (CARRY) {
-                    if ((nbits >> i) & 1u) {
-                        acc[3] += ew;
-                        acc[4] += exw;
-                    }
-                }
+                const bool xj = (xb >> i) & 1u;
+                acc[3] += nb ? (double)ew : 0.0;
+                acc[4] += nb && xj ? (double)ew : 0.0;
             }
             int d = (int)((dw[i / 4] >> (8 * (i % 4))) & 255u);
-            if (d != 0) {
-                const int64_t kk = t0 + tile_pos<BLOCK, IPT>(i, tid);
-                if (d == 255) d = a.d32[kk];
-                // the run end's prefix; Fine-Gray adds G(Y) times the weighted
-                // suffix (the totals minus the inclusive prefix)
-                double Sd[NC];
+            if (d == 255) d = a.d32[t0 + tile_pos<BLOCK, IPT>(i, tid)];
+            // the run end's prefix S0, S1, S2; Fine-Gray adds G(Y) times the
+            // weighted suffix (the totals minus the inclusive prefix)
+            double Sd[NX];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) Sd[c] = F32S ? carry[c] + (double)S[c] : S[c];
-                double S0 = Sd[0], S1 = Sd[1], S2 = Sd[2];
-                if (MODEL == SS_FINE_GRAY) {
-                    const double g = a.g_end[kk];
-                    S0 += g * (tot[0] - Sd[3]);
-                    S1 += g * (tot[1] - Sd[4]);
-                    S2 += g * (tot[2] - Sd[5]);
-                }
-                const AT r = (AT)1 / (AT)S0;
+            for (int c = 0; c < NX; ++c) Sd[c] = F32S ? carry[c] + (double)S[c] : (double)S[c];
+            double S0 = Sd[0], S1 = Sd[Tx::EX], S2 = Sd[Tx::EXX];
+            if (MODEL == SS_FINE_GRAY) {
+                double g = 0.0;
+                if (d != 0) g = a.g_end[t0 + tile_pos<BLOCK, IPT>(i, tid)];
+                S0 += g * (tot[0] - Sd[Tx::EW]);
+                S1 += g * (tot[1] - Sd[Tx::EXW]);
+                S2 = VALS ? S2 + g * (tot[2] - Sd[Tx::EXXW]) : S1;
+            }
+            // (evaluating the transform at every position without a branch
+            // holds far more registers)
+            if (d != 0) {
+                const AT r = recip((AT)S0);
                 const AT G = (AT)S1 * r;
-                const AT H = (AT)S2 * r;
+                const AT H = VALS ? (AT)S2 * r : G;
                 const AT dd = (AT)d;
                 acc_t[0] += dd * G;
                 acc_t[1] += dd * (H - G * G);
-                if (a.want_log) lsum.add(S0, d);
+                if (a.want_log) {
+                    if (d > 1) lsum.add(S0, d);
+                    else lsum.add01(S0, 1);
+                }
             }
         }
+        lsum.renorm_all();
     }
     acc[0] = (double)acc_t[0];
     acc[1] = (double)acc_t[1];
@@ -1017,6 +1085,7 @@ bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v)
     v->hdr = (WsHeader *)p;
     off = sizeof(WsHeader);
     v->lb = take(16 * 8 * (size_t)tiles);
+    v->glb = take(16 * 8 * (size_t)groups);
     v->part = take(16 * 8 * (size_t)tiles);
     v->fg_part = take(16 * 4 * (size_t)tiles);
     v->gpart = take(16 * 8 * (size_t)groups);

@@ -143,6 +143,16 @@ struct LogSum {
         }
         renorm(m, k);
     }
+    // d in {0, 1}: no branch and no renormalisation (m stays above 2^-33
+    // for up to 32 calls between renorm_all() calls)
+    __device__ __forceinline__ void add01(double s, int d)
+    {
+        const double f = __builtin_amdgcn_frexp_mant(s);
+        const int e = __builtin_amdgcn_frexp_exp(s);
+        m *= d ? f : 1.0;
+        k += d ? e : 0;
+    }
+    __device__ __forceinline__ void renorm_all() { renorm(m, k); }
     __device__ __forceinline__ double value() const
     {
         return (double)k * 0.69314718055994530942 + log(m);
@@ -247,6 +257,17 @@ __device__ __forceinline__ void ld_pairs<1>(const u32x4 *p, u32x4 (&r)[1])
     asm volatile("global_load_dwordx4 %0, %1, off sc1\n\t"
                  "s_waitcnt vmcnt(0)"
                  : "=&v"(r[0])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs<2>(const u32x4 *p, u32x4 (&r)[2])
+{
+    asm volatile("global_load_dwordx4 %0, %2, off sc1\n\t"
+                 "global_load_dwordx4 %1, %2, off offset:16 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1])
                  : "v"(p)
                  : "memory");
 }
@@ -570,6 +591,40 @@ __device__ __forceinline__ void ld_lb<3, 3>(const u32x4 *const (&p)[3],
 }
 
 template <>
+__device__ __forceinline__ void ld_lb<2, 2>(const u32x4 *const (&p)[2],
+                                               u32x4 (&r)[2][2])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %4, off sc1\n\t"
+                 "global_load_dwordx4 %1, %4, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %5, off sc1\n\t"
+                 "global_load_dwordx4 %3, %5, off offset:16 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0][0]), "=&v"(r[0][1]), "=&v"(r[1][0]), "=&v"(r[1][1])
+                 : "v"(p[0]), "v"(p[1])
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_lb<2, 4>(const u32x4 *const (&p)[2],
+                                               u32x4 (&r)[2][4])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %8, off sc1\n\t"
+                 "global_load_dwordx4 %1, %8, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %8, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %8, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %9, off sc1\n\t"
+                 "global_load_dwordx4 %5, %9, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %6, %9, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %7, %9, off offset:48 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0][0]), "=&v"(r[0][1]), "=&v"(r[0][2]), "=&v"(r[0][3]), "=&v"(r[1][0]), "=&v"(r[1][1]), "=&v"(r[1][2]), "=&v"(r[1][3])
+                 : "v"(p[0]), "v"(p[1])
+                 : "memory");
+}
+
+template <>
 __device__ __forceinline__ void ld_lb<2, 3>(const u32x4 *const (&p)[2],
                                                u32x4 (&r)[2][3])
 {
@@ -606,6 +661,34 @@ __device__ __forceinline__ void ld_lb<2, 6>(const u32x4 *const (&p)[2],
                  "s_waitcnt vmcnt(0)"
                  : "=&v"(r[0][0]), "=&v"(r[0][1]), "=&v"(r[0][2]), "=&v"(r[0][3]), "=&v"(r[0][4]), "=&v"(r[0][5]), "=&v"(r[1][0]), "=&v"(r[1][1]), "=&v"(r[1][2]), "=&v"(r[1][3]), "=&v"(r[1][4]), "=&v"(r[1][5])
                  : "v"(p[0]), "v"(p[1])
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_lb<1, 2>(const u32x4 *const (&p)[1],
+                                               u32x4 (&r)[1][2])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %2, off sc1\n\t"
+                 "global_load_dwordx4 %1, %2, off offset:16 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0][0]), "=&v"(r[0][1])
+                 : "v"(p[0])
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_lb<1, 4>(const u32x4 *const (&p)[1],
+                                               u32x4 (&r)[1][4])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %4, off sc1\n\t"
+                 "global_load_dwordx4 %1, %4, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %4, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %4, off offset:48 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0][0]), "=&v"(r[0][1]), "=&v"(r[0][2]), "=&v"(r[0][3])
+                 : "v"(p[0])
                  : "memory");
 }
 

@@ -92,7 +92,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Layout of the workspace (every region 256-byte aligned), T = max_tiles
 // and U = ceil(T / kGroup) + 1 tile groups:
-//   WsHeader | lb[T][8] | part[T][8] | fg_part[T][4] | gpart[U][8] |
+//   WsHeader | lb[T][8] | glb[U][8] | part[T][8] | fg_part[T][4] | gpart[U][8] |
 //   fg_gpart[U][4] | sw_agg[T][8] | sw_part[T][4] | sw_step[T] |
 //   sw_pre[T][8] | sw_pub[max(T, 2 kMaxSweepBlocks)][16]
 struct alignas(256) WsHeader {
@@ -124,6 +124,7 @@ constexpr uint32_t kSpinLimit = 1u << 20;
 struct WsView {
     WsHeader *hdr;
     u32x4 *lb;        // [max_tiles][8]  look-back (aggregate / inclusive prefix)
+    u32x4 *glb;       // [groups][8]     look-back of groups of 64 tiles
     u32x4 *part;      // [max_tiles][8]  per-tile partial sums
     u32x4 *fg_part;   // [max_tiles][4]  Fine-Gray totals pass, per tile
     u32x4 *gpart;     // [groups][8]     per-group partial sums
@@ -156,6 +157,7 @@ constexpr size_t fused_ws_bytes(int64_t n)
     const int64_t npub = tiles > 2 * kMaxSweepBlocks ? tiles : 2 * kMaxSweepBlocks;
     size_t b = sizeof(WsHeader);
     b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // lb
+    b = align_up(b + 16 * 8 * (size_t)groups, 256);  // glb
     b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // part
     b = align_up(b + 16 * 4 * (size_t)tiles, 256);   // fg_part
     b = align_up(b + 16 * 8 * (size_t)groups, 256);  // gpart

@@ -44,6 +44,10 @@ SHAPE_CASES = [
     ("cox", 100_001, 2, 74, 50, 0.05, True),
     ("fg", 1_000_003, 2, 75, 1500, 0.05, False),  # 255+ event runs across tiles
     ("cox", 2_000_003, 2, 76, 1500, 0.05, True),
+    # whole groups of 64 tiles at 4096 positions: the last group's last tile
+    # is the launch's last tile (no group slot), and one position more
+    ("fg", 262_144, 2, 77, 300, 0.05, False),
+    ("cox", 262_145, 2, 78, 0, 0.3, True),
 ]
 
 
