@@ -15,6 +15,7 @@ One JSON line is printed.  Besides the throughput it carries
   cpu_baseline  the FP64 oracle (serial C scan) on a bounded sample, one
                 thread; cpu_baseline_all_cores: the same scan on every host
                 core, coordinates in parallel;
+  roofline_fg   the Fine-Gray gradient and Hessian at N = 2^27;
   precision     FP32 storage of e in the same single-pass kernel at N = 2^27;
   context       our fused kernel at N = 1e5 next to the paper's GV100 time;
   paper_sizes   the fused kernel at N = 1e5 ... 1e6 and the sweeps at
@@ -60,9 +61,14 @@ def parse():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-context", action="store_true")
     ap.add_argument("--no-cv", action="store_true")
+    ap.add_argument("--record-traffic", nargs=4, metavar="CSV",
+                    help="write the roofline kernel's calibrated traffic from rocprofv3 "
+                         "--pmc CSVs: FETCH_SIZE, WRITE_SIZE (of --only roofline), "
+                         "FETCH_SIZE, WRITE_SIZE (of --copy-calibration)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--only", choices=["cv", "eta_gradient", "fit", "precision"],
+    ap.add_argument("--only", choices=["cv", "eta_gradient", "fit", "precision", "roofline",
+                                       "roofline_fg"],
                     help="only run one of the secondary measurements (for profiling)")
     return ap.parse_args()
 
@@ -124,15 +130,15 @@ def roofline(torch, ss, gen, n, reps):
     # column's row index (4) and value (8) per non-zero
     algo = n * (8 + 1) + nnz * (4 + 8)
     achieved = algo / (us * 1e-6) / 1e9
+    ipt = ss.tune_get(ss.TUNE_GRAD_HESS, "cox", "f64", True, n)  # the tile shape launched
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
-        if t.get("kernel_sha") == kernel_hash() and t.get("n") == n:
+        if t.get("kernel_sha") == kernel_hash() and t.get("n") == n and t.get("ipt") == ipt:
             traffic = t.get("bytes_per_launch")
     err = prob.workspace_error()
     copy_gbs = copy_peak_gbs(torch)
-    ipt = ss.tune_get(ss.TUNE_GRAD_HESS, "cox", "f64", True, n)  # the tile shape launched
     del prob
     torch.cuda.empty_cache()
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -141,6 +147,108 @@ def roofline(torch, ss, gen, n, reps):
             "algo_bytes_per_launch": algo, "avg_us": round(us, 2), "reps": reps,
             "copy_peak_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
             "wait_errors": err, "tuning": tune}
+
+
+def roofline_fg(torch, ss, gen, n, reps):
+    """The Fine-Gray gradient and Hessian (a4) at N = 2^27 on the Sec. 3.2
+    competing-risks design with one 0/1 column at 5% density.  Algorithmic
+    bytes per coordinate: e, w and G(Y) (8 each) and the event count (1) per
+    subject, plus 4 per non-zero.  Two ways to run it:
+      standalone        ss_grad_hess: a totals pass (sum e w x^m), then the
+                        scan pass (the totals are needed before the scan);
+      in_sweep          one coordinate inside a sweep that launches per
+                        coordinate (the size is above the persistent
+                        sweep's): one launch, the totals carried in closed
+                        form from the previous coordinate, plus that
+                        coordinate's update of X beta."""
+    import numpy as np
+    p = 4
+    log("Fine-Gray at N=%d: Sec. 3.2 design, %d 0/1 columns at 5%%" % (n, p))
+    d = gen.fg_data(3, n, p, 0.05)
+    eta = np.random.default_rng(5).normal(0.0, 0.5, n)
+    prob = ss.Problem("fg", d["y"], d["status"], d["col_ptr"], d["rows"], None, "cuda:0")
+    prob.set_eta(eta)
+    nnz = int(d["col_ptr"][1] - d["col_ptr"][0])
+    nnz_all = int(d["rows"].size)
+    del d, eta
+    tune = tuned(prob, j=0, reps=3, sweep=False)
+    out = torch.empty(3, dtype=torch.float64, device="cuda:0")
+    for _ in range(3):
+        prob.grad_hess(0, out=out)
+    torch.cuda.synchronize()
+    us = event_time_us(torch, lambda: prob.grad_hess(0, out=out), reps)
+    algo = n * (3 * 8 + 1) + nnz * 4
+    res = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "n": n, "nnz": nnz,
+           "algo_bytes_per_coordinate": algo, "tuning": tune,
+           "standalone": {"avg_us": round(us, 2), "launches": 2,
+                          "achieved": round(algo / (us * 1e-6) / 1e9, 1),
+                          "frac": round(algo / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
+    # the per-coordinate path of a sweep over the p columns: one launch each
+    # (the first also runs the totals pass)
+    os.environ["SURVSCAN_SWEEP"] = "launch"
+    try:
+        prob.sweep("l1", 1.0)
+        torch.cuda.synchronize()
+        us_sw = event_time_us(torch, lambda: prob.sweep("l1", 1.0), 3)
+    finally:
+        del os.environ["SURVSCAN_SWEEP"]
+    per = us_sw / p
+    # per coordinate: the scan pass plus the update of the previous column
+    # (28 bytes per non-zero) and the next column's indices for the carry
+    algo_c = n * (3 * 8 + 1) + (nnz_all // p) * (4 + 4 + 28)
+    res["in_sweep"] = {"avg_us_per_coordinate": round(per, 2), "launches_per_coordinate": 1,
+                       "p": p, "achieved": round(algo_c / (per * 1e-6) / 1e9, 1),
+                       "frac": round(algo_c / (per * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                       "algo_bytes_per_coordinate": algo_c}
+    res["wait_errors"] = prob.workspace_error()
+    del prob
+    torch.cuda.empty_cache()
+    return res
+
+
+def record_traffic(paths, n):
+    """Writes the calibrated per-launch HBM traffic of the roofline kernel
+    from four rocprofv3 --pmc CSV files (FETCH_SIZE and WRITE_SIZE of
+    `bench.py --only roofline`, then of `bench.py --copy-calibration`)."""
+    import csv
+    import statistics
+
+    def values(path, pick):
+        out = []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if pick(r["Kernel_Name"]):
+                    out.append(float(r["Counter_Value"]))
+        return out
+
+    fetch_p, write_p, cfetch_p, cwrite_p = paths
+    ipt = 16
+    with open(fetch_p) as f:
+        names = {r["Kernel_Name"] for r in csv.DictReader(f) if "k_fused<256" in r["Kernel_Name"]}
+    # the roofline kernel: Cox, valued column, FP64, the most launched shape
+    counts = {}
+    for nm in names:
+        if ", 0, true, false, false, double, false>" in nm:
+            counts[nm] = len(values(fetch_p, lambda k, nm=nm: k == nm))
+    name = max(counts, key=counts.get)
+    ipt = int(name.split("k_fused<256, ")[1].split(",")[0])
+    fetch = statistics.median(values(fetch_p, lambda k: k == name))
+    write = statistics.median(values(write_p, lambda k: k == name))
+    copy = lambda k: "copyBuffer" in k  # noqa: E731
+    cf = statistics.median(values(cfetch_p, copy))
+    cw = statistics.median(values(cwrite_p, copy))
+    gib_kib = (1 << 27) * 8 / 1024.0  # the calibration copy: 1 GiB read, 1 GiB written
+    fs, ws = gib_kib / cf, gib_kib / cw
+    rec = {"kernel": "k_fused<256,%d,cox,vals>" % ipt, "n": n, "ipt": ipt,
+           "kernel_sha": kernel_hash(), "fetch_kib_raw_median": fetch,
+           "write_kib_raw_median": write, "fetch_scale": round(fs, 5),
+           "write_scale": round(ws, 5), "fetch_bytes_per_launch": int(fetch * 1024 * fs),
+           "write_bytes_per_launch": int(write * 1024 * ws),
+           "bytes_per_launch": int(fetch * 1024 * fs + write * 1024 * ws),
+           "algo_bytes_per_launch": n * (8 + 1) + n * (4 + 8)}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
 
 
 def precision(torch, ss, gen, n, reps):
@@ -423,6 +531,10 @@ def main():
               "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
+    if args.record_traffic:
+        record_traffic(args.record_traffic, args.roof_n)
+        return
+
     import numpy as np  # noqa: F401
     import torch
 
@@ -438,6 +550,14 @@ def main():
         return
     if args.only == "cv":
         print(json.dumps({"cv": cross_validation(torch, ss, gen)}), flush=True)
+        return
+    if args.only == "roofline":
+        print(json.dumps({"roofline": roofline(torch, ss, gen, args.roof_n, args.roof_reps)}),
+              flush=True)
+        return
+    if args.only == "roofline_fg":
+        print(json.dumps({"roofline_fg": roofline_fg(torch, ss, gen, args.roof_n,
+                                                     args.roof_reps)}), flush=True)
         return
     if args.only == "precision":
         print(json.dumps({"precision": precision(torch, ss, gen, args.roof_n, args.roof_reps)}),
@@ -524,6 +644,7 @@ def main():
     if not args.no_roofline:
         line["roofline"] = roofline(torch, ss, gen, args.roof_n, args.roof_reps)
     if not args.no_roofline:
+        line["roofline_fg"] = roofline_fg(torch, ss, gen, args.roof_n, args.roof_reps)
         log("FP32 storage of e at N=%d" % args.roof_n)
         line["precision"] = precision(torch, ss, gen, args.roof_n, args.roof_reps)
     if not args.no_context:

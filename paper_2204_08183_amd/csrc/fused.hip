@@ -73,7 +73,10 @@ using namespace dev;
 // anyone, and a group's aggregate waits only on its members, so every wait
 // ends; it is bounded all the same.
 constexpr int kLbSlot = 8;     // pairs per tile or group slot (128 bytes)
-constexpr int kLbGroup = 64;   // tiles per look-back group
+#ifndef SS_LB_GROUP
+#define SS_LB_GROUP 64
+#endif
+constexpr int kLbGroup = SS_LB_GROUP;   // tiles per look-back group
 
 // Lanes 0 .. NC-1 of the calling wave store one pair each.
 template <int NC>
