@@ -341,8 +341,12 @@ int32_t ss_gather_u8(int64_t n, const int32_t *perm, const uint8_t *src,
  * design) and each is CCD on its own training subjects: held-out subjects
  * carry e = 0 and drop out of every risk set, event counts and c_j count
  * training events only, and eta = X beta is kept for every subject so the
- * held-out log-likelihood can be scored at the fitted beta.  Cox model and
- * 0/1 designs (the designs of Sec. 3.2); SS_EUNSUPPORTED otherwise.
+ * held-out log-likelihood can be scored at the fitted beta.  Cox and
+ * Fine-Gray models, 0/1 designs (the designs of Sec. 3.2); SS_EUNSUPPORTED
+ * for valued designs.  Fine-Gray: each replicate's competing-event weights
+ * use the Kaplan-Meier estimate of its own training subjects (Sec. 2.2, the
+ * weight after eq. fg_l, on the replicate's data set), and its held-out
+ * likelihood that of its held-out subjects.
  *
  * Per-replicate vectors are in SORTED order, replicate r starting at
  * r * ss_cv_stride(n) elements (the stride is a multiple of 16384; the
@@ -351,7 +355,8 @@ int32_t ss_gather_u8(int64_t n, const int32_t *perm, const uint8_t *src,
  *   train_s, d8_r: R * stride bytes; d32_r: R * stride int32 (read only
  *   where d8_r = 255, no initialisation needed); eta, e: R * stride
  *   doubles; xbits: P * stride / 8 bytes; c_r, beta, delta: R * P doubles
- *   (replicate-major); g12_out: R * P * 3 doubles or NULL; out of
+ *   (replicate-major); g12_out: R * P * 3 doubles or NULL; Fine-Gray only
+ *   (NULL for Cox): w_r, g_r, g_h: R * stride doubles each; out of
  *   ss_cv_loglik: 2 R doubles; ws of ss_cv_prepare:
  *   ss_cv_prepare_workspace_bytes(n, R) bytes.
  *
@@ -361,7 +366,12 @@ int32_t ss_gather_u8(int64_t n, const int32_t *perm, const uint8_t *src,
  * per run end d8_r / d32_r (same encoding as ss_prepare), the column
  * bitmask xbits (bit k of column j, word k/32 of the column's stride/32
  * 32-bit words) and c_r[r][j] = the training events with x_kj = 1.
- * vals_sorted must be NULL (0/1 design).
+ * vals_sorted must be NULL (0/1 design).  Fine-Gray also takes the
+ * ORIGINAL-order times y (for the tie runs of the Kaplan-Meier estimates)
+ * and writes, per replicate and sorted position k, g_r = G of the training
+ * subjects at y_k, g_h = G of the held-out subjects at y_k (G(t) = product
+ * over censoring times c <= t of 1 - m_c / n_c within the subset) and
+ * w_r = 1 / g_r for training subjects with status 2, else 0.
  *
  * ss_cv_exp: e = exp(eta) at training positions, 0 elsewhere (all R).
  *
@@ -373,28 +383,33 @@ int32_t ss_gather_u8(int64_t n, const int32_t *perm, const uint8_t *src,
  * NULL.  At the end eta holds X beta and e = exp(eta) (masked) afresh.
  * One workgroup per replicate, or two (each half of the positions, one
  * exchange per coordinate, cooperative launch) when all of them fit on
- * the device at once; fixed summation order either way (deterministic for
- * a given device).  ws: ss_cv_workspace_bytes(R) bytes, 256-byte aligned,
+ * the device at once (Cox), one per replicate (Fine-Gray: the weighted
+ * totals sum e w and sum e w x_j over the replicate are carried from one
+ * coordinate to the next in closed form, a pass before the first
+ * coordinate sums them); fixed summation order either way (deterministic
+ * for a given device).  ws: ss_cv_workspace_bytes(R) bytes, 256-byte aligned,
  * zero-filled before first use (ss_workspace_init), kept between calls; a
  * bounded wait that gives up sets its error word (ss_workspace_error),
  * after which it must be zero-filled again.  Errors: SS_EINVAL for bad
  * sizes or ranges or a null pointer, SS_EWORKSPACE for a short or
- * misaligned workspace, SS_EUNSUPPORTED for Fine-Gray.
+ * misaligned workspace, SS_EUNSUPPORTED for an unknown model.
  *
- * ss_cv_loglik: out[2r] = the training log partial likelihood of replicate
- * r at its current eta, out[2r+1] = the held-out one: the held-out subjects
- * as a data set of their own (their risk sets, their events), the
+ * ss_cv_loglik: out[2r] = the training log partial (Fine-Gray: pseudo-)
+ * likelihood of replicate r at its current eta, out[2r+1] = the held-out
+ * one: the held-out subjects as a data set of their own (their risk sets,
+ * their events, for Fine-Gray their own Kaplan-Meier weights g_h), the
  * predictive log-likelihood of the fold (Sec. 2.8).  d8, d32: ss_prepare's
  * full-data counts. */
 int64_t ss_cv_stride(int64_t n);
 size_t ss_cv_prepare_workspace_bytes(int64_t n, int32_t reps);
 int32_t ss_cv_prepare(int32_t model, int64_t n, int64_t p, int32_t reps,
                       const int32_t *perm, const int8_t *status,
-                      const uint8_t *d8, const uint8_t *train,
+                      const double *y, const uint8_t *d8, const uint8_t *train,
                       const int64_t *col_ptr, const int32_t *rows_sorted,
                       const double *vals_sorted, uint8_t *train_s,
                       uint8_t *d8_r, int32_t *d32_r, uint32_t *xbits,
-                      double *c_r, void *ws, size_t ws_bytes, void *stream);
+                      double *c_r, double *w_r, double *g_r, double *g_h,
+                      void *ws, size_t ws_bytes, void *stream);
 int32_t ss_cv_exp(int64_t n, int32_t reps, const double *eta,
                   const uint8_t *train_s, double *e, void *stream);
 size_t ss_cv_workspace_bytes(int32_t reps);
@@ -402,7 +417,8 @@ int32_t ss_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n,
                     int64_t p, int32_t reps, int64_t j_begin, int64_t j_end,
                     double *eta, double *e, const uint8_t *d8_r,
                     const int32_t *d32_r, const uint8_t *train_s,
-                    const uint32_t *xbits, const double *c_r, double *beta,
+                    const uint32_t *xbits, const double *c_r,
+                    const double *w_r, const double *g_r, double *beta,
                     double *delta, double *g12_out, void *ws, size_t ws_bytes,
                     void *stream);
 int32_t ss_cv_loglik(int32_t model, int64_t n, int32_t reps,
@@ -410,7 +426,9 @@ int32_t ss_cv_loglik(int32_t model, int64_t n, int32_t reps,
                      const double *eta, const double *e,
                      const uint8_t *train_s, const uint8_t *d8,
                      const int32_t *d32, const uint8_t *d8_r,
-                     const int32_t *d32_r, double *out, void *stream);
+                     const int32_t *d32_r, const double *w_r,
+                     const double *g_r, const double *g_h, double *out,
+                     void *stream);
 
 /* ss_cv_select: the choice of the penalty strength by cross-validation
  * (Sec. 2.8, and the largest mean predictive log-likelihood as the reading

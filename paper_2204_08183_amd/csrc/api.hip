@@ -591,23 +591,24 @@ static bool bad_cv(int64_t n, int64_t p, int32_t reps)
 }
 
 int32_t ss_cv_prepare(int32_t model, int64_t n, int64_t p, int32_t reps, const int32_t *perm,
-                      const int8_t *status, const uint8_t *d8, const uint8_t *train,
-                      const int64_t *col_ptr, const int32_t *rows_sorted,
+                      const int8_t *status, const double *y, const uint8_t *d8,
+                      const uint8_t *train, const int64_t *col_ptr, const int32_t *rows_sorted,
                       const double *vals_sorted, uint8_t *train_s, uint8_t *d8_r,
-                      int32_t *d32_r, uint32_t *xbits, double *c_r, void *ws, size_t ws_bytes,
-                      void *stream)
+                      int32_t *d32_r, uint32_t *xbits, double *c_r, double *w_r, double *g_r,
+                      double *g_h, void *ws, size_t ws_bytes, void *stream)
 {
-    if (model == SS_FINE_GRAY) return SS_EUNSUPPORTED;
-    if (model != SS_COX) return SS_EUNSUPPORTED;
+    if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
     if (vals_sorted) return SS_EUNSUPPORTED;
     if (bad_cv(n, p, reps)) return SS_EINVAL;
     if (!perm || !status || !d8 || !train || !col_ptr || !rows_sorted || !train_s || !d8_r ||
         !d32_r || !xbits || !c_r)
         return SS_EINVAL;
+    if (model == SS_FINE_GRAY && (!y || !w_r || !g_r || !g_h)) return SS_EINVAL;
     if (!ws || ((uintptr_t)ws & 255) || ws_bytes < ss_cv_prepare_workspace_bytes(n, reps))
         return SS_EWORKSPACE;
-    return launch_cv_prepare(model, n, p, reps, perm, status, d8, train, col_ptr, rows_sorted,
-                             train_s, d8_r, d32_r, xbits, c_r, ws, (hipStream_t)stream);
+    return launch_cv_prepare(model, n, p, reps, perm, status, y, d8, train, col_ptr,
+                             rows_sorted, train_s, d8_r, d32_r, xbits, c_r, w_r, g_r, g_h, ws,
+                             (hipStream_t)stream);
 }
 
 int32_t ss_cv_exp(int64_t n, int32_t reps, const double *eta, const uint8_t *train_s,
@@ -627,10 +628,12 @@ size_t ss_cv_workspace_bytes(int32_t reps)
 int32_t ss_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, int64_t p,
                     int32_t reps, int64_t j_begin, int64_t j_end, double *eta, double *e,
                     const uint8_t *d8_r, const int32_t *d32_r, const uint8_t *train_s,
-                    const uint32_t *xbits, const double *c_r, double *beta, double *delta,
-                    double *g12_out, void *ws, size_t ws_bytes, void *stream)
+                    const uint32_t *xbits, const double *c_r, const double *w_r,
+                    const double *g_r, double *beta, double *delta, double *g12_out, void *ws,
+                    size_t ws_bytes, void *stream)
 {
-    if (model != SS_COX) return SS_EUNSUPPORTED;
+    if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
+    if (model == SS_FINE_GRAY && (!w_r || !g_r)) return SS_EINVAL;
     if (penalty != SS_PENALTY_NONE && penalty != SS_PENALTY_L1 && penalty != SS_PENALTY_L2)
         return SS_EUNSUPPORTED;
     if (penalty != SS_PENALTY_NONE && !(lambda > 0.0)) return SS_EINVAL;
@@ -638,21 +641,24 @@ int32_t ss_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, in
     if (!eta || !e || !d8_r || !d32_r || !train_s || !xbits || !c_r || !beta || !delta)
         return SS_EINVAL;
     if (!ws || ((uintptr_t)ws & 255) || ws_bytes < cv_ws_bytes(reps)) return SS_EWORKSPACE;
-    return launch_cv_sweep(penalty, lambda, n, p, reps, j_begin, j_end, eta, e, d8_r, d32_r,
-                           train_s, xbits, c_r, beta, delta, g12_out, ws, (hipStream_t)stream);
+    return launch_cv_sweep(model, penalty, lambda, n, p, reps, j_begin, j_end, eta, e, d8_r,
+                           d32_r, train_s, xbits, c_r, w_r, g_r, beta, delta, g12_out, ws,
+                           (hipStream_t)stream);
 }
 
 int32_t ss_cv_loglik(int32_t model, int64_t n, int32_t reps, const int32_t *perm,
                      const int8_t *status, const double *eta, const double *e,
                      const uint8_t *train_s, const uint8_t *d8, const int32_t *d32,
-                     const uint8_t *d8_r, const int32_t *d32_r, double *out, void *stream)
+                     const uint8_t *d8_r, const int32_t *d32_r, const double *w_r,
+                     const double *g_r, const double *g_h, double *out, void *stream)
 {
-    if (model != SS_COX) return SS_EUNSUPPORTED;
+    if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
     if (n < 1 || n > INT32_MAX || reps < 1 || reps > 65535) return SS_EINVAL;
     if (!perm || !status || !eta || !e || !train_s || !d8 || !d32 || !d8_r || !d32_r || !out)
         return SS_EINVAL;
+    if (model == SS_FINE_GRAY && (!w_r || !g_r || !g_h)) return SS_EINVAL;
     return launch_cv_loglik(model, n, reps, perm, status, eta, e, train_s, d8, d32, d8_r,
-                            d32_r, out, (hipStream_t)stream);
+                            d32_r, w_r, g_r, g_h, out, (hipStream_t)stream);
 }
 
 int32_t ss_cv_select(int32_t n_gamma, int32_t reps, const double *scores, double *mean,

@@ -143,6 +143,164 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_prep(int32_t model, int64_t n, 
     }
 }
 
+
+// Kaplan-Meier estimates of the censoring distribution per replicate, for
+// the Fine-Gray weights of Sec. 2.2 (reading: G(t) = prod over censoring
+// times c <= t of (1 - m_c / n_c), right-continuous): one for the training
+// subjects (the replicate's own data set) and one for the held-out subjects
+// (the data set its held-out likelihood is scored on).  In sorted order
+// (decreasing time) G at position k is the product of one factor per tie
+// run from k's run to the end: m_c / n_c are the run's censored subjects of
+// the subset and the subset's subjects at or before the run's end.  Pass 1
+// writes the factors at run ends (1 elsewhere), pass 2 turns them into the
+// suffix product (last chunk first; thread t takes the chunk's position
+// 1023 - t, so a prefix product over the threads is a suffix product over
+// the positions).  Outputs per replicate: g_r = G of the training subset and
+// g_h = G of the held-out subset at every position, w_r = I(training and
+// status 2) / g_r; the stride's padding gets G = 1, w = 0.
+__device__ __forceinline__ double wave_incl_prod(double x)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const double y = __shfl_up(x, d);
+        if (lane >= d) x *= y;
+    }
+    return x;
+}
+
+__global__ __launch_bounds__(kCvBlock) void k_cv_km(int64_t n, int64_t stride,
+                                                    const int32_t *perm, const int8_t *status,
+                                                    const double *y, const uint8_t *train_s,
+                                                    double *w_r, double *g_r, double *g_h)
+{
+    __shared__ int s_cnt[4][kCvWaves];
+    __shared__ int s_last[2][kCvWaves];
+    __shared__ double s_prod[2][kCvWaves];
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int w = tid / kWave;
+    const int64_t r = blockIdx.x;
+    const int64_t off = r * stride;
+    // pass 1: the factor of every tie run at its last position
+    int carry[4] = {0, 0, 0, 0};  // subset sizes and censored counts before the chunk
+    int carry_last[2] = {0, 0};   // censored counts at the last run end before it
+    for (int64_t base = 0; base < n; base += kCvBlock) {
+        const int64_t k = base + tid;
+        bool flag[4] = {false, false, false, false};  // train, train cens, held, held cens
+        bool re = false;
+        if (k < n) {
+            const bool tr = train_s[off + k] != 0;
+            const int8_t st = status[perm[k]];
+            flag[0] = tr;
+            flag[1] = tr && st == 0;
+            flag[2] = !tr;
+            flag[3] = !tr && st == 0;
+            re = k == n - 1 || y[perm[k + 1]] != y[perm[k]];
+        }
+        int cnt[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t b = __ballot(flag[q]);
+            cnt[q] = __popcll(b & (lanes_below(lane) | (1ull << lane)));
+            if (lane == kWave - 1) s_cnt[q][w] = __popcll(b);
+        }
+        const uint64_t bre = __ballot(re);
+        __syncthreads();
+        int tot[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int before = carry[q];
+            tot[q] = carry[q];
+            for (int v = 0; v < kCvWaves; ++v) {
+                const int c = s_cnt[q][v];
+                if (v < w) before += c;
+                tot[q] += c;
+            }
+            cnt[q] += before;  // inclusive count at k
+        }
+        // censored counts at the nearest run end below k
+        const uint64_t below = bre & lanes_below(lane);
+        const int src = below ? 63 - __clzll(below) : lane;
+        const int top = bre ? 63 - __clzll(bre) : 0;
+        int prevc[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int cc = cnt[2 * h + 1];
+            const int v_below = __shfl(cc, src);
+            const int v_top = __shfl(cc, top);
+            if (lane == 0) s_last[h][w] = bre ? v_top : -1;
+            prevc[h] = v_below;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            int prev = carry_last[h], last = carry_last[h];
+            for (int v = 0; v < kCvWaves; ++v) {
+                const int c = s_last[h][v];
+                if (c >= 0) {
+                    if (v < w) prev = c;
+                    last = c;
+                }
+            }
+            if (below) prev = prevc[h];
+            double f = 1.0;
+            if (re) {
+                const int m = cnt[2 * h + 1] - prev;
+                const int at = cnt[2 * h];
+                if (m > 0) f = 1.0 - (double)m / (double)at;
+            }
+            if (k < n) (h == 0 ? g_r : g_h)[off + k] = f;
+            carry_last[h] = last;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) carry[q] = tot[q];
+        __syncthreads();
+    }
+    // pass 2: suffix products, last chunk first
+    double carry_p[2] = {1.0, 1.0};
+    const int64_t nch = (n + kCvBlock - 1) / kCvBlock;
+    for (int64_t ch = nch - 1; ch >= 0; --ch) {
+        const int64_t k = ch * kCvBlock + (kCvBlock - 1 - tid);
+        double f[2] = {1.0, 1.0};
+        if (k < n) {
+            f[0] = g_r[off + k];
+            f[1] = g_h[off + k];
+        }
+        double inc[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            inc[h] = wave_incl_prod(f[h]);
+            if (lane == kWave - 1) s_prod[h][w] = inc[h];
+        }
+        __syncthreads();
+        double G[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            double before = carry_p[h], all = carry_p[h];
+            for (int v = 0; v < kCvWaves; ++v) {
+                const double q = s_prod[h][v];
+                if (v < w) before *= q;
+                all *= q;
+            }
+            G[h] = before * inc[h];
+            carry_p[h] = all;
+        }
+        if (k < n) {
+            const bool tr = train_s[off + k] != 0;
+            g_r[off + k] = G[0];
+            g_h[off + k] = G[1];
+            w_r[off + k] = tr && status[perm[k]] == 2 ? 1.0 / G[0] : 0.0;
+        }
+        __syncthreads();
+    }
+    for (int64_t k = n + tid; k < stride; k += kCvBlock) {
+        g_r[off + k] = 1.0;
+        g_h[off + k] = 1.0;
+        w_r[off + k] = 0.0;
+    }
+}
+
 // Column bitmask of a 0/1 design: bit k of column j is set where x_kj = 1
 // (k a sorted position).  The mask is cleared beforehand.
 __global__ __launch_bounds__(256) void k_cv_bits(int64_t p, int64_t words,
@@ -610,6 +768,323 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
         st_relaxed_u64(cv_epoch(a, r), ep0 + (uint64_t)T + 1);
 }
 
+
+// ---------------------------------------------------------------- Fine-Gray
+// One workgroup per replicate, Fine-Gray model, 0/1 design.  The tuple of
+// Sec. 2.7 has four distinct components here (e, e x, e w, e x w; x^2 = x),
+// and each run end with training events needs, besides the prefix sums,
+// G of the replicate's training subset times the weighted suffix: the
+// totals T = sum e w and Tx = sum e w x_j of the replicate minus the
+// inclusive prefixes of e w and e x w.  The totals are needed before the
+// scan, so they are carried from one coordinate to the next in closed form:
+// the step s of column j multiplies e by exp(s) at its rows, so the totals
+// of column j + 1 are A + expm1(s) D and A1 + expm1(s) D1, with A = sum e w,
+// D = sum e w x_j, A1 = sum e w x_{j+1}, D1 = sum e w x_j x_{j+1} summed
+// during the pass of column j.  A pass before the first coordinate sums the
+// totals of column j_begin.  Summation order fixed (deterministic).
+struct CvFgArgs {
+    CvArgs a;
+    const double *w;  // w_r: training competing weights, replicate-major
+    const double *g;  // g_r: G of the training subset
+};
+
+
+template <int IPT>
+__global__ __launch_bounds__(kCvBlock) void k_cv_sweep_fg(CvFgArgs f)
+{
+    const CvArgs &a = f.a;
+    constexpr int CHUNK = kCvBlock * IPT;
+    __shared__ double s_tot[2][kCvWaves][4];
+    __shared__ double s_red[kCvWaves * 4];
+    __shared__ double s_step[4];  // step, exp(step), the next column's totals
+    __shared__ int32_t s_lj[kCvList];
+    __shared__ double s_ls[kCvList];
+    __shared__ int s_ln;
+
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int w = tid / kWave;
+    const int64_t r = blockIdx.x;
+    const int64_t off = r * a.stride;
+    double *eta = a.eta + off;
+    double *e = a.e + off;
+    const double *wr = f.w + off;
+    const double *gr = f.g + off;
+    const uint8_t *d8 = a.d8 + off;
+    const int32_t *d32 = a.d32 + off;
+    const int nch = (int)min(a.stride / CHUNK, (a.n + CHUNK - 1) / CHUNK);
+    const int64_t tpos = (int64_t)tid * IPT;
+    const int64_t T = a.j_end - a.j_begin;
+    if (tid == 0) s_ln = 0;
+
+    // totals of the first coordinate
+    double tw = 0.0, twx = 0.0;
+    if (T > 0) {
+        double x[2] = {0.0, 0.0};
+        for (int ch = 0; ch < nch; ++ch) {
+            const int64_t pos = (int64_t)ch * CHUNK + tpos;
+            const uint32_t xb = cv_bits<IPT>(a, a.j_begin, pos);
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const double ew = e[pos + i] * wr[pos + i];
+                x[0] += ew;
+                x[1] += ((xb >> i) & 1u) ? ew : 0.0;
+            }
+        }
+        block_sum<2, kCvBlock>(x, s_red);
+        if (tid == 0) {
+            s_step[2] = x[0];
+            s_step[3] = x[1];
+        }
+    }
+    __syncthreads();
+    tw = s_step[2];
+    twx = s_step[3];
+
+    double s_prev = 0.0, es_prev = 1.0;
+    int64_t jp = -1;
+    // the next chunk's e, counts and column bits are loaded during the
+    // current one's arithmetic (x1: column j + 1, for the next totals); the
+    // weights are loaded with the chunk itself (fewer registers)
+    CvChunk<IPT> cur;
+    if (T > 0 && nch > 0)
+        cv_load<IPT>(a, e, d8, tpos, a.j_begin, -1, a.j_begin + 1 < a.j_end ? a.j_begin + 1 : -1,
+                     cur);
+    int par = 0;
+    for (int64_t j = a.j_begin; j < a.j_end; ++j) {
+        double cj = 0.0, bj = 0.0, dj = 0.0;
+        if (tid == 0) {
+            cj = a.c[r * a.p + j];
+            bj = a.beta[r * a.p + j];
+            dj = a.delta[r * a.p + j];
+        }
+        // carry[2], carry[3] end the pass as sum e w and sum e w x_j over the
+        // replicate (the same value in every thread)
+        double acc1 = 0.0, acc2 = 0.0, sa1 = 0.0, sd1 = 0.0;
+        double carry[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int ch = 0; ch < nch; ++ch) {
+            const int64_t pos = (int64_t)ch * CHUNK + tpos;
+            if (cur.px != 0u && s_prev != 0.0) {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i)
+                    if ((cur.px >> i) & 1u) cur.v[i] *= es_prev;
+                double2 *dst = reinterpret_cast<double2 *>(e + pos);
+#pragma unroll
+                for (int i = 0; i < IPT / 2; ++i)
+                    dst[i] = make_double2(cur.v[2 * i], cur.v[2 * i + 1]);
+            }
+            uint32_t dv[IPT];
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) dv[i] = (cur.d[i / 4] >> (8 * (i % 4))) & 0xffu;
+#pragma unroll
+            for (int i = 0; i < IPT; ++i)
+                if (dv[i] == 255u) dv[i] = (uint32_t)d32[pos + i];
+            double wv[IPT];
+            {
+                const double2 *ws = reinterpret_cast<const double2 *>(wr + pos);
+#pragma unroll
+                for (int i = 0; i < IPT / 2; ++i) {
+                    const double2 u = ws[i];
+                    wv[2 * i] = u.x;
+                    wv[2 * i + 1] = u.y;
+                }
+            }
+            CvChunk<IPT> nx;
+            const bool last = ch + 1 == nch;
+            const int64_t jn = last ? (j + 1 < a.j_end ? j + 1 : j) : j;
+            const int64_t jn1 = jn + 1 < a.j_end ? jn + 1 : -1;
+            cv_load<IPT>(a, e, d8, last ? tpos : pos + CHUNK, jn, last ? j : jp, jn1, nx);
+
+            double t[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const bool xi = (cur.x >> i) & 1u;
+                const double ew = cur.v[i] * wv[i];
+                t[0] += cur.v[i];
+                t[1] += xi ? cur.v[i] : 0.0;
+                t[2] += ew;
+                t[3] += xi ? ew : 0.0;
+                const bool x1 = (cur.x1 >> i) & 1u;
+                sa1 += x1 ? ew : 0.0;
+                sd1 += (x1 && xi) ? ew : 0.0;
+            }
+            double inc[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                inc[c] = dpp_incl_scan(t[c]);
+                if (lane == kWave - 1) s_tot[par][w][c] = inc[c];
+            }
+            __syncthreads();
+            double S[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double b, tt;
+                wave_totals_prefix(lane < kCvWaves ? s_tot[par][lane][c] : 0.0, w, b, tt);
+                S[c] = carry[c] + b + (inc[c] - t[c]);
+                carry[c] += tt;
+            }
+            par ^= 1;
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const bool xi = (cur.x >> i) & 1u;
+                const double ew = cur.v[i] * wv[i];
+                S[0] += cur.v[i];
+                S[1] += xi ? cur.v[i] : 0.0;
+                S[2] += ew;
+                S[3] += xi ? ew : 0.0;
+                const uint32_t d = dv[i];
+                if (d != 0u) {
+                    // G of the training subset at the run end
+                    const double gk = gr[pos + i];
+                    const double S0 = S[0] + gk * (tw - S[2]);
+                    const double S1 = S[1] + gk * (twx - S[3]);
+                    const double g = S1 / S0;
+                    const double dd = (double)d;
+                    acc1 = fma(dd, g, acc1);
+                    acc2 = fma(dd, g - g * g, acc2);
+                }
+            }
+            cur = nx;
+        }
+        double red[4] = {acc1, acc2, sa1, sd1};
+        block_sum<4, kCvBlock>(red, s_red);
+        if (tid == 0) {
+            const double g1 = cj - red[0];
+            const double g2 = -red[1];
+            double step = 0.0;
+            ccd_apply(g1, g2, a.penalty, a.lambda, &bj, &dj, &step);
+            a.beta[r * a.p + j] = bj;
+            a.delta[r * a.p + j] = dj;
+            if (a.g12_out) {
+                double *o = a.g12_out + (r * a.p + j) * 3;
+                o[0] = g1;
+                o[1] = g2;
+                o[2] = step;
+            }
+            const double em = expm1(step);
+            s_step[0] = step;
+            s_step[1] = exp(step);
+            s_step[2] = fma(em, carry[3], carry[2]);
+            s_step[3] = fma(em, red[3], red[2]);
+            if (step != 0.0) {
+                s_lj[s_ln] = (int32_t)j;
+                s_ls[s_ln] = step;
+                s_ln = s_ln + 1;
+            }
+        }
+        __syncthreads();
+        s_prev = s_step[0];
+        es_prev = s_step[1];
+        tw = s_step[2];
+        twx = s_step[3];
+        jp = j;
+        if (s_ln == kCvList) {
+            cv_apply_steps<IPT>(a, eta, e, a.train_s + off, s_lj, s_ls, kCvList, 0, nch, tpos,
+                                false);
+            __syncthreads();
+            if (tid == 0) s_ln = 0;
+            __syncthreads();
+        }
+    }
+    cv_apply_steps<IPT>(a, eta, e, a.train_s + off, s_lj, s_ls, s_ln, 0, nch, tpos, true);
+}
+
+// Fine-Gray training and held-out log pseudo-likelihoods (eq. fg_l on each
+// subset): a first pass sums the weighted totals of both subsets, the
+// second scans e and e w of each subset and takes d log S0 at the run ends
+// of each subset's events (S0 = prefix + G (total - weighted prefix)).
+__global__ __launch_bounds__(kCvBlock) void k_cv_loglik_fg(int64_t n, int64_t stride,
+                                                           const int32_t *perm,
+                                                           const int8_t *status,
+                                                           const double *eta, const double *e,
+                                                           const uint8_t *train_s,
+                                                           const uint8_t *d8, const int32_t *d32,
+                                                           const uint8_t *d8_r,
+                                                           const int32_t *d32_r,
+                                                           const double *w_r, const double *g_r,
+                                                           const double *g_h, double *out)
+{
+    __shared__ double s_tot[kCvWaves][4];
+    __shared__ double s_red[kCvWaves * 4];
+    __shared__ double s_t[2];
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int w = tid / kWave;
+    const int64_t r = blockIdx.x;
+    const int64_t off = r * stride;
+    // pass 1: sum e w over the training subset and over the held-out one
+    double tt[2] = {0.0, 0.0};
+    for (int64_t k = tid; k < n; k += kCvBlock) {
+        const bool tr = train_s[off + k] != 0;
+        if (tr) {
+            tt[0] += e[off + k] * w_r[off + k];
+        } else if (status[perm[k]] == 2) {
+            tt[1] += exp(eta[off + k]) / g_h[off + k];
+        }
+    }
+    block_sum<2, kCvBlock>(tt, s_red);
+    if (tid == 0) {
+        s_t[0] = tt[0];
+        s_t[1] = tt[1];
+    }
+    __syncthreads();
+    const double T0 = s_t[0], T1 = s_t[1];
+    double carry[4] = {0.0, 0.0, 0.0, 0.0}, lt = 0.0, lh = 0.0;
+    for (int64_t base = 0; base < n; base += kCvBlock) {
+        const int64_t k = base + tid;
+        double v[4] = {0.0, 0.0, 0.0, 0.0};  // e_t, e_t w_t, e_h, e_h w_h
+        double x = 0.0;
+        int dt = 0, dall = 0;
+        bool tr = false, ev = false;
+        if (k < n) {
+            tr = train_s[off + k] != 0;
+            x = eta[off + k];
+            const int8_t st = status[perm[k]];
+            ev = st == 1;
+            if (tr) {
+                v[0] = e[off + k];
+                v[1] = v[0] * w_r[off + k];
+            } else {
+                v[2] = exp(x);
+                v[3] = st == 2 ? v[2] / g_h[off + k] : 0.0;
+            }
+            dt = d8_r[off + k];
+            if (dt == 255) dt = d32_r[off + k];
+            dall = d8[k];
+            if (dall == 255) dall = d32[k];
+        }
+        double inc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            inc[c] = dpp_incl_scan(v[c]);
+            if (lane == kWave - 1) s_tot[w][c] = inc[c];
+        }
+        __syncthreads();
+        double S[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double b, t;
+            wave_totals_prefix(lane < kCvWaves ? s_tot[lane][c] : 0.0, w, b, t);
+            S[c] = carry[c] + b + inc[c];
+            carry[c] += t;
+        }
+        const int dh = dall - dt;
+        if (ev) {
+            if (tr) lt += x;
+            else lh += x;
+        }
+        if (dt > 0) lt -= (double)dt * log(S[0] + g_r[off + k] * (T0 - S[1]));
+        if (dh > 0) lh -= (double)dh * log(S[2] + g_h[off + k] * (T1 - S[3]));
+        __syncthreads();
+    }
+    double red[2] = {lt, lh};
+    block_sum<2, kCvBlock>(red, s_red);
+    if (tid == 0) {
+        out[2 * r] = red[0];
+        out[2 * r + 1] = red[1];
+    }
+}
+
 // ---------------------------------------------------------------- likelihood
 // Per replicate: the training log-likelihood (the e of the replicate, its
 // event counts) and the held-out one (exp(eta) of the held-out subjects,
@@ -727,10 +1202,11 @@ int32_t launch_cv_select(int32_t n_gamma, int32_t reps, const double *scores, do
 int64_t cv_stride(int64_t n) { return ceil_div(n, kCvAlign) * kCvAlign; }
 
 int32_t launch_cv_prepare(int32_t model, int64_t n, int64_t p, int32_t reps, const int32_t *perm,
-                          const int8_t *status, const uint8_t *d8, const uint8_t *train,
-                          const int64_t *col_ptr, const int32_t *rows_sorted, uint8_t *train_s,
-                          uint8_t *d8_r, int32_t *d32_r, uint32_t *xbits, double *c_r,
-                          void *ws, hipStream_t s)
+                          const int8_t *status, const double *y, const uint8_t *d8,
+                          const uint8_t *train, const int64_t *col_ptr,
+                          const int32_t *rows_sorted, uint8_t *train_s, uint8_t *d8_r,
+                          int32_t *d32_r, uint32_t *xbits, double *c_r, double *w_r,
+                          double *g_r, double *g_h, void *ws, hipStream_t s)
 {
     const int64_t stride = cv_stride(n);
     const int64_t words = stride / 32;
@@ -747,6 +1223,11 @@ int32_t launch_cv_prepare(int32_t model, int64_t n, int64_t p, int32_t reps, con
     hipLaunchKernelGGL(k_cv_c, dim3((unsigned)p, (unsigned)reps), dim3(256), 0, s, p, words,
                        xbits, evbits, c_r);
     SS_LAUNCH_CHECK();
+    if (model == SS_FINE_GRAY) {
+        hipLaunchKernelGGL(k_cv_km, dim3(reps), dim3(kCvBlock), 0, s, n, stride, perm, status, y,
+                           train_s, w_r, g_r, g_h);
+        SS_LAUNCH_CHECK();
+    }
     return SS_OK;
 }
 
@@ -762,11 +1243,12 @@ int32_t launch_cv_exp(int64_t n, int32_t reps, const double *eta, const uint8_t 
 
 size_t cv_ws_bytes(int32_t reps) { return 256 + (size_t)reps * kCvXchBytes; }
 
-int32_t launch_cv_sweep(int32_t penalty, double lambda, int64_t n, int64_t p, int32_t reps,
-                        int64_t j_begin, int64_t j_end, double *eta, double *e,
+int32_t launch_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, int64_t p,
+                        int32_t reps, int64_t j_begin, int64_t j_end, double *eta, double *e,
                         const uint8_t *d8_r, const int32_t *d32_r, const uint8_t *train_s,
-                        const uint32_t *xbits, const double *c_r, double *beta, double *delta,
-                        double *g12_out, void *ws, hipStream_t s)
+                        const uint32_t *xbits, const double *c_r, const double *w_r,
+                        const double *g_r, double *beta, double *delta, double *g12_out,
+                        void *ws, hipStream_t s)
 {
     CvArgs a;
     a.n = n;
@@ -789,6 +1271,16 @@ int32_t launch_cv_sweep(int32_t penalty, double lambda, int64_t n, int64_t p, in
     a.g12_out = g12_out;
     a.hdr = reinterpret_cast<WsHeader *>(ws);
     a.xch = reinterpret_cast<char *>(ws) + 256;
+    if (model == SS_FINE_GRAY) {
+        // one workgroup per replicate (no exchange, no co-residency needed)
+        CvFgArgs f;
+        f.a = a;
+        f.w = w_r;
+        f.g = g_r;
+        hipLaunchKernelGGL((k_cv_sweep_fg<8>), dim3(reps), dim3(kCvBlock), 0, s, f);
+        SS_LAUNCH_CHECK();
+        return SS_OK;
+    }
     // two workgroups per replicate when all of them fit on the device at
     // once (a cooperative launch checks it); one per replicate otherwise.
     // SURVSCAN_CV_HALVES=1 forces one.
@@ -817,8 +1309,16 @@ int32_t launch_cv_sweep(int32_t penalty, double lambda, int64_t n, int64_t p, in
 int32_t launch_cv_loglik(int32_t model, int64_t n, int32_t reps, const int32_t *perm,
                          const int8_t *status, const double *eta, const double *e,
                          const uint8_t *train_s, const uint8_t *d8, const int32_t *d32,
-                         const uint8_t *d8_r, const int32_t *d32_r, double *out, hipStream_t s)
+                         const uint8_t *d8_r, const int32_t *d32_r, const double *w_r,
+                         const double *g_r, const double *g_h, double *out, hipStream_t s)
 {
+    if (model == SS_FINE_GRAY) {
+        hipLaunchKernelGGL(k_cv_loglik_fg, dim3(reps), dim3(kCvBlock), 0, s, n, cv_stride(n),
+                           perm, status, eta, e, train_s, d8, d32, d8_r, d32_r, w_r, g_r, g_h,
+                           out);
+        SS_LAUNCH_CHECK();
+        return SS_OK;
+    }
     hipLaunchKernelGGL(k_cv_loglik, dim3(reps), dim3(kCvBlock), 0, s, model, n, cv_stride(n),
                        perm, status, eta, e, train_s, d8, d32, d8_r, d32_r, out);
     SS_LAUNCH_CHECK();

@@ -316,22 +316,25 @@ int32_t launch_eta_gradient(int32_t model, int64_t n, const int32_t *inv_perm,
                             double *grad, double *loglik, void *ws, hipStream_t s);
 int64_t cv_stride(int64_t n);
 int32_t launch_cv_prepare(int32_t model, int64_t n, int64_t p, int32_t reps, const int32_t *perm,
-                          const int8_t *status, const uint8_t *d8, const uint8_t *train,
-                          const int64_t *col_ptr, const int32_t *rows_sorted, uint8_t *train_s,
-                          uint8_t *d8_r, int32_t *d32_r, uint32_t *xbits, double *c_r,
-                          void *ws, hipStream_t s);
+                          const int8_t *status, const double *y, const uint8_t *d8,
+                          const uint8_t *train, const int64_t *col_ptr,
+                          const int32_t *rows_sorted, uint8_t *train_s, uint8_t *d8_r,
+                          int32_t *d32_r, uint32_t *xbits, double *c_r, double *w_r,
+                          double *g_r, double *g_h, void *ws, hipStream_t s);
 int32_t launch_cv_exp(int64_t n, int32_t reps, const double *eta, const uint8_t *train_s,
                       double *e, hipStream_t s);
 size_t cv_ws_bytes(int32_t reps);
-int32_t launch_cv_sweep(int32_t penalty, double lambda, int64_t n, int64_t p, int32_t reps,
-                        int64_t j_begin, int64_t j_end, double *eta, double *e,
+int32_t launch_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n, int64_t p,
+                        int32_t reps, int64_t j_begin, int64_t j_end, double *eta, double *e,
                         const uint8_t *d8_r, const int32_t *d32_r, const uint8_t *train_s,
-                        const uint32_t *xbits, const double *c_r, double *beta, double *delta,
-                        double *g12_out, void *ws, hipStream_t s);
+                        const uint32_t *xbits, const double *c_r, const double *w_r,
+                        const double *g_r, double *beta, double *delta, double *g12_out,
+                        void *ws, hipStream_t s);
 int32_t launch_cv_loglik(int32_t model, int64_t n, int32_t reps, const int32_t *perm,
                          const int8_t *status, const double *eta, const double *e,
                          const uint8_t *train_s, const uint8_t *d8, const int32_t *d32,
-                         const uint8_t *d8_r, const int32_t *d32_r, double *out, hipStream_t s);
+                         const uint8_t *d8_r, const int32_t *d32_r, const double *w_r,
+                         const double *g_r, const double *g_h, double *out, hipStream_t s);
 int32_t launch_cv_select(int32_t n_gamma, int32_t reps, const double *scores, double *mean,
                          int32_t *best, hipStream_t s);
 int32_t launch_mixed(int32_t acc, int32_t model, int64_t n, int64_t p, int32_t j,

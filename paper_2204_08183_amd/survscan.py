@@ -83,13 +83,13 @@ SIGNATURES = {
     "ss_cv_stride": (_i64, [_i64]),
     "ss_cv_prepare_workspace_bytes": (_sz, [_i64, _i32]),
     "ss_cv_prepare": (_i32, [_i32, _i64, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                             _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_cv_exp": (_i32, [_i64, _i32, _vp, _vp, _vp, _vp]),
     "ss_cv_workspace_bytes": (_sz, [_i32]),
     "ss_cv_sweep": (_i32, [_i32, _i32, _f64, _i64, _i64, _i32, _i64, _i64, _vp, _vp, _vp, _vp,
-                           _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+                           _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_cv_loglik": (_i32, [_i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                            _vp, _vp]),
+                            _vp, _vp, _vp, _vp, _vp]),
     "ss_objective": (_i32, [_i32, _i32, _f64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                             _vp, _vp, _sz, _vp]),
     "ss_cv_select": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp]),
@@ -225,6 +225,7 @@ class Problem:
             torch.as_tensor(vals, dtype=torch.float64).to(dev).contiguous()
         self.col_ptr = col_ptr
         self.status = status
+        self.y = y
         self.perm = torch.empty(n, dtype=torch.int32, device=dev)
         self.inv_perm = torch.empty(n, dtype=torch.int32, device=dev)
         self.d8 = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -465,8 +466,8 @@ class Problem:
 
 
 class CrossValidation:
-    """R cross-validation replicates of a prepared Cox problem with a 0/1
-    design, fitted together (one workgroup per replicate).
+    """R cross-validation replicates of a prepared Cox or Fine-Gray problem
+    with a 0/1 design, fitted together in one launch per sweep.
 
     `train` is [R, n] (1 = training subject, original subject order).
     Per-replicate state lives in sorted order with replicate r at offset
@@ -488,11 +489,16 @@ class CrossValidation:
         self.d32_r = torch.empty(reps * stride, dtype=torch.int32, device=dev)
         self.xbits = torch.empty(p * stride // 32, dtype=torch.int32, device=dev)
         self.c = torch.empty(reps * p, dtype=torch.float64, device=dev)
+        fg = prob.model == FINE_GRAY
+        self.w_r = torch.empty(reps * stride, dtype=torch.float64, device=dev) if fg else None
+        self.g_r = torch.empty(reps * stride, dtype=torch.float64, device=dev) if fg else None
+        self.g_h = torch.empty(reps * stride, dtype=torch.float64, device=dev) if fg else None
         ws = Workspace(lib.ss_cv_prepare_workspace_bytes(n, reps), dev)
         check(lib.ss_cv_prepare(prob.model, n, p, reps, _p(prob.perm), _p(prob.status),
-                                _p(prob.d8), _p(train), _p(prob.col_ptr), _p(prob.rows_sorted),
-                                _p(prob.vals_sorted), _p(self.train_s), _p(self.d8_r),
-                                _p(self.d32_r), _p(self.xbits), _p(self.c), ws.ptr, ws.nbytes,
+                                _p(prob.y), _p(prob.d8), _p(train), _p(prob.col_ptr),
+                                _p(prob.rows_sorted), _p(prob.vals_sorted), _p(self.train_s),
+                                _p(self.d8_r), _p(self.d32_r), _p(self.xbits), _p(self.c),
+                                _p(self.w_r), _p(self.g_r), _p(self.g_h), ws.ptr, ws.nbytes,
                                 _stream(dev)), "ss_cv_prepare")
         del ws
         self.eta = torch.zeros(reps * stride, dtype=torch.float64, device=dev)
@@ -523,67 +529,11 @@ class CrossValidation:
         check(load().ss_cv_sweep(self.prob.model, PENALTIES[penalty], float(lam), self.prob.n,
                                  self.prob.p, self.reps, int(j_begin), int(j_end),
                                  _p(self.eta), _p(self.e), _p(self.d8_r), _p(self.d32_r),
-                                 _p(self.train_s), _p(self.xbits), _p(self.c), _p(self.beta),
-                                 _p(self.delta), _p(g12_out), self.ws.ptr, self.ws.nbytes,
+                                 _p(self.train_s), _p(self.xbits), _p(self.c), _p(self.w_r),
+                                 _p(self.g_r), _p(self.beta), _p(self.delta), _p(g12_out),
+                                 self.ws.ptr, self.ws.nbytes,
                                  _stream(self.prob.device)),
               "ss_cv_sweep")
-
-    def autotune(self, j=0, reps=20, e32=None, storage="f64", sweep=True, sweep_coords=64,
-                 penalty="l1", lam=1.0, sweep_reps=3, cache=None):
-        """Times the launch-shape candidates on this problem and stores the
-        fastest in the library's table (ss_autotune_grad_hess for coordinate
-        j; with `sweep`, ss_autotune_sweep over the first `sweep_coords`
-        coordinates on scratch copies of the state).  With `cache` (a file
-        path) entries measured earlier on this GPU architecture are loaded
-        first and keys already present are not timed again; the table is
-        saved there afterwards.  Returns {"grad_hess": (choice, us per
-        candidate), "sweep": (choice, us per candidate) or None}."""
-        lib = load()
-        valued = self.vals_sorted is not None
-        if cache and os.path.exists(cache):
-            tune_load(cache)
-        res = {"grad_hess": None, "sweep": None}
-        e = self.e if storage == "f64" else e32
-        if e is None:
-            raise SurvScanError("autotune: FP32 storage needs e32 (make_e32)")
-        if not (cache and tune_has(TUNE_GRAD_HESS, self.model_name, storage, valued, self.n)):
-            choice = ctypes.c_int32(0)
-            us = (ctypes.c_float * 4)()
-            out = torch.empty(3, dtype=torch.float64, device=self.device)
-            rc = lib.ss_autotune_grad_hess(
-                self.model, STORAGES[storage], self.n, self.p, int(j), _p(e), _p(self.d8),
-                _p(self.d32), _p(self.w_comp), _p(self.g_end), _p(self.col_ptr),
-                _p(self.rows_sorted), _p(self.vals_sorted), _p(self.chunk_ptr), _p(self.c),
-                _p(out), self.ws.ptr, self.ws.nbytes, int(reps), ctypes.byref(choice), us,
-                _stream(self.device))
-            check(rc, "ss_autotune_grad_hess")
-            res["grad_hess"] = (int(choice.value), [float(x) for x in us])
-        if sweep and storage == "f64" and not (
-                cache and tune_has(TUNE_SWEEP, self.model_name, "f64", valued, self.n)):
-            jb, je = 0, min(self.p, int(sweep_coords))
-            eta_s = torch.empty_like(self.eta)
-            e_s = torch.empty_like(self.e)
-            beta_s = torch.empty_like(self.beta)
-            delta_s = torch.empty_like(self.delta)
-            steps_s = torch.empty_like(self.steps)
-            choice = ctypes.c_int32(0)
-            us = (ctypes.c_float * 4)()
-            rc = lib.ss_autotune_sweep(
-                self.model, PENALTIES[penalty], float(lam), self.n, self.p, jb, je,
-                _p(self.eta), _p(self.e), _p(self.d8), _p(self.d32), _p(self.w_comp),
-                _p(self.g_end), _p(self.col_ptr), _p(self.rows_sorted), _p(self.vals_sorted),
-                _p(self.chunk_ptr), _p(self.c), _p(self.beta), _p(self.delta), _p(eta_s),
-                _p(e_s), _p(beta_s), _p(delta_s), _p(steps_s), self.ws.ptr, self.ws.nbytes,
-                int(sweep_reps), ctypes.byref(choice), us, _stream(self.device))
-            if rc != SS_EUNSUPPORTED:  # too large for any persistent shape
-                check(rc, "ss_autotune_sweep")
-                res["sweep"] = (int(choice.value), [float(x) for x in us])
-        if cache:
-            d = os.path.dirname(cache)
-            if d:
-                os.makedirs(d, exist_ok=True)
-            tune_save(cache)
-        return res
 
     def workspace_error(self):
         """Non-zero if a bounded wait of a two-half launch gave up."""
@@ -599,8 +549,9 @@ class CrossValidation:
         pr = self.prob
         check(load().ss_cv_loglik(pr.model, pr.n, self.reps, _p(pr.perm), _p(pr.status),
                                   _p(self.eta), _p(self.e), _p(self.train_s), _p(pr.d8),
-                                  _p(pr.d32), _p(self.d8_r), _p(self.d32_r), _p(out),
-                                  _stream(pr.device)), "ss_cv_loglik")
+                                  _p(pr.d32), _p(self.d8_r), _p(self.d32_r), _p(self.w_r),
+                                  _p(self.g_r), _p(self.g_h), _p(out), _stream(pr.device)),
+              "ss_cv_loglik")
         return out.view(self.reps, 2)
 
     def sorted_view(self, t):

@@ -113,7 +113,8 @@ def test_new_entry_points_validate_on_the_host(lib):
                                None) == ss.SS_EINVAL
     assert lib.ss_eta_gradient(0, 1000, f, f, f, f, f, f, None, None, f, f, f, ws - 1,
                                None) == ss.SS_EWORKSPACE
-    # cross-validation: sizes, Fine-Gray and valued designs unsupported
+    # cross-validation: sizes, valued designs unsupported, Fine-Gray needs its
+    # Kaplan-Meier arrays
     s = lib.ss_cv_stride(100_000)
     assert s >= 100_000 and s % 16384 == 0
     assert lib.ss_cv_stride(0) == 0
@@ -121,17 +122,28 @@ def test_new_entry_points_validate_on_the_host(lib):
     assert lib.ss_cv_prepare_workspace_bytes(100_000, 0) == 0
     assert lib.ss_cv_workspace_bytes(100) > 100 * 1024
     assert lib.ss_cv_workspace_bytes(0) == 0
-    prep = [f, f, f, f, f, f, None, f, f, f, f, f, f, big, None]
-    assert lib.ss_cv_prepare(1, 1000, 5, 10, *prep) == ss.SS_EUNSUPPORTED
+    # perm status y d8 train col_ptr rows vals train_s d8_r d32_r xbits c_r w_r g_r g_h ws
+    prep = [f, f, f, f, f, f, f, None, f, f, f, f, f, f, f, f, f, big, None]
+    assert lib.ss_cv_prepare(5, 1000, 5, 10, *prep) == ss.SS_EUNSUPPORTED
+    no_km = list(prep)
+    no_km[14] = None
+    assert lib.ss_cv_prepare(1, 1000, 5, 10, *no_km) == ss.SS_EINVAL
+    no_y = list(prep)
+    no_y[2] = None
+    assert lib.ss_cv_prepare(1, 1000, 5, 10, *no_y) == ss.SS_EINVAL
     valued = list(prep)
-    valued[6] = f
+    valued[7] = f
     assert lib.ss_cv_prepare(0, 1000, 5, 10, *valued) == ss.SS_EUNSUPPORTED
     assert lib.ss_cv_prepare(0, 1000, 5, 0, *prep) == ss.SS_EINVAL
     short = list(prep)
     short[-2] = 8
     assert lib.ss_cv_prepare(0, 1000, 5, 10, *short) == ss.SS_EWORKSPACE
-    sw = [f] * 9 + [None, f, big, None]
-    assert lib.ss_cv_sweep(1, 0, 0.0, 1000, 5, 10, 0, 5, *sw) == ss.SS_EUNSUPPORTED
+    # eta e d8_r d32_r train_s xbits c_r w_r g_r beta delta g12 ws
+    sw = [f] * 11 + [None, f, big, None]
+    assert lib.ss_cv_sweep(5, 0, 0.0, 1000, 5, 10, 0, 5, *sw) == ss.SS_EUNSUPPORTED
+    no_w = list(sw)
+    no_w[7] = None
+    assert lib.ss_cv_sweep(1, 0, 0.0, 1000, 5, 10, 0, 5, *no_w) == ss.SS_EINVAL
     assert lib.ss_cv_sweep(0, 0, 0.0, 1000, 5, 10, 0, 6, *sw) == ss.SS_EINVAL
     assert lib.ss_cv_sweep(0, 3, 0.0, 1000, 5, 10, 0, 5, *sw) == ss.SS_EUNSUPPORTED
     # a penalty needs a positive strength (l2: the prior variance; l1: gamma)
@@ -141,8 +153,12 @@ def test_new_entry_points_validate_on_the_host(lib):
     small = sw[:-2] + [16, None]
     assert lib.ss_cv_sweep(0, 0, 0.0, 1000, 5, 10, 0, 5, *small) == ss.SS_EWORKSPACE
     assert lib.ss_cv_exp(1000, 0, f, f, f, None) == ss.SS_EINVAL
-    assert lib.ss_cv_loglik(1, 1000, 10, f, f, f, f, f, f, f, f, f, f,
-                            None) == ss.SS_EUNSUPPORTED
+    # perm status eta e train_s d8 d32 d8_r d32_r w_r g_r g_h out
+    ll = [f] * 13 + [None]
+    assert lib.ss_cv_loglik(5, 1000, 10, *ll) == ss.SS_EUNSUPPORTED
+    no_gh = list(ll)
+    no_gh[11] = None
+    assert lib.ss_cv_loglik(1, 1000, 10, *no_gh) == ss.SS_EINVAL
     # FP32 path: unknown accumulation
     assert lib.ss_grad_hess_mixed(0, 9, 10, 2, 0, f, f, f, None, None, f, f, None, f, f, f,
                                   f, big, None) == ss.SS_EINVAL

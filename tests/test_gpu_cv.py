@@ -42,8 +42,15 @@ def cox_case(n, p, seed, ties=0, density=0.1):
     return d
 
 
-def make_cv(d, train):
-    prob = ss.Problem("cox", d["y"], d["status"], d["col_ptr"], d["rows"], None, DEV)
+def fg_case(n, p, seed, ties=0, density=0.1):
+    d = gen.fg_data(seed, n, p, density)
+    if ties:
+        d["y"] = gen.force_ties(d["y"], ties)
+    return d
+
+
+def make_cv(d, train, model="cox"):
+    prob = ss.Problem(model, d["y"], d["status"], d["col_ptr"], d["rows"], None, DEV)
     return prob, ss.CrossValidation(prob, train)
 
 
@@ -97,8 +104,8 @@ def test_cv_prepare_long_tie_runs():
         assert run_end_counts(d["y"][perm], dr[r]) == run_end_counts(ysub[o], want_d)
 
 
-def check_sweeps(d, train, penalty, lam, sweeps, tol, reps_to_check=None):
-    prob, cvp = make_cv(d, train)
+def check_sweeps(d, train, penalty, lam, sweeps, tol, reps_to_check=None, model="cox"):
+    prob, cvp = make_cv(d, train, model)
     R, p, n = cvp.reps, d["p"], d["n"]
     g12 = torch.zeros(R * p * 3, dtype=torch.float64, device=DEV)
     hist_gpu = []
@@ -113,7 +120,7 @@ def check_sweeps(d, train, penalty, lam, sweeps, tol, reps_to_check=None):
     ll = cvp.loglik().cpu().numpy()
     assert cvp.workspace_error() == 0
     for r in (range(R) if reps_to_check is None else reps_to_check):
-        b, dl, eta_all, hist = ocv.fit_replicate("cox", d["y"], d["status"], d["col_ptr"],
+        b, dl, eta_all, hist = ocv.fit_replicate(model, d["y"], d["status"], d["col_ptr"],
                                                  d["rows"], None, train[r], PEN[penalty], lam,
                                                  sweeps)
         for s in range(sweeps):
@@ -130,8 +137,8 @@ def check_sweeps(d, train, penalty, lam, sweeps, tol, reps_to_check=None):
         tr = train[r] == 1
         np.testing.assert_allclose(e_s[r], np.where(tr[perm], np.exp(eta_s[r]), 0.0), rtol=1e-15)
         # likelihoods at the GPU's eta
-        lt = ocv.training_loglik("cox", d["y"], d["status"], eta, train[r])
-        lh = ocv.heldout_loglik("cox", d["y"], d["status"], eta, train[r])
+        lt = ocv.training_loglik(model, d["y"], d["status"], eta, train[r])
+        lh = ocv.heldout_loglik(model, d["y"], d["status"], eta, train[r])
         assert ll[r, 0] == pytest.approx(lt, rel=1e-11, abs=1e-11)
         assert ll[r, 1] == pytest.approx(lh, rel=1e-11, abs=1e-11)
     return prob, cvp
@@ -248,8 +255,11 @@ def test_cv_rejects_unsupported():
     args = [ss._p(cvp.eta), ss._p(cvp.e), ss._p(cvp.d8_r), ss._p(cvp.d32_r),
             ss._p(cvp.train_s), ss._p(cvp.xbits), ss._p(cvp.c), ss._p(cvp.beta),
             ss._p(cvp.delta), None, cvp.ws.ptr, cvp.ws.nbytes, None]
+    args = args[:7] + [None, None] + args[7:]   # w_r, g_r: Fine-Gray only
+    # Fine-Gray without its weights
     assert lib.ss_cv_sweep(ss.FINE_GRAY, 0, 0.0, prob.n, prob.p, 3, 0, 2,
-                           *args) == ss.SS_EUNSUPPORTED
+                           *args) == ss.SS_EINVAL
+    assert lib.ss_cv_sweep(5, 0, 0.0, prob.n, prob.p, 3, 0, 2, *args) == ss.SS_EUNSUPPORTED
     assert lib.ss_cv_sweep(ss.COX, 0, 0.0, prob.n, prob.p, 3, 0, 3, *args) == ss.SS_EINVAL
     assert lib.ss_cv_sweep(ss.COX, 0, 0.0, prob.n, prob.p, 0, 0, 2, *args) == ss.SS_EINVAL
     assert lib.ss_cv_sweep(ss.COX, 9, 0.0, prob.n, prob.p, 3, 0, 2, *args) == ss.SS_EUNSUPPORTED
@@ -264,7 +274,8 @@ def test_cv_rejects_unsupported():
     with pytest.raises(ss.SurvScanError):
         ss.CrossValidation(valued, gen.cv_folds(1, d["n"], 3, 1))
     fg = gen.fg_data(1, 3000, 2, 0.1)
-    fprob = ss.Problem("fg", fg["y"], fg["status"], fg["col_ptr"], fg["rows"], None, DEV)
+    fprob = ss.Problem("fg", fg["y"], fg["status"], fg["col_ptr"], fg["rows"],
+                       np.ones(fg["rows"].size), DEV)
     with pytest.raises(ss.SurvScanError):
         ss.CrossValidation(fprob, gen.cv_folds(1, 3000, 3, 1))
 
@@ -320,3 +331,94 @@ def test_cv_path_matches_oracle():
     np.testing.assert_allclose(scores, want, rtol=1e-9, atol=1e-9)
     assert best == gammas[int(want.mean(axis=1).argmax())]
     assert len(set(np.round(scores.mean(axis=1), 6))) > 1   # the path moves
+
+
+# ---------------------------------------------------------------- Fine-Gray
+def test_cv_fg_prepare_km_matches_oracle():
+    """Per replicate: the Kaplan-Meier estimate of the censoring
+    distribution of its training subjects and of its held-out subjects at
+    every sorted position, and the training competing-event weights, against
+    the oracle's estimate on the subsets (with tie runs across the folds)."""
+    from oracle import km as okm
+    d = fg_case(20001, 3, 21, ties=700)
+    train = gen.cv_folds(22, d["n"], 4, 2)
+    prob, cvp = make_cv(d, train, "fg")
+    perm = prob.perm.cpu().numpy()
+    ys = d["y"][perm]
+    st = d["status"][perm]
+    g_r = cvp.sorted_view(cvp.g_r).cpu().numpy()
+    g_h = cvp.sorted_view(cvp.g_h).cpu().numpy()
+    w_r = cvp.sorted_view(cvp.w_r).cpu().numpy()
+    pad = cvp.w_r.view(cvp.reps, cvp.stride)[:, d["n"]:].cpu().numpy()
+    assert np.all(pad == 0.0)
+    for r in range(cvp.reps):
+        tr = train[r] == 1
+        for mask, got in ((tr, g_r[r]), (~tr, g_h[r])):
+            t, v = okm.km_censoring(d["y"][mask], d["status"][mask])
+            np.testing.assert_allclose(got, okm.km_eval(t, v, ys), rtol=1e-12, atol=0)
+        want_w = np.where(tr[perm] & (st == 2), 1.0 / g_r[r], 0.0)
+        np.testing.assert_array_equal(w_r[r], want_w)
+        # c_j counts training events of type 1 only
+        c = cvp.c.cpu().numpy().reshape(cvp.reps, d["p"])
+        for j in range(d["p"]):
+            x = ocv.column(d["n"], d["col_ptr"], d["rows"], None, j)
+            assert c[r, j] == float(np.sum(x[tr] * (d["status"][tr] == 1)))
+
+
+@pytest.mark.parametrize("penalty,lam", [("l1", 2.0), ("l2", 1.0), ("none", 0.0)])
+def test_cv_fg_sweeps_match_oracle(penalty, lam):
+    d = fg_case(7000, 8, 23, density=0.2)
+    train = gen.cv_folds(24, d["n"], 4, 2)
+    check_sweeps(d, train, penalty, lam, 2, 1e-9, model="fg")
+
+
+@pytest.mark.parametrize("n,p,ties", [(1, 2, 0), (3, 2, 0), (8193, 4, 0), (50001, 5, 40),
+                                      (16384, 3, 0), (16385, 3, 5)])
+def test_cv_fg_sizes_and_ties(n, p, ties):
+    d = fg_case(n, p, 25, ties=ties, density=0.3 if n < 10 else 0.1)
+    train = gen.cv_folds(26, n, 3, 2) if n >= 3 else np.ones((2, n), np.uint8)
+    check_sweeps(d, train, "l1", 0.5, 1, 1e-10, model="fg")
+
+
+def test_cv_fg_many_steps_in_one_launch():
+    """More non-zero steps than the kernel holds before eta is brought up to
+    date, so the carried weighted totals cross that update too."""
+    d = fg_case(2500, 700, 27, density=0.05)
+    train = gen.cv_folds(28, d["n"], 5, 1)[:2]
+    check_sweeps(d, train, "none", 0.0, 2, 1e-9, model="fg")
+
+
+def test_cv_fg_everyone_training_equals_single_sweep():
+    d = fg_case(30000, 6, 29)
+    train = np.ones((2, d["n"]), np.uint8)
+    prob, cvp = make_cv(d, train, "fg")
+    g12 = torch.zeros(2 * d["p"] * 3, dtype=torch.float64, device=DEV)
+    cvp.sweep("l1", 1.0, g12_out=g12)
+    single = torch.zeros(3 * d["p"], dtype=torch.float64, device=DEV)
+    prob.sweep("l1", 1.0, g12_out=single)
+    got = g12.cpu().numpy().reshape(2, d["p"], 3)
+    want = single.cpu().numpy().reshape(d["p"], 3)
+    np.testing.assert_allclose(got[0, :, :2], want[:, :2], rtol=1e-10, atol=1e-9)
+    assert np.array_equal(got[0], got[1])
+
+
+def test_cv_fg_ten_by_ten_design():
+    """10 x 10 cross-validation of the Fine-Gray model at N = 1e5,
+    P = 1000, one l1 sweep: replicates 0, 57 and 99 against the oracle."""
+    d = fg_case(100_000, 1000, 0, density=0.05)
+    train = gen.cv_folds(0, d["n"], 10, 10)
+    check_sweeps(d, train, "l1", float(np.sqrt(2.0)), 1, 1e-10, reps_to_check=(0, 57, 99),
+                 model="fg")
+
+
+def test_cv_fg_path_matches_oracle():
+    d = fg_case(3000, 8, 30, density=0.2)
+    train = gen.cv_folds(31, d["n"], 5, 1)
+    gammas = [16.0, 8.0, 4.0, 2.0, 1.0]
+    prob = ss.Problem("fg", d["y"], d["status"], d["col_ptr"], d["rows"], None, DEV)
+    scores, best = ss.cv_path(prob, train, gammas, sweeps=3)
+    want = np.stack([ocv.path("fg", d["y"], d["status"], d["col_ptr"], d["rows"], None,
+                              train[r], occd.PENALTY_L1, gammas, 3)
+                     for r in range(train.shape[0])], axis=1)
+    np.testing.assert_allclose(scores, want, rtol=1e-9, atol=1e-9)
+    assert best == gammas[int(want.mean(axis=1).argmax())]
