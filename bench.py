@@ -20,13 +20,14 @@ One JSON line is printed.  Besides the throughput it carries
   context       our fused kernel at N = 1e5 next to the paper's GV100 time;
   paper_sizes   the fused kernel at N = 1e5 ... 1e6 and the sweeps at
                 N = 1e5 (latency-bound sizes, not an HBM fraction);
-  eta_gradient  the full gradient in eta at N = 1e6 and 2^27;
+  eta_gradient  the full gradient in eta at N = 1e6 and 2^27, and X' times
+                it formed in sorted order (no permutation);
   fit           the l1 fits of both models to convergence at N = 1e6, with
                 the largest violation of the optimality conditions;
   cv            10-fold x 10-repetition cross-validation (100 replicates) at
-                N = 1e5, P = 1000: one l1 sweep of every replicate in one
-                launch, next to one replicate-sized problem swept alone
-                (times 100: the replicates one after another).
+                N = 1e5, P = 1000, Cox and Fine-Gray: one l1 sweep of every
+                replicate in one launch, next to the replicates as problems
+                of their own swept on 1, 2, 4 or 8 streams.
 """
 import argparse
 import hashlib
@@ -375,39 +376,106 @@ def eta_gradient(torch, ss, gen):
         prob.eta_gradient(grad, ll)
         torch.cuda.synchronize()
         us = event_time_us(torch, lambda: prob.eta_gradient(grad, ll), 10)
+        gb = torch.empty(1, dtype=torch.float64, device="cuda:0")
+        prob.beta_gradient(gb, None, ll)
+        torch.cuda.synchronize()
+        us_b = event_time_us(torch, lambda: prob.beta_gradient(gb, None, ll), 10)
+        # X' (dl/deta) of the dense column: status, eta, e, d per subject
+        # (18 bytes) and the column's index and value per non-zero (12)
+        algo_b = 30.0 * n
         res[str(n)] = {"us": round(us, 1), "algo_gbs": round(30.0 * n / (us * 1e3), 1),
-                       "frac_of_hbm_peak": round(30.0 * n / (us * 1e3) / HBM_PEAK_GBS, 4)}
+                       "frac_of_hbm_peak": round(30.0 * n / (us * 1e3) / HBM_PEAK_GBS, 4),
+                       "beta_gradient_us": round(us_b, 1),
+                       "beta_gradient_algo_gbs": round(algo_b / (us_b * 1e3), 1),
+                       "beta_gradient_frac_of_hbm_peak": round(algo_b / (us_b * 1e3) /
+                                                               HBM_PEAK_GBS, 4)}
         del prob, grad
         torch.cuda.empty_cache()
     return res
 
 
+def subset_problem(ss, d, keep, model):
+    """The data set of the subjects with keep != 0 (CSC columns restricted
+    to them, rows renumbered), prepared as a problem of its own."""
+    import numpy as np
+    keep = np.asarray(keep) != 0
+    idx = np.nonzero(keep)[0]
+    new = np.full(keep.size, -1, dtype=np.int64)
+    new[idx] = np.arange(idx.size)
+    rows = np.asarray(d["rows"], dtype=np.int64)
+    m = keep[rows]
+    csum = np.concatenate([[0], np.cumsum(m, dtype=np.int64)])
+    cp = csum[np.asarray(d["col_ptr"], dtype=np.int64)]
+    return ss.Problem(model, d["y"][idx], d["status"][idx], cp, new[rows[m]].astype(np.int32),
+                      None, "cuda:0")
+
+
 def cross_validation(torch, ss, gen):
     """Sec. 3.3 design at its smallest size: 10 x 10 cross-validation of the
-    l1 Cox model (gamma = sqrt 2) at N = 1e5, P = 1000; one sweep of all 100
-    replicates in one launch, and one replicate-sized problem (N = 9e4, the
-    training set of a 10-fold replicate) swept alone."""
+    l1 model (gamma = sqrt 2) at N = 1e5, P = 1000, Cox and Fine-Gray; one
+    sweep of all 100 replicates in one launch, next to the paper's way
+    (Sec. 2.8): every replicate a problem of its own (its training subjects),
+    their single-problem sweeps spread over s = 1, 2, 4, 8 streams."""
     n, p, reps = 100_000, 1000, 100
     gamma = math.sqrt(2.0)
-    d = gen.cox_data(0, n, p, 0.05)
     train = gen.cv_folds(0, n, 10, 10)
-    prob = ss.Problem("cox", d["y"], d["status"], d["col_ptr"], d["rows"], None, "cuda:0")
-    cvp = ss.CrossValidation(prob, train)
-    cvp.sweep("l1", gamma)
-    torch.cuda.synchronize()
-    us_cv = event_time_us(torch, lambda: cvp.sweep("l1", gamma), 5)
-    one = gen.cox_data(1, 90_000, p, 0.05)
-    p1 = ss.Problem("cox", one["y"], one["status"], one["col_ptr"], one["rows"], None,
-                    "cuda:0")
-    p1.sweep("l1", gamma)
-    torch.cuda.synchronize()
-    us_one = event_time_us(torch, lambda: p1.sweep("l1", gamma), 5)
-    return {"workload": "10-fold x 10 cross-validation, l1 Cox, N=1e5, P=1000, 0.05 density",
-            "replicates": reps, "sweep_ms_all_replicates": round(us_cv / 1e3, 3),
-            "replicate_coords_per_s": round(reps * p / (us_cv * 1e-6), 1),
-            "one_replicate_sweep_ms": round(us_one / 1e3, 3),
-            "one_at_a_time_ms_100_replicates": round(100 * us_one / 1e3, 2),
-            "speedup_vs_one_at_a_time": round(100 * us_one / us_cv, 2)}
+    out = {"workload": "10-fold x 10 cross-validation, l1, N=1e5, P=1000, 0.05 density",
+           "replicates": reps}
+    for model in ("cox", "fg"):
+        d = gen.cox_data(0, n, p, 0.05) if model == "cox" else gen.fg_data(0, n, p, 0.05)
+        prob = ss.Problem(model, d["y"], d["status"], d["col_ptr"], d["rows"], None, "cuda:0")
+        cvp = ss.CrossValidation(prob, train)
+        cvp.sweep("l1", gamma)
+        torch.cuda.synchronize()
+        us_cv = event_time_us(torch, lambda: cvp.sweep("l1", gamma), 3)
+        err = cvp.workspace_error()
+        del cvp, prob
+        torch.cuda.empty_cache()
+        # the multi-stream baseline
+        probs = [subset_problem(ss, d, train[r], model) for r in range(reps)]
+        for pr in probs:
+            pr.sweep("l1", gamma)
+        torch.cuda.synchronize()
+        streams_ms = {}
+        for ns in (1, 2, 4, 8):
+            streams = [torch.cuda.Stream() for _ in range(ns)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for r, pr in enumerate(probs):
+                with torch.cuda.stream(streams[r % ns]):
+                    pr.sweep("l1", gamma)
+            torch.cuda.synchronize()
+            streams_ms[str(ns)] = round((time.perf_counter() - t0) * 1e3, 3)
+        # the same with one launch per coordinate (the sweep as the paper's
+        # CPU-driven loop launches it; launches of different streams can
+        # overlap, the cooperative persistent sweep above cannot)
+        launch_ms = {}
+        os.environ["SURVSCAN_SWEEP"] = "launch"
+        try:
+            for pr in probs:
+                pr.sweep("l1", gamma)
+            for ns in (1, 2, 4, 8):
+                streams = [torch.cuda.Stream() for _ in range(ns)]
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for r, pr in enumerate(probs):
+                    with torch.cuda.stream(streams[r % ns]):
+                        pr.sweep("l1", gamma)
+                torch.cuda.synchronize()
+                launch_ms[str(ns)] = round((time.perf_counter() - t0) * 1e3, 3)
+        finally:
+            del os.environ["SURVSCAN_SWEEP"]
+        err += sum(pr.workspace_error() for pr in probs)
+        best = min(min(streams_ms.values()), min(launch_ms.values()))
+        out[model] = {"sweep_ms_all_replicates_one_launch": round(us_cv / 1e3, 3),
+                      "replicate_coords_per_s": round(reps * p / (us_cv * 1e-6), 1),
+                      "multi_stream_sweep_ms_by_streams": streams_ms,
+                      "multi_stream_per_coordinate_launches_ms_by_streams": launch_ms,
+                      "speedup_one_launch_vs_best_multi_stream": round(best / (us_cv / 1e3), 2),
+                      "wait_errors": err}
+        del probs
+        torch.cuda.empty_cache()
+    return out
 
 
 def fit_to_convergence(torch, ss, cox, fg, tol=1e-15):

@@ -334,6 +334,28 @@ int32_t ss_eta_gradient(int32_t model, int64_t n, const int32_t *inv_perm,
 int32_t ss_gather_u8(int64_t n, const int32_t *perm, const uint8_t *src,
                      uint8_t *dst, void *stream);
 
+/* ss_beta_gradient: the full gradient of l in beta, X' (dl/deta) (Sec. 2.9:
+ * the gradient a proximal-gradient method takes is X' times the vector
+ * ss_eta_gradient computes), formed from the gradient in eta in SORTED
+ * order and the sorted-position design of ss_prepare (col_ptr,
+ * rows_sorted, vals_sorted or NULL for 0/1), so no permutation of the
+ * subjects is involved: grad_beta[j] = sum over column j's non-zeros of
+ * x * (dl/deta at that position), one workgroup per column, fixed-order sums
+ * (deterministic).  Also l in *loglik, and, if grad_eta is not NULL, dl/deta
+ * in subject order as ss_eta_gradient writes it (then inv_perm is needed;
+ * otherwise it may be NULL).  Other arguments, the workspace
+ * (ss_eta_gradient_workspace_bytes(n)) and the errors as ss_eta_gradient,
+ * plus SS_EINVAL for p < 1 or a null column array. */
+int32_t ss_beta_gradient(int32_t model, int64_t n, int64_t p,
+                         const int32_t *inv_perm, const int8_t *status_sorted,
+                         const double *eta, const double *e,
+                         const uint8_t *d8, const int32_t *d32,
+                         const double *w_comp, const double *g_end,
+                         const int64_t *col_ptr, const int32_t *rows_sorted,
+                         const double *vals_sorted, double *grad_beta,
+                         double *grad_eta, double *loglik, void *ws,
+                         size_t ws_bytes, void *stream);
+
 /* ---------------------------------------------------------------------
  * Cross-validation replicates in one launch (Sec. 2.8; the single larger
  * kernel for many k-fold repetitions proposed in the paper's concluding

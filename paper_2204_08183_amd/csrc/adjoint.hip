@@ -175,6 +175,30 @@ __global__ __launch_bounds__(256) void k_adj_to_subjects(int64_t n, const int32_
         grad[i] = grad_s[inv_perm[i]];
 }
 
+// X' g for the columns of the sorted-position CSC design: one workgroup per
+// column, its non-zeros strided over the threads, a fixed-order block sum
+// (deterministic).  g is the gradient in sorted order, so no permutation is
+// involved.
+__global__ __launch_bounds__(256) void k_adj_xt(int64_t p, const int64_t *col_ptr,
+                                                const int32_t *rows_sorted,
+                                                const double *vals_sorted, const double *grad_s,
+                                                double *out)
+{
+    __shared__ double s_red[4];
+    for (int64_t j = blockIdx.x; j < p; j += gridDim.x) {
+        const int64_t lo = col_ptr[j], hi = col_ptr[j + 1];
+        double v = 0.0;
+        for (int64_t q = lo + threadIdx.x; q < hi; q += 256) {
+            const double g = grad_s[rows_sorted[q]];
+            v += vals_sorted ? vals_sorted[q] * g : g;
+        }
+        double t[1] = {v};
+        block_sum<1, 256>(t, s_red);
+        if (threadIdx.x == 0) out[j] = t[0];
+        __syncthreads();
+    }
+}
+
 struct AdjWs {
     double *a, *b, *q, *q2, *lpart;
     void *sums;
@@ -221,14 +245,13 @@ int32_t launch_gather_u8(int64_t n, const int32_t *perm, const uint8_t *src, uin
 
 size_t adjoint_ws_bytes(int64_t n) { return adj_layout(n, nullptr, nullptr); }
 
-int32_t launch_eta_gradient(int32_t model, int64_t n, const int32_t *inv_perm,
-                            const int8_t *status_s, const double *eta, const double *e,
-                            const uint8_t *d8, const int32_t *d32, const double *w_comp,
-                            const double *g_end, double *grad, double *loglik, void *ws,
-                            hipStream_t s)
+// The gradient in eta in sorted order into w.a (and l into *loglik).
+static int32_t eta_gradient_sorted(int32_t model, int64_t n, const int8_t *status_s,
+                                   const double *eta, const double *e, const uint8_t *d8,
+                                   const int32_t *d32, const double *w_comp,
+                                   const double *g_end, double *loglik, const AdjWs &w,
+                                   hipStream_t s)
 {
-    AdjWs w;
-    adj_layout(n, ws, &w);
     const bool fg = model == SS_FINE_GRAY;
     const int grid = grid_of(n);
     const unsigned tiles = (unsigned)ceil_div(n, ST);
@@ -264,8 +287,47 @@ int32_t launch_eta_gradient(int32_t model, int64_t n, const int32_t *inv_perm,
                            status_s, e, w_comp, w.b, w.lpart, (int64_t)tiles, w.a, loglik);
     }
     SS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_adj_to_subjects, dim3(grid), dim3(256), 0, s, n, inv_perm, w.a, grad);
+    return SS_OK;
+}
+
+int32_t launch_eta_gradient(int32_t model, int64_t n, const int32_t *inv_perm,
+                            const int8_t *status_s, const double *eta, const double *e,
+                            const uint8_t *d8, const int32_t *d32, const double *w_comp,
+                            const double *g_end, double *grad, double *loglik, void *ws,
+                            hipStream_t s)
+{
+    AdjWs w;
+    adj_layout(n, ws, &w);
+    const int32_t rc = eta_gradient_sorted(model, n, status_s, eta, e, d8, d32, w_comp, g_end,
+                                           loglik, w, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_adj_to_subjects, dim3(grid_of(n)), dim3(256), 0, s, n, inv_perm, w.a,
+                       grad);
     SS_LAUNCH_CHECK();
+    return SS_OK;
+}
+
+int32_t launch_beta_gradient(int32_t model, int64_t n, int64_t p, const int32_t *inv_perm,
+                             const int8_t *status_s, const double *eta, const double *e,
+                             const uint8_t *d8, const int32_t *d32, const double *w_comp,
+                             const double *g_end, const int64_t *col_ptr,
+                             const int32_t *rows_sorted, const double *vals_sorted,
+                             double *grad_beta, double *grad_eta, double *loglik, void *ws,
+                             hipStream_t s)
+{
+    AdjWs w;
+    adj_layout(n, ws, &w);
+    int32_t rc = eta_gradient_sorted(model, n, status_s, eta, e, d8, d32, w_comp, g_end, loglik,
+                                     w, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_adj_xt, dim3((unsigned)std::min<int64_t>(p, 65535)), dim3(256), 0, s, p,
+                       col_ptr, rows_sorted, vals_sorted, w.a, grad_beta);
+    SS_LAUNCH_CHECK();
+    if (grad_eta) {
+        hipLaunchKernelGGL(k_adj_to_subjects, dim3(grid_of(n)), dim3(256), 0, s, n, inv_perm,
+                           w.a, grad_eta);
+        SS_LAUNCH_CHECK();
+    }
     return SS_OK;
 }
 

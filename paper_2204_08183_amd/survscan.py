@@ -94,6 +94,8 @@ SIGNATURES = {
                             _vp, _vp, _sz, _vp]),
     "ss_cv_select": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp]),
     "ss_gather_u8": (_i32, [_i64, _vp, _vp, _vp, _vp]),
+    "ss_beta_gradient": (_i32, [_i32, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_noalloc_scratch_bytes": (_sz, []),
     "ss_grad_hess_noalloc": (_i32, [_i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
                                     _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -341,6 +343,30 @@ class Problem:
                                  self.adj_ws.ptr, self.adj_ws.nbytes, _stream(self.device))
         check(rc, "ss_eta_gradient")
         return grad, loglik
+
+    def beta_gradient(self, grad_beta=None, grad_eta=None, loglik=None):
+        """X' (dl/deta) at the current eta as a device tensor [p] (Sec. 2.9),
+        with l [1]; with a grad_eta tensor [n] also dl/deta in subject order.
+        Returns (grad_beta, loglik)."""
+        lib = load()
+        if getattr(self, "adj_ws", None) is None:
+            self.adj_ws = Workspace(lib.ss_eta_gradient_workspace_bytes(self.n), self.device)
+            self.status_sorted = torch.empty(self.n, dtype=torch.int8, device=self.device)
+            check(lib.ss_gather_u8(self.n, _p(self.perm), _p(self.status),
+                                   _p(self.status_sorted), _stream(self.device)),
+                  "ss_gather_u8")
+        grad_beta = torch.empty(self.p, dtype=torch.float64, device=self.device) \
+            if grad_beta is None else grad_beta
+        loglik = torch.empty(1, dtype=torch.float64, device=self.device) \
+            if loglik is None else loglik
+        rc = lib.ss_beta_gradient(self.model, self.n, self.p, _p(self.inv_perm),
+                                  _p(self.status_sorted), _p(self.eta), _p(self.e), _p(self.d8),
+                                  _p(self.d32), _p(self.w_comp), _p(self.g_end),
+                                  _p(self.col_ptr), _p(self.rows_sorted), _p(self.vals_sorted),
+                                  _p(grad_beta), _p(grad_eta), _p(loglik), self.adj_ws.ptr,
+                                  self.adj_ws.nbytes, _stream(self.device))
+        check(rc, "ss_beta_gradient")
+        return grad_beta, loglik
 
     def loglik(self, beta=None, out=None):
         beta = self.beta if beta is None else \

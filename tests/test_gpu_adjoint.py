@@ -143,3 +143,66 @@ def test_loglik_eta_autograd(model):
     eta = torch.tensor(c["eta"], dtype=torch.float64, device=DEV, requires_grad=True)
     assert torch.autograd.gradcheck(lambda t: ss.loglik_eta(small, t), (eta,), eps=1e-6,
                                     atol=1e-7, rtol=1e-6)
+
+
+# ---------------------------------------------------------------- X' (dl/deta)
+BETA_CASES = CASES + [("cox", 1, 2, 40, 0, False), ("fg", 2, 2, 41, 0, True),
+                      ("cox", 200_003, 6, 42, 900, True), ("fg", 131_073, 5, 43, 0, False)]
+
+
+@pytest.mark.parametrize("model,n,p,seed,ties,valued", BETA_CASES)
+def test_beta_gradient_matches_oracle(model, n, p, seed, ties, valued):
+    """ss_beta_gradient: X' times the oracle's gradient in eta, column by
+    column, within 1e-10 of sum |x| (|dl/deta| + 1); l as the oracle's;
+    the optional subject-order gradient equals ss_eta_gradient's; and each
+    entry equals g' of the fused coordinate kernel (a different algorithm)."""
+    c = make_case(model, n, p, seed, ties, 0.1, valued)
+    prob = gpu_problem(model, c)
+    grad_eta = torch.empty(n, dtype=torch.float64, device=DEV)
+    gb, ll = prob.beta_gradient(grad_eta=grad_eta)
+    got = gb.cpu().numpy()
+    want_eta = oadj.eta_gradient_scan(model, c["y"], c["status"], c["eta"])
+    want_l = oadj.loglik_eta(model, c["y"], c["status"], c["eta"])
+    ev = oprep.event_indicator(model, c["status"]).astype(np.float64)
+    l_scale = float(np.sum(np.abs(c["eta"] * ev))) + abs(want_l) + 1.0
+    assert abs(float(ll.cpu()[0]) - want_l) <= TOL * l_scale
+    for j in range(p):
+        x = xcol(c, j)
+        scale = float(np.sum(np.abs(x) * (np.abs(want_eta) + 1.0)))
+        assert abs(got[j] - float(x @ want_eta)) <= TOL * scale, (model, n, j)
+        g1 = float(prob.grad_hess(j).cpu()[0])
+        assert abs(got[j] - g1) <= TOL * scale, (model, n, j, got[j], g1)
+    ge, _ = prob.eta_gradient()
+    np.testing.assert_array_equal(grad_eta.cpu().numpy(), ge.cpu().numpy())
+    # without the subject-order output the sums are the same (deterministic)
+    gb2, _ = prob.beta_gradient()
+    np.testing.assert_array_equal(gb2.cpu().numpy(), got)
+    assert prob.workspace_error() == 0
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+def test_beta_gradient_paper_scale(model):
+    """N = 1e6, P = 1000 (the Sec. 3.2 design) at the generating
+    coefficients: every entry of X' (dl/deta) against g' of ss_grad_hess
+    (property at any size), sampled columns against the oracle's scan."""
+    import gen
+    d = gen.cox_data(0, 1_000_000, 1000, 0.05) if model == "cox" else \
+        gen.fg_data(0, 1_000_000, 1000, 0.05)
+    eta = gen.linear_predictor(d["n"], d["col_ptr"], d["rows"], None, d["beta_true"])
+    prob = ss.Problem(model, d["y"], d["status"], d["col_ptr"], d["rows"], None, DEV)
+    prob.set_eta(eta)
+    gb, _ = prob.beta_gradient()
+    got = gb.cpu().numpy()
+    g = torch.empty((1000, 3), dtype=torch.float64, device=DEV)
+    for j in range(1000):
+        prob.grad_hess(j, out=g[j])
+    g1 = g[:, 0].cpu().numpy()
+    cnt = np.diff(d["col_ptr"]).astype(np.float64)
+    # |x_j' g| <= sum |x_j| (|grad| + 1) <= 2 * (number of events + nnz_j)
+    scale = 2.0 * (cnt + d["n"])
+    assert np.all(np.abs(got - g1) <= TOL * scale)
+    pr = oscan.Prepared(model, d["y"], d["status"])
+    for j in (0, 500, 999):
+        x = gen.dense_column(d["n"], d["col_ptr"], d["rows"], None, j)
+        want = pr.coordinate(eta, x)
+        assert abs(got[j] - want["g1"]) <= TOL * want["scale_g1"], j
