@@ -338,23 +338,28 @@ int32_t ss_gather_u8(int64_t n, const int32_t *perm, const uint8_t *src,
  * the gradient a proximal-gradient method takes is X' times the vector
  * ss_eta_gradient computes), formed from the gradient in eta in SORTED
  * order and the sorted-position design of ss_prepare (col_ptr,
- * rows_sorted, vals_sorted or NULL for 0/1), so no permutation of the
- * subjects is involved: grad_beta[j] = sum over column j's non-zeros of
- * x * (dl/deta at that position), one workgroup per column, fixed-order sums
- * (deterministic).  Also l in *loglik, and, if grad_eta is not NULL, dl/deta
- * in subject order as ss_eta_gradient writes it (then inv_perm is needed;
- * otherwise it may be NULL).  Other arguments, the workspace
- * (ss_eta_gradient_workspace_bytes(n)) and the errors as ss_eta_gradient,
- * plus SS_EINVAL for p < 1 or a null column array. */
+ * rows_sorted, vals_sorted or NULL for 0/1, chunk_ptr), so no permutation
+ * of the subjects is involved: grad_beta[j] = sum over column j's
+ * non-zeros of x * (dl/deta at that position).  The positions are cut into
+ * spans of whole chunks; each (column, span) piece is summed by one
+ * wavefront, then each column's pieces in span order: every sum in a fixed
+ * order (deterministic).  Also l in *loglik, and, if grad_eta is not NULL,
+ * dl/deta in subject order as ss_eta_gradient writes it (then inv_perm is
+ * needed; otherwise it may be NULL).  The workspace is
+ * ss_beta_gradient_workspace_bytes(n, p) bytes (at most
+ * ss_eta_gradient_workspace_bytes(n) plus 16 (n + p) + 256); other
+ * arguments and errors as ss_eta_gradient, plus SS_EINVAL for p < 1 or a
+ * null column array. */
+size_t ss_beta_gradient_workspace_bytes(int64_t n, int64_t p);
 int32_t ss_beta_gradient(int32_t model, int64_t n, int64_t p,
                          const int32_t *inv_perm, const int8_t *status_sorted,
                          const double *eta, const double *e,
                          const uint8_t *d8, const int32_t *d32,
                          const double *w_comp, const double *g_end,
                          const int64_t *col_ptr, const int32_t *rows_sorted,
-                         const double *vals_sorted, double *grad_beta,
-                         double *grad_eta, double *loglik, void *ws,
-                         size_t ws_bytes, void *stream);
+                         const double *vals_sorted, const int32_t *chunk_ptr,
+                         double *grad_beta, double *grad_eta, double *loglik,
+                         void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------
  * Cross-validation replicates in one launch (Sec. 2.8; the single larger

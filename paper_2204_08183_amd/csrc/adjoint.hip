@@ -175,28 +175,75 @@ __global__ __launch_bounds__(256) void k_adj_to_subjects(int64_t n, const int32_
         grad[i] = grad_s[inv_perm[i]];
 }
 
-// X' g for the columns of the sorted-position CSC design: one workgroup per
-// column, its non-zeros strided over the threads, a fixed-order block sum
-// (deterministic).  g is the gradient in sorted order, so no permutation is
-// involved.
-__global__ __launch_bounds__(256) void k_adj_xt(int64_t p, const int64_t *col_ptr,
-                                                const int32_t *rows_sorted,
-                                                const double *vals_sorted, const double *grad_s,
-                                                double *out)
+// X' g over the sorted-position CSC design, cut along the positions into
+// spans of kspan chunks (kspan * SS_CHUNK positions): one wave sums column
+// j's non-zeros inside span c, found through the chunk index, into
+// part[j * nspan + c].  A wave's unit is (span, column group); the waves of
+// one span sit next to each other in launch order, so the stretch of g a
+// span gathers from stays in L2 while its columns are summed.  Every sum is
+// in a fixed order (four interleaved accumulators, then the wave), so the
+// result is deterministic.
+constexpr int kXtWaves = 4;
+
+__global__ __launch_bounds__(256) void k_xt_span(int64_t p, int64_t nspan, int64_t kspan,
+                                                 int64_t nchunk, int64_t groups,
+                                                 const int64_t *col_ptr,
+                                                 const int32_t *chunk_ptr,
+                                                 const int32_t *rows_sorted,
+                                                 const double *vals_sorted, const double *g,
+                                                 double *part)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t unit = (int64_t)blockIdx.x * kXtWaves + (threadIdx.x >> 6);
+    if (unit >= nspan * groups) return;  // the whole wave
+    const int64_t c = unit / groups;
+    const int64_t t0 = c * kspan, t1 = min(t0 + kspan, nchunk);
+    for (int64_t j = unit - c * groups; j < p; j += groups) {
+        const int32_t *cp = chunk_ptr + j * (nchunk + 1);
+        const int64_t base = col_ptr[j];
+        const int64_t hi = base + cp[t1];
+        int64_t q = base + cp[t0] + lane;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (vals_sorted) {
+            for (; q + 3 * kWave < hi; q += 4 * kWave) {
+                a0 += vals_sorted[q] * g[rows_sorted[q]];
+                a1 += vals_sorted[q + kWave] * g[rows_sorted[q + kWave]];
+                a2 += vals_sorted[q + 2 * kWave] * g[rows_sorted[q + 2 * kWave]];
+                a3 += vals_sorted[q + 3 * kWave] * g[rows_sorted[q + 3 * kWave]];
+            }
+            for (; q < hi; q += kWave) a0 += vals_sorted[q] * g[rows_sorted[q]];
+        } else {
+            for (; q + 3 * kWave < hi; q += 4 * kWave) {
+                a0 += g[rows_sorted[q]];
+                a1 += g[rows_sorted[q + kWave]];
+                a2 += g[rows_sorted[q + 2 * kWave]];
+                a3 += g[rows_sorted[q + 3 * kWave]];
+            }
+            for (; q < hi; q += kWave) a0 += g[rows_sorted[q]];
+        }
+        const double v = dpp_wave_sum((a0 + a1) + (a2 + a3));
+        if (lane == 0) part[j * nspan + c] = v;
+    }
+}
+
+// grad_beta[j] = the sum of column j's span partials, one workgroup per
+// column: four interleaved accumulators per thread, then the workgroup's
+// fixed-order sum.
+__global__ __launch_bounds__(256) void k_xt_cols(int64_t nspan, const double *part, double *out)
 {
     __shared__ double s_red[4];
-    for (int64_t j = blockIdx.x; j < p; j += gridDim.x) {
-        const int64_t lo = col_ptr[j], hi = col_ptr[j + 1];
-        double v = 0.0;
-        for (int64_t q = lo + threadIdx.x; q < hi; q += 256) {
-            const double g = grad_s[rows_sorted[q]];
-            v += vals_sorted ? vals_sorted[q] * g : g;
-        }
-        double t[1] = {v};
-        block_sum<1, 256>(t, s_red);
-        if (threadIdx.x == 0) out[j] = t[0];
-        __syncthreads();
+    const double *pj = part + (int64_t)blockIdx.x * nspan;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t c = threadIdx.x;
+    for (; c + 768 < nspan; c += 1024) {
+        a0 += pj[c];
+        a1 += pj[c + 256];
+        a2 += pj[c + 512];
+        a3 += pj[c + 768];
     }
+    for (; c < nspan; c += 256) a0 += pj[c];
+    const double t = block_total((a0 + a1) + (a2 + a3), s_red);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 struct AdjWs {
@@ -307,21 +354,47 @@ int32_t launch_eta_gradient(int32_t model, int64_t n, const int32_t *inv_perm,
     return SS_OK;
 }
 
+// Span length (in chunks) of the X' pass: 8 chunks (8192 positions), longer
+// where p * spans would pass 2 (n + p) partials (designs much wider than
+// long), which bounds the workspace.
+int64_t xt_span_chunks(int64_t n, int64_t p)
+{
+    const int64_t nchunk = ceil_div(n, (int64_t)SS_CHUNK);
+    int64_t k = 8;
+    while (k < nchunk && p * ceil_div(nchunk, k) > 2 * (n + p)) k *= 2;
+    return k;
+}
+
+size_t beta_ws_bytes(int64_t n, int64_t p)
+{
+    const int64_t nspan = ceil_div(ceil_div(n, (int64_t)SS_CHUNK), xt_span_chunks(n, p));
+    return adjoint_ws_bytes(n) + align_up(8 * (size_t)p * (size_t)nspan, 256);
+}
+
 int32_t launch_beta_gradient(int32_t model, int64_t n, int64_t p, const int32_t *inv_perm,
                              const int8_t *status_s, const double *eta, const double *e,
                              const uint8_t *d8, const int32_t *d32, const double *w_comp,
                              const double *g_end, const int64_t *col_ptr,
                              const int32_t *rows_sorted, const double *vals_sorted,
-                             double *grad_beta, double *grad_eta, double *loglik, void *ws,
-                             hipStream_t s)
+                             const int32_t *chunk_ptr, double *grad_beta, double *grad_eta,
+                             double *loglik, void *ws, hipStream_t s)
 {
     AdjWs w;
     adj_layout(n, ws, &w);
     int32_t rc = eta_gradient_sorted(model, n, status_s, eta, e, d8, d32, w_comp, g_end, loglik,
                                      w, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_adj_xt, dim3((unsigned)std::min<int64_t>(p, 65535)), dim3(256), 0, s, p,
-                       col_ptr, rows_sorted, vals_sorted, w.a, grad_beta);
+    const int64_t nchunk = ceil_div(n, (int64_t)SS_CHUNK);
+    const int64_t kspan = xt_span_chunks(n, p);
+    const int64_t nspan = ceil_div(nchunk, kspan);
+    // about 16K waves when the design allows: column groups per span
+    const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(p, ceil_div(16384, nspan)));
+    double *part = reinterpret_cast<double *>(static_cast<char *>(ws) + adjoint_ws_bytes(n));
+    hipLaunchKernelGGL(k_xt_span, dim3((unsigned)ceil_div(nspan * groups, kXtWaves)), dim3(256),
+                       0, s, p, nspan, kspan, nchunk, groups, col_ptr, chunk_ptr, rows_sorted,
+                       vals_sorted, w.a, part);
+    SS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_xt_cols, dim3((unsigned)p), dim3(256), 0, s, nspan, part, grad_beta);
     SS_LAUNCH_CHECK();
     if (grad_eta) {
         hipLaunchKernelGGL(k_adj_to_subjects, dim3(grid_of(n)), dim3(256), 0, s, n, inv_perm,

@@ -573,24 +573,30 @@ int32_t ss_eta_gradient(int32_t model, int64_t n, const int32_t *inv_perm,
                                loglik, ws, (hipStream_t)stream);
 }
 
+size_t ss_beta_gradient_workspace_bytes(int64_t n, int64_t p)
+{
+    if (bad_size(n, p)) return 0;
+    return beta_ws_bytes(n, p);
+}
+
 int32_t ss_beta_gradient(int32_t model, int64_t n, int64_t p, const int32_t *inv_perm,
                          const int8_t *status_sorted, const double *eta, const double *e,
                          const uint8_t *d8, const int32_t *d32, const double *w_comp,
                          const double *g_end, const int64_t *col_ptr,
                          const int32_t *rows_sorted, const double *vals_sorted,
-                         double *grad_beta, double *grad_eta, double *loglik, void *ws,
-                         size_t ws_bytes, void *stream)
+                         const int32_t *chunk_ptr, double *grad_beta, double *grad_eta,
+                         double *loglik, void *ws, size_t ws_bytes, void *stream)
 {
     if (model != SS_COX && model != SS_FINE_GRAY) return SS_EUNSUPPORTED;
     if (bad_size(n, p)) return SS_EINVAL;
     if (!status_sorted || !eta || !e || !d8 || !d32 || !grad_beta || !loglik) return SS_EINVAL;
-    if (!col_ptr || !rows_sorted) return SS_EINVAL;
+    if (!col_ptr || !rows_sorted || !chunk_ptr) return SS_EINVAL;
     if (grad_eta && !inv_perm) return SS_EINVAL;
     if (model == SS_FINE_GRAY && (!w_comp || !g_end)) return SS_EINVAL;
-    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < adjoint_ws_bytes(n)) return SS_EWORKSPACE;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < beta_ws_bytes(n, p)) return SS_EWORKSPACE;
     return launch_beta_gradient(model, n, p, inv_perm, status_sorted, eta, e, d8, d32, w_comp,
-                                g_end, col_ptr, rows_sorted, vals_sorted, grad_beta, grad_eta,
-                                loglik, ws, (hipStream_t)stream);
+                                g_end, col_ptr, rows_sorted, vals_sorted, chunk_ptr, grad_beta,
+                                grad_eta, loglik, ws, (hipStream_t)stream);
 }
 
 int64_t ss_cv_stride(int64_t n)

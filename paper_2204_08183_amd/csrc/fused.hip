@@ -842,9 +842,37 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     // across the look-back (registers bound how many tiles a CU holds)
     uint32_t xb = xbits;
     asm volatile("" : "+v"(xb));
-    if (MODEL == SS_FINE_GRAY) {
+    if (MODEL == SS_FINE_GRAY && !CARRY) {
 #pragma unroll
         for (int i = 0; i < IPT; ++i) asm volatile("" : "+v"(wv[i]));
+    }
+    if (MODEL == SS_FINE_GRAY && CARRY) {
+        // w again (an L2 or last-level cache hit: the tile read it moments
+        // ago) rather than held across the look-back: 28 fewer VGPRs at 16
+        // positions per thread, three workgroups per CU instead of two
+        // (measured 1721 -> 1649 us per coordinate at N = 2^27; without the
+        // carried sums, held w measured faster, 1525 against 1600 us)
+        const double *wsrc = a.w_comp;
+        asm volatile("" : "+s"(wsrc));  // a new load, not the staged values
+        if (cnt == TILE) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const double2 *wp = reinterpret_cast<const double2 *>(
+                    wsrc + t0 + (int64_t)q * BLOCK * C + (int64_t)tid * C);
+#pragma unroll
+                for (int h = 0; h < C / 2; ++h) {
+                    const double2 v = wp[h];
+                    wv[q * C + 2 * h] = v.x;
+                    wv[q * C + 2 * h + 1] = v.y;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int64_t k = t0 + tile_pos<BLOCK, IPT>(i, tid);
+                wv[i] = k < a.n ? wsrc[k] : 0.0;
+            }
+        }
     }
     // the tile's prefix: added to the FP64 in-tile prefixes now, or (F32S)
     // to each run end's FP32 in-tile prefix in FP64

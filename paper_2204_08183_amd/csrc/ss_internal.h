@@ -307,6 +307,7 @@ size_t scan_sums_bytes(int64_t m);
 // finishes the scan itself.
 int32_t scan_carries_f64(const double *in, int64_t m, bool rev, void *sums, hipStream_t s);
 size_t adjoint_ws_bytes(int64_t n);
+size_t beta_ws_bytes(int64_t n, int64_t p);
 int32_t launch_gather_u8(int64_t n, const int32_t *perm, const uint8_t *src, uint8_t *dst,
                          hipStream_t s);
 int32_t launch_beta_gradient(int32_t model, int64_t n, int64_t p, const int32_t *inv_perm,
@@ -314,8 +315,8 @@ int32_t launch_beta_gradient(int32_t model, int64_t n, int64_t p, const int32_t 
                              const uint8_t *d8, const int32_t *d32, const double *w_comp,
                              const double *g_end, const int64_t *col_ptr,
                              const int32_t *rows_sorted, const double *vals_sorted,
-                             double *grad_beta, double *grad_eta, double *loglik, void *ws,
-                             hipStream_t s);
+                             const int32_t *chunk_ptr, double *grad_beta, double *grad_eta,
+                             double *loglik, void *ws, hipStream_t s);
 int32_t launch_eta_gradient(int32_t model, int64_t n, const int32_t *inv_perm,
                             const int8_t *status_s,
                             const double *eta, const double *e, const uint8_t *d8,

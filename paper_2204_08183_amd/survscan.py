@@ -94,8 +94,9 @@ SIGNATURES = {
                             _vp, _vp, _sz, _vp]),
     "ss_cv_select": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp]),
     "ss_gather_u8": (_i32, [_i64, _vp, _vp, _vp, _vp]),
+    "ss_beta_gradient_workspace_bytes": (_sz, [_i64, _i64]),
     "ss_beta_gradient": (_i32, [_i32, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ss_noalloc_scratch_bytes": (_sz, []),
     "ss_grad_hess_noalloc": (_i32, [_i32, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
                                     _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -323,16 +324,23 @@ class Problem:
         check(rc, "ss_grad_hess_f32")
         return out
 
-    def eta_gradient(self, grad=None, loglik=None):
-        """dl/deta for every subject (original order) and l at the current
-        eta, as device tensors (grad [n], loglik [1])."""
+    def _adjoint_setup(self, ws_bytes):
+        """The status in sorted order (once) and an adjoint workspace of at
+        least ws_bytes."""
         lib = load()
-        if getattr(self, "adj_ws", None) is None:
-            self.adj_ws = Workspace(lib.ss_eta_gradient_workspace_bytes(self.n), self.device)
+        if getattr(self, "status_sorted", None) is None:
             self.status_sorted = torch.empty(self.n, dtype=torch.int8, device=self.device)
             check(lib.ss_gather_u8(self.n, _p(self.perm), _p(self.status),
                                    _p(self.status_sorted), _stream(self.device)),
                   "ss_gather_u8")
+        if getattr(self, "adj_ws", None) is None or self.adj_ws.nbytes < ws_bytes:
+            self.adj_ws = Workspace(ws_bytes, self.device)
+
+    def eta_gradient(self, grad=None, loglik=None):
+        """dl/deta for every subject (original order) and l at the current
+        eta, as device tensors (grad [n], loglik [1])."""
+        lib = load()
+        self._adjoint_setup(lib.ss_eta_gradient_workspace_bytes(self.n))
         grad = torch.empty(self.n, dtype=torch.float64, device=self.device) \
             if grad is None else grad
         loglik = torch.empty(1, dtype=torch.float64, device=self.device) \
@@ -349,12 +357,7 @@ class Problem:
         with l [1]; with a grad_eta tensor [n] also dl/deta in subject order.
         Returns (grad_beta, loglik)."""
         lib = load()
-        if getattr(self, "adj_ws", None) is None:
-            self.adj_ws = Workspace(lib.ss_eta_gradient_workspace_bytes(self.n), self.device)
-            self.status_sorted = torch.empty(self.n, dtype=torch.int8, device=self.device)
-            check(lib.ss_gather_u8(self.n, _p(self.perm), _p(self.status),
-                                   _p(self.status_sorted), _stream(self.device)),
-                  "ss_gather_u8")
+        self._adjoint_setup(lib.ss_beta_gradient_workspace_bytes(self.n, self.p))
         grad_beta = torch.empty(self.p, dtype=torch.float64, device=self.device) \
             if grad_beta is None else grad_beta
         loglik = torch.empty(1, dtype=torch.float64, device=self.device) \
@@ -363,8 +366,8 @@ class Problem:
                                   _p(self.status_sorted), _p(self.eta), _p(self.e), _p(self.d8),
                                   _p(self.d32), _p(self.w_comp), _p(self.g_end),
                                   _p(self.col_ptr), _p(self.rows_sorted), _p(self.vals_sorted),
-                                  _p(grad_beta), _p(grad_eta), _p(loglik), self.adj_ws.ptr,
-                                  self.adj_ws.nbytes, _stream(self.device))
+                                  _p(self.chunk_ptr), _p(grad_beta), _p(grad_eta), _p(loglik),
+                                  self.adj_ws.ptr, self.adj_ws.nbytes, _stream(self.device))
         check(rc, "ss_beta_gradient")
         return grad_beta, loglik
 

@@ -113,6 +113,28 @@ def test_new_entry_points_validate_on_the_host(lib):
                                None) == ss.SS_EINVAL
     assert lib.ss_eta_gradient(0, 1000, f, f, f, f, f, f, None, None, f, f, f, ws - 1,
                                None) == ss.SS_EWORKSPACE
+    # X' (dl/deta): the workspace holds the eta-gradient workspace and the
+    # per-span partials, at most 2 (n + p) of them
+    for n, p in ((1000, 3), (1 << 27, 1), (1_000_000, 1000), (40_000, 30_000), (100, 10**6)):
+        wb = lib.ss_beta_gradient_workspace_bytes(n, p)
+        we = lib.ss_eta_gradient_workspace_bytes(n)
+        assert we < wb <= we + 16 * (n + p) + 256, (n, p)
+    assert lib.ss_beta_gradient_workspace_bytes(0, 5) == 0
+    assert lib.ss_beta_gradient_workspace_bytes(5, 0) == 0
+    wb = lib.ss_beta_gradient_workspace_bytes(1000, 3)
+    # model n p inv_perm status eta e d8 d32 w g col rows vals chunk gb ge ll ws
+    assert lib.ss_beta_gradient(4, 1000, 3, None, f, f, f, f, f, None, None, f, f, None, f, f,
+                                None, f, f, wb, None) == ss.SS_EUNSUPPORTED
+    assert lib.ss_beta_gradient(0, 1000, 0, None, f, f, f, f, f, None, None, f, f, None, f, f,
+                                None, f, f, wb, None) == ss.SS_EINVAL
+    assert lib.ss_beta_gradient(0, 1000, 3, None, f, f, f, f, f, None, None, f, f, None, None,
+                                f, None, f, f, wb, None) == ss.SS_EINVAL
+    assert lib.ss_beta_gradient(0, 1000, 3, None, f, f, f, f, f, None, None, f, f, None, f, f,
+                                f, f, f, wb, None) == ss.SS_EINVAL   # grad_eta needs inv_perm
+    assert lib.ss_beta_gradient(1, 1000, 3, None, f, f, f, f, f, None, None, f, f, None, f, f,
+                                None, f, f, wb, None) == ss.SS_EINVAL
+    assert lib.ss_beta_gradient(0, 1000, 3, None, f, f, f, f, f, None, None, f, f, None, f, f,
+                                None, f, f, wb - 1, None) == ss.SS_EWORKSPACE
     # cross-validation: sizes, valued designs unsupported, Fine-Gray needs its
     # Kaplan-Meier arrays
     s = lib.ss_cv_stride(100_000)

@@ -206,3 +206,26 @@ def test_beta_gradient_paper_scale(model):
         x = gen.dense_column(d["n"], d["col_ptr"], d["rows"], None, j)
         want = pr.coordinate(eta, x)
         assert abs(got[j] - want["g1"]) <= TOL * want["scale_g1"], j
+
+
+@pytest.mark.parametrize("model", ["cox", "fg"])
+def test_beta_gradient_wide_design(model):
+    """A design wider than long (N = 40000, P = 30000 sparse indicator
+    columns, ties): the spans of the X' pass grow to keep the partials
+    within 2 (N + P), and every entry still equals X' of the oracle's
+    gradient in eta (sparse product in subject order)."""
+    import scipy.sparse as sp
+    n, p = 40_000, 30_000
+    c = make_case(model, n, p, 44, 30, 0.0005, False)
+    prob = gpu_problem(model, c)
+    lib = ss.load()
+    assert lib.ss_beta_gradient_workspace_bytes(n, p) <= \
+        lib.ss_eta_gradient_workspace_bytes(n) + 16 * (n + p) + 256
+    gb, _ = prob.beta_gradient()
+    got = gb.cpu().numpy()
+    want_eta = oadj.eta_gradient_scan(model, c["y"], c["status"], c["eta"])
+    x = sp.csc_matrix((np.ones(c["rows"].size), c["rows"], c["col_ptr"]), shape=(n, p))
+    want = x.T @ want_eta
+    scale = x.T @ (np.abs(want_eta) + 1.0)
+    assert np.all(np.abs(got - want) <= TOL * scale), np.max(np.abs(got - want) / scale)
+    assert prob.workspace_error() == 0
