@@ -381,7 +381,8 @@ int32_t ss_beta_gradient(int32_t model, int64_t n, int64_t p,
  * e = 0).  Sizes the caller allocates (device memory, caller-owned):
  *   train_s, d8_r: R * stride bytes; d32_r: R * stride int32 (read only
  *   where d8_r = 255, no initialisation needed); eta, e: R * stride
- *   doubles; xbits: P * stride / 8 bytes; c_r, beta, delta: R * P doubles
+ *   doubles; xbits: P * stride / 8 bytes (Fine-Gray: (P + 1) * stride / 8,
+ *   the last column marking competing events); c_r, beta, delta: R * P doubles
  *   (replicate-major); g12_out: R * P * 3 doubles or NULL; Fine-Gray only
  *   (NULL for Cox): w_r, g_r, g_h: R * stride doubles each; out of
  *   ss_cv_loglik: 2 R doubles; ws of ss_cv_prepare:
@@ -392,7 +393,9 @@ int32_t ss_beta_gradient(int32_t model, int64_t n, int64_t p,
  * replicate-major): the sorted training flags train_s, the training events
  * per run end d8_r / d32_r (same encoding as ss_prepare), the column
  * bitmask xbits (bit k of column j, word k/32 of the column's stride/32
- * 32-bit words) and c_r[r][j] = the training events with x_kj = 1.
+ * 32-bit words; Fine-Gray adds column P, bit k set where the subject at
+ * sorted position k had a competing event) and c_r[r][j] = the training
+ * events with x_kj = 1.
  * vals_sorted must be NULL (0/1 design).  Fine-Gray also takes the
  * ORIGINAL-order times y (for the tie runs of the Kaplan-Meier estimates)
  * and writes, per replicate and sorted position k, g_r = G of the training

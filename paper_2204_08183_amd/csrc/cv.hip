@@ -38,7 +38,19 @@ using namespace dev;
 constexpr int kCvBlock = 1024;
 constexpr int kCvWaves = kCvBlock / kWave;
 constexpr int kCvAlign = 16384;  // per-replicate stride unit (a whole chunk)
-constexpr int kCvList = 512;     // non-zero steps held before eta is brought up to date
+constexpr int kCvList = 512;
+#ifndef SS_CV_FG_BLOCK
+#define SS_CV_FG_BLOCK 512
+#endif
+#ifndef SS_CV_FG_IPT
+#define SS_CV_FG_IPT 8
+#endif
+#ifndef SS_CV_COX_BLOCK
+#define SS_CV_COX_BLOCK 1024
+#endif
+constexpr int kCvFgBlock = SS_CV_FG_BLOCK;
+constexpr int kCvCoxBlock = SS_CV_COX_BLOCK;
+constexpr int kCvFgIpt = SS_CV_FG_IPT;     // non-zero steps held before eta is brought up to date
 constexpr int kCvGather = 16;    // column bitmask loads in flight while eta is updated
 // share of a replicate's chunks taken by half 0 of a two-half launch
 // (measured at N = 1e5 .. 4e5, 100 replicates: 12/25 against 2/5, 5/11
@@ -54,14 +66,16 @@ __device__ __forceinline__ bool cv_event(int32_t model, int8_t s)
 // Prefix over the 16 wave totals of a chunk: lane q < 16 holds wave q's
 // total; an inclusive scan within the first DPP row of 16 lanes, then the
 // calling wave takes the sum of the waves before it and the chunk total.
+template <int NW = kCvWaves>
 __device__ __forceinline__ void wave_totals_prefix(double v, int w, double &before,
                                                    double &total)
 {
+    static_assert(NW <= 16, "one DPP row");
     v += dpp_double<0x111, 0xF, true>(v);  // row_shr:1
     v += dpp_double<0x112, 0xF, true>(v);  // row_shr:2
     v += dpp_double<0x114, 0xF, true>(v);  // row_shr:4
     v += dpp_double<0x118, 0xF, true>(v);  // row_shr:8
-    total = read_lane(v, kCvWaves - 1);
+    total = read_lane(v, NW - 1);
     before = w > 0 ? read_lane(v, w - 1) : 0.0;
 }
 
@@ -317,6 +331,20 @@ __global__ __launch_bounds__(256) void k_cv_bits(int64_t p, int64_t words,
 }
 
 // c_j of every replicate: the training events with x_kj = 1.
+// Fine-Gray: bit k of the extra column p is set where the subject at
+// sorted position k had a competing event (status 2).  The mask is cleared
+// beforehand.
+__global__ __launch_bounds__(256) void k_cv_comp_bits(int64_t n, const int32_t *perm,
+                                                      const int8_t *status, uint32_t *bits)
+{
+    for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+        const uint64_t b = __ballot(status[perm[k]] == 2);
+        // lanes 0 and 32 of the wave write their 32-position words
+        const int lane = lane_id();
+        if ((lane & 31) == 0 && (k & 31) == 0) bits[k >> 5] = (uint32_t)(b >> lane);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_cv_c(int64_t p, int64_t words, const uint32_t *xbits,
                                               const uint32_t *evbits, double *c)
 {
@@ -391,6 +419,7 @@ struct CvChunk {
 template <int IPT>
 __device__ __forceinline__ uint32_t cv_bits(const CvArgs &a, int64_t j, int64_t pos)
 {
+    static_assert(IPT == 8 || IPT == 16, "whole bytes of the column bitmask per thread");
     const uint8_t *col = a.xbits + j * (a.stride / 8) + pos / 8;
     if constexpr (IPT == 16) return *reinterpret_cast<const uint16_t *>(col);
     else return *col;
@@ -425,12 +454,12 @@ __device__ __forceinline__ void cv_load(const CvArgs &a, const double *e, const 
 // coordinate-by-coordinate update would add them); with `resync`,
 // e = exp(eta) at training positions and 0 elsewhere afterwards.  Column
 // bitmasks are fetched kCvGather at a time.
-template <int IPT>
+template <int IPT, int BLOCK = kCvBlock>
 __device__ void cv_apply_steps(const CvArgs &a, double *eta, double *e, const uint8_t *train_s,
                                const int32_t *lj, const double *ls, int nlist, int ch_lo,
                                int ch_hi, int64_t tpos, bool resync)
 {
-    constexpr int CHUNK = kCvBlock * IPT;
+    constexpr int CHUNK = BLOCK * IPT;
     for (int ch = ch_lo; ch < ch_hi; ++ch) {
         const int64_t pos = (int64_t)ch * CHUNK + tpos;
         double v[IPT];
@@ -479,12 +508,13 @@ __device__ void cv_apply_steps(const CvArgs &a, double *eta, double *e, const ui
 // A1 + expm1(s) D1 (e at column j + 1; D1 = e at both columns), all
 // summed during the pass of coordinate j before s is known.  Both halves
 // then take the same Newton step from the same numbers.
-template <int IPT, int KH>
-__global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
+template <int BLOCK, int IPT, int KH>
+__global__ __launch_bounds__(BLOCK) void k_cv_sweep(CvArgs a)
 {
-    constexpr int CHUNK = kCvBlock * IPT;
-    __shared__ double s_tot[2][kCvWaves][2];
-    __shared__ double s_red[kCvWaves * 4];
+    constexpr int CHUNK = BLOCK * IPT;
+    constexpr int NW = BLOCK / kWave;
+    __shared__ double s_tot[2][NW][2];
+    __shared__ double s_red[NW * 4];
     __shared__ double s_step[4];  // step, exp(step), half 1's next carry
     __shared__ int32_t s_lj[kCvList];
     __shared__ double s_ls[kCvList];
@@ -552,7 +582,7 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
                             (((xb >> (2 * i + 1)) & 1u) ? t.y : 0.0);
                 }
             }
-            block_sum<2, kCvBlock>(x, s_red);
+            block_sum<2, BLOCK>(x, s_red);
             if (tid == 0) {
                 u32x4 *sl = cv_slot(a, r, 0, 0);
                 st_pair(sl + 0, x[0], tag);
@@ -652,8 +682,8 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
             }
             __syncthreads();
             double b0, b1, T0, T1;
-            wave_totals_prefix(lane < kCvWaves ? s_tot[par][lane][0] : 0.0, w, b0, T0);
-            wave_totals_prefix(lane < kCvWaves ? s_tot[par][lane][1] : 0.0, w, b1, T1);
+            wave_totals_prefix<NW>(lane < NW ? s_tot[par][lane][0] : 0.0, w, b0, T0);
+            wave_totals_prefix<NW>(lane < NW ? s_tot[par][lane][1] : 0.0, w, b1, T1);
             const double p0 = carry0 + b0, p1 = carry1 + b1;
             const double c0 = carry0 + T0, c1 = carry1 + T1;
             par ^= 1;
@@ -677,8 +707,8 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
         }
         // g' = c_j - sum d S1/S0, g'' = -sum d (S2/S0 - (S1/S0)^2), S2 = S1
         double red[4] = {acc1, acc2, a1, d1};
-        if (sums_next) block_sum<4, kCvBlock>(red, s_red);
-        else block_sum<2, kCvBlock>(*reinterpret_cast<double(*)[2]>(red), s_red);
+        if (sums_next) block_sum<4, BLOCK>(red, s_red);
+        else block_sum<2, BLOCK>(*reinterpret_cast<double(*)[2]>(red), s_red);
         if (tid == 0) {
             double g1, g2, step = 0.0;
             bool ok = true;
@@ -752,7 +782,7 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
         }
         jp = j;
         if (s_ln == kCvList) {  // uniform: every thread reads the same count
-            cv_apply_steps<IPT>(a, eta, e, a.train_s + off, s_lj, s_ls, kCvList, ch_lo, ch_hi,
+            cv_apply_steps<IPT, BLOCK>(a, eta, e, a.train_s + off, s_lj, s_ls, kCvList, ch_lo, ch_hi,
                                 tpos, false);
             __syncthreads();
             if (tid == 0) s_ln = 0;
@@ -761,7 +791,7 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep(CvArgs a)
     }
 
     // eta brought up to date, and e = exp(eta) afresh (masked) everywhere
-    cv_apply_steps<IPT>(a, eta, e, a.train_s + off, s_lj, s_ls, s_ln, ch_lo, ch_hi, tpos, true);
+    cv_apply_steps<IPT, BLOCK>(a, eta, e, a.train_s + off, s_lj, s_ls, s_ln, ch_lo, ch_hi, tpos, true);
     // half 0 has seen half 1's last publication, made after half 1 read the
     // epoch: the next launch's tags start after this launch's
     if (KH == 2 && h == 0 && tid == 0 && T > 0 && !s_abort)
@@ -789,13 +819,14 @@ struct CvFgArgs {
 };
 
 
-template <int IPT>
-__global__ __launch_bounds__(kCvBlock) void k_cv_sweep_fg(CvFgArgs f)
+template <int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void k_cv_sweep_fg(CvFgArgs f)
 {
     const CvArgs &a = f.a;
-    constexpr int CHUNK = kCvBlock * IPT;
-    __shared__ double s_tot[2][kCvWaves][4];
-    __shared__ double s_red[kCvWaves * 4];
+    constexpr int CHUNK = BLOCK * IPT;
+    constexpr int NW = BLOCK / kWave;
+    __shared__ double s_tot[2][NW][4];
+    __shared__ double s_red[NW * 4];
     __shared__ double s_step[4];  // step, exp(step), the next column's totals
     __shared__ int32_t s_lj[kCvList];
     __shared__ double s_ls[kCvList];
@@ -831,7 +862,7 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep_fg(CvFgArgs f)
                 x[1] += ((xb >> i) & 1u) ? ew : 0.0;
             }
         }
-        block_sum<2, kCvBlock>(x, s_red);
+        block_sum<2, BLOCK>(x, s_red);
         if (tid == 0) {
             s_step[2] = x[0];
             s_step[3] = x[1];
@@ -879,15 +910,23 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep_fg(CvFgArgs f)
 #pragma unroll
             for (int i = 0; i < IPT; ++i)
                 if (dv[i] == 255u) dv[i] = (uint32_t)d32[pos + i];
-            double wv[IPT];
+            // G of the training subset at the chunk's positions; w = 1/G at
+            // competing events (the w_r of the preparation, bit for bit: the
+            // same division), 0 elsewhere and where G = 0 (no training
+            // competing event there; a held-out one has e = 0)
+            double gv[IPT], wv[IPT];
             {
-                const double2 *ws = reinterpret_cast<const double2 *>(wr + pos);
+                const double2 *gs = reinterpret_cast<const double2 *>(gr + pos);
 #pragma unroll
                 for (int i = 0; i < IPT / 2; ++i) {
-                    const double2 u = ws[i];
-                    wv[2 * i] = u.x;
-                    wv[2 * i + 1] = u.y;
+                    const double2 u = gs[i];
+                    gv[2 * i] = u.x;
+                    gv[2 * i + 1] = u.y;
                 }
+                const uint32_t cb = cv_bits<IPT>(a, a.p, pos);
+#pragma unroll
+                for (int i = 0; i < IPT; ++i)
+                    wv[i] = ((cb >> i) & 1u) && gv[i] != 0.0 ? 1.0 / gv[i] : 0.0;
             }
             CvChunk<IPT> nx;
             const bool last = ch + 1 == nch;
@@ -919,7 +958,7 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep_fg(CvFgArgs f)
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 double b, tt;
-                wave_totals_prefix(lane < kCvWaves ? s_tot[par][lane][c] : 0.0, w, b, tt);
+                wave_totals_prefix<NW>(lane < NW ? s_tot[par][lane][c] : 0.0, w, b, tt);
                 S[c] = carry[c] + b + (inc[c] - t[c]);
                 carry[c] += tt;
             }
@@ -935,7 +974,7 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep_fg(CvFgArgs f)
                 const uint32_t d = dv[i];
                 if (d != 0u) {
                     // G of the training subset at the run end
-                    const double gk = gr[pos + i];
+                    const double gk = gv[i];
                     const double S0 = S[0] + gk * (tw - S[2]);
                     const double S1 = S[1] + gk * (twx - S[3]);
                     const double g = S1 / S0;
@@ -947,7 +986,7 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep_fg(CvFgArgs f)
             cur = nx;
         }
         double red[4] = {acc1, acc2, sa1, sd1};
-        block_sum<4, kCvBlock>(red, s_red);
+        block_sum<4, BLOCK>(red, s_red);
         if (tid == 0) {
             const double g1 = cj - red[0];
             const double g2 = -red[1];
@@ -979,14 +1018,14 @@ __global__ __launch_bounds__(kCvBlock) void k_cv_sweep_fg(CvFgArgs f)
         twx = s_step[3];
         jp = j;
         if (s_ln == kCvList) {
-            cv_apply_steps<IPT>(a, eta, e, a.train_s + off, s_lj, s_ls, kCvList, 0, nch, tpos,
+            cv_apply_steps<IPT, BLOCK>(a, eta, e, a.train_s + off, s_lj, s_ls, kCvList, 0, nch, tpos,
                                 false);
             __syncthreads();
             if (tid == 0) s_ln = 0;
             __syncthreads();
         }
     }
-    cv_apply_steps<IPT>(a, eta, e, a.train_s + off, s_lj, s_ls, s_ln, 0, nch, tpos, true);
+    cv_apply_steps<IPT, BLOCK>(a, eta, e, a.train_s + off, s_lj, s_ls, s_ln, 0, nch, tpos, true);
 }
 
 // Fine-Gray training and held-out log pseudo-likelihoods (eq. fg_l on each
@@ -1214,9 +1253,15 @@ int32_t launch_cv_prepare(int32_t model, int64_t n, int64_t p, int32_t reps, con
     hipLaunchKernelGGL(k_cv_prep, dim3(reps), dim3(kCvBlock), 0, s, model, n, stride, perm,
                        status, train, d8, train_s, d8_r, d32_r, evbits);
     SS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_cv_fill, dim3(grid_of(p * words, 8192)), dim3(256), 0, s, xbits,
-                       p * words);
+    const int64_t cols = model == SS_FINE_GRAY ? p + 1 : p;
+    hipLaunchKernelGGL(k_cv_fill, dim3(grid_of(cols * words, 8192)), dim3(256), 0, s, xbits,
+                       cols * words);
     SS_LAUNCH_CHECK();
+    if (model == SS_FINE_GRAY) {
+        hipLaunchKernelGGL(k_cv_comp_bits, dim3(grid_of(n, 256)), dim3(256), 0, s, n, perm,
+                           status, xbits + p * words);
+        SS_LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(k_cv_bits, dim3((unsigned)std::min<int64_t>(p, 65535)), dim3(256), 0, s,
                        p, words, col_ptr, rows_sorted, xbits);
     SS_LAUNCH_CHECK();
@@ -1277,7 +1322,7 @@ int32_t launch_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n
         f.a = a;
         f.w = w_r;
         f.g = g_r;
-        hipLaunchKernelGGL((k_cv_sweep_fg<8>), dim3(reps), dim3(kCvBlock), 0, s, f);
+        hipLaunchKernelGGL((k_cv_sweep_fg<kCvFgBlock, kCvFgIpt>), dim3(reps), dim3(kCvFgBlock), 0, s, f);
         SS_LAUNCH_CHECK();
         return SS_OK;
     }
@@ -1291,17 +1336,17 @@ int32_t launch_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n
         SS_HIP_CHECK(hipGetDevice(&dev));
         SS_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         SS_HIP_CHECK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-        void *k = reinterpret_cast<void *>(k_cv_sweep<8, 2>);
-        SS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kCvBlock, 0));
+        void *k = reinterpret_cast<void *>(k_cv_sweep<kCvCoxBlock, 8, 2>);
+        SS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kCvCoxBlock, 0));
         const int64_t G = 16 * ceil_div(reps, 8);
         if (coop && G <= (int64_t)per_cu * cus) {
             void *args[] = {&a};
-            SS_HIP_CHECK(hipLaunchCooperativeKernel(k, dim3((unsigned)G), dim3(kCvBlock), args,
+            SS_HIP_CHECK(hipLaunchCooperativeKernel(k, dim3((unsigned)G), dim3(kCvCoxBlock), args,
                                                     0, s));
             return SS_OK;
         }
     }
-    hipLaunchKernelGGL((k_cv_sweep<8, 1>), dim3(reps), dim3(kCvBlock), 0, s, a);
+    hipLaunchKernelGGL((k_cv_sweep<kCvCoxBlock, 8, 1>), dim3(reps), dim3(kCvCoxBlock), 0, s, a);
     SS_LAUNCH_CHECK();
     return SS_OK;
 }

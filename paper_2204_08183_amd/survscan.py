@@ -516,7 +516,8 @@ class CrossValidation:
         self.train_s = torch.empty(reps * stride, dtype=torch.uint8, device=dev)
         self.d8_r = torch.empty(reps * stride, dtype=torch.uint8, device=dev)
         self.d32_r = torch.empty(reps * stride, dtype=torch.int32, device=dev)
-        self.xbits = torch.empty(p * stride // 32, dtype=torch.int32, device=dev)
+        cols = p + 1 if prob.model == FINE_GRAY else p  # Fine-Gray: competing-event bits
+        self.xbits = torch.empty(cols * stride // 32, dtype=torch.int32, device=dev)
         self.c = torch.empty(reps * p, dtype=torch.float64, device=dev)
         fg = prob.model == FINE_GRAY
         self.w_r = torch.empty(reps * stride, dtype=torch.float64, device=dev) if fg else None
