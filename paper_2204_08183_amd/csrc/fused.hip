@@ -399,6 +399,9 @@ __device__ void finish(const FusedCall &a, const WsView &ws, uint64_t epoch,
 // CU instead of 4) and the tile waits on its look-back far longer than on
 // its loads, so one row of 16 measured faster (0.89 ms against 0.93 ms at
 // N = 2^27).  kConsecMax keeps the choice in one place.
+#ifndef SS_FG_G_LDS
+#define SS_FG_G_LDS 1
+#endif
 #ifndef SS_CONSEC_MAX
 #define SS_CONSEC_MAX 16
 #endif
@@ -690,7 +693,13 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
 
     __shared__ __attribute__((aligned(16))) uint8_t s_flag[TILE];
     __shared__ double s_xv[VALS ? TILE : 1];
-    __shared__ double s_ep[PREV ? TILE : 1];
+    // G(Y) of the tile (Fine-Gray) and the patched e of the pending update
+    // (PREV) share one array: the patch is consumed during staging, and with
+    // PREV the copy of G is only started after that
+    constexpr bool kGLds = SS_FG_G_LDS && MODEL == SS_FINE_GRAY;
+    __shared__ __attribute__((aligned(16))) double s_eg[(PREV || kGLds) ? TILE : 1];
+    double *const s_ep = s_eg;
+    double *const s_g = s_eg;
     __shared__ double s_wsum[TileMap<IPT>::R][NW][NX];
     __shared__ double s_excl[NX];
     __shared__ double s_red[NW * NR + NR];
@@ -726,6 +735,28 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     // ---- 2-4. tile data, column j and the pending update into registers
     constexpr int C = TileMap<IPT>::CONSEC;
     constexpr int R = TileMap<IPT>::R;
+    // Fine-Gray: G(Y) of a full tile goes straight from memory into LDS
+    // (no registers), issued with the staging loads, so the transform finds
+    // it there at the run ends instead of waiting on loads of its own after
+    // the look-back.  Lane l of wave v puts its elements 2u, 2u + 1 at
+    // s_g[v * IPT * 64 + u * 128 + 2 l].  A partial last tile reads G at its
+    // run ends.
+    const bool g_lds = kGLds && cnt == TILE;
+    if (!PREV && g_lds) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+#pragma unroll
+            for (int h = 0; h < C / 2; ++h) {
+                const int u = q * (C / 2) + h;
+                __builtin_amdgcn_global_load_lds(
+                    static_cast<const void *>(a.g_end + t0 + (int64_t)q * BLOCK * C +
+                                              (int64_t)tid * C + 2 * h),
+                    (__attribute__((address_space(3))) void *)(s_g + w * (IPT * kWave) +
+                                                               u * (2 * kWave)),
+                    16, 0, 0);
+            }
+        }
+    }
     ET ev[IPT];
     double wv[MODEL == SS_FINE_GRAY ? IPT : 1];
     uint32_t dw[(IPT + 3) / 4];  // event counts, one byte per element
@@ -733,6 +764,24 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     const uint32_t xbits =
         stage_tile<BLOCK, IPT, MODEL == SS_FINE_GRAY, VALS, PREV, true, CARRY, ET>(
             a, t0, cnt, chunk0, chunk1, s_flag, s_xv, s_ep, ev, wv, dw, &nbits);
+    if constexpr (PREV && kGLds) {
+        // every thread has read its patches: the array takes G now, loaded
+        // by waves 1.. for all waves (wave 0's loads would hold up its
+        // look-back, which waits on its own memory counter)
+        __syncthreads();
+        if (g_lds && w != 0) {
+            for (int m = w - 1; m < NW * (IPT / 2); m += NW - 1) {
+                const int v = m / (IPT / 2), u = m % (IPT / 2);
+                const int q = u / (C / 2), h = u % (C / 2);
+                __builtin_amdgcn_global_load_lds(
+                    static_cast<const void *>(a.g_end + t0 + (int64_t)q * BLOCK * C +
+                                              (int64_t)(v * kWave + lane) * C + 2 * h),
+                    (__attribute__((address_space(3))) void *)(s_g + v * (IPT * kWave) +
+                                                               u * (2 * kWave)),
+                    16, 0, 0);
+            }
+        }
+    }
     SS_TRACE(ws, tile, 1);
 
     // ---- 5. thread totals per row and their wave scans (which are also the
@@ -836,6 +885,9 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
             }
         }
     }
+    // the copy of G in LDS has landed: each wave waits for its own loads
+    // (they count on its memory counter), the barrier for the others'
+    if (g_lds) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     SS_TRACE(ws, tile, 3);
     // the products of step 5 are formed again below rather than kept live
@@ -927,7 +979,10 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
             double S0 = Sd[0], S1 = Sd[Tx::EX], S2 = Sd[Tx::EXX];
             if (MODEL == SS_FINE_GRAY) {
                 double g = 0.0;
-                if (d != 0) g = a.g_end[t0 + tile_pos<BLOCK, IPT>(i, tid)];
+                if (d != 0) {
+                    g = g_lds ? s_g[w * (IPT * kWave) + (i / 2) * (2 * kWave) + 2 * lane + (i & 1)]
+                              : a.g_end[t0 + tile_pos<BLOCK, IPT>(i, tid)];
+                }
                 S0 += g * (tot[0] - Sd[Tx::EW]);
                 S1 += g * (tot[1] - Sd[Tx::EXW]);
                 S2 = VALS ? S2 + g * (tot[2] - Sd[Tx::EXXW]) : S1;
