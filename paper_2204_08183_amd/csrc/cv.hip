@@ -800,100 +800,181 @@ __global__ __launch_bounds__(BLOCK) void k_cv_sweep(CvArgs a)
 
 
 // ---------------------------------------------------------------- Fine-Gray
-// One workgroup per replicate, Fine-Gray model, 0/1 design.  The tuple of
-// Sec. 2.7 has four distinct components here (e, e x, e w, e x w; x^2 = x),
-// and each run end with training events needs, besides the prefix sums,
-// G of the replicate's training subset times the weighted suffix: the
-// totals T = sum e w and Tx = sum e w x_j of the replicate minus the
-// inclusive prefixes of e w and e x w.  The totals are needed before the
-// scan, so they are carried from one coordinate to the next in closed form:
-// the step s of column j multiplies e by exp(s) at its rows, so the totals
-// of column j + 1 are A + expm1(s) D and A1 + expm1(s) D1, with A = sum e w,
-// D = sum e w x_j, A1 = sum e w x_{j+1}, D1 = sum e w x_j x_{j+1} summed
-// during the pass of column j.  A pass before the first coordinate sums the
-// totals of column j_begin.  Summation order fixed (deterministic).
+// Fine-Gray model, 0/1 design.  The tuple of Sec. 2.7 has four distinct
+// components here (e, e x, e w, e x w; x^2 = x), and each run end with
+// training events needs, besides the prefix sums, G of the replicate's
+// training subset times the weighted suffix: the totals T = sum e w and
+// Tx = sum e w x_j of the replicate minus the inclusive prefixes of e w and
+// e x w.  The totals are needed before the scan, so they are carried from
+// one coordinate to the next in closed form: the step s of column j
+// multiplies e by exp(s) at its rows, so the totals of column j + 1 are
+// A + expm1(s) D and A1 + expm1(s) D1, with A = sum e w, D = sum e w x_j,
+// A1 = sum e w x_{j+1}, D1 = sum e w x_j x_{j+1} summed during the pass of
+// column j.  A pass before the first coordinate sums the totals of column
+// j_begin.  w = 1/G where the subject had a competing event (a bit column
+// after the design's columns), 0 elsewhere: the division the preparation
+// makes for w_r, so the same bits.
+//
+// KH = 2: two workgroups per replicate, the halves of its chunks, as in the
+// Cox sweep.  Half 1 starts each coordinate from half 0's sums of the four
+// components, which half 0 gives it in closed form from the previous pass
+// (its sums of e, e x_j, e w, e w x_j and of e x_{j+1}, e x_j x_{j+1},
+// e w x_{j+1}, e w x_j x_{j+1}); before the first coordinate half 1 sums
+// them itself over half 0's chunks.  Per coordinate the halves exchange once
+// (half 0: its partial sums, those eight, c_j, beta_j, delta_j; half 1: its
+// partial sums, its prefix carries of e w and e w x_j, which end as the
+// replicate's, and its sums for A1, D1) and both take the same step and the
+// same next totals from the same numbers.  Summation order fixed
+// (deterministic).
 struct CvFgArgs {
     CvArgs a;
-    const double *w;  // w_r: training competing weights, replicate-major
     const double *g;  // g_r: G of the training subset
 };
 
+// w at a thread's IPT positions from G and the competing-event bits.
+template <int IPT>
+__device__ __forceinline__ void fg_weights(uint32_t cb, const double (&gv)[IPT],
+                                           double (&wv)[IPT])
+{
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) wv[i] = ((cb >> i) & 1u) && gv[i] != 0.0 ? 1.0 / gv[i] : 0.0;
+}
 
+template <int IPT>
+__device__ __forceinline__ void fg_load_g(const double *gr, int64_t pos, double (&gv)[IPT])
+{
+    const double2 *gs = reinterpret_cast<const double2 *>(gr + pos);
+#pragma unroll
+    for (int i = 0; i < IPT / 2; ++i) {
+        const double2 u = gs[i];
+        gv[2 * i] = u.x;
+        gv[2 * i + 1] = u.y;
+    }
+}
+
+// Sums over chunks [lo, hi) of e, e x_j, e w, e w x_j (the four components
+// of column j), in the workgroup's fixed order; every thread gets them.
 template <int BLOCK, int IPT>
+__device__ void fg_sums(const CvArgs &a, const double *e, const double *gr, int64_t j, int lo,
+                        int hi, int64_t tpos, double *s_red, double *s_bc, double (&out)[4])
+{
+    constexpr int CHUNK = BLOCK * IPT;
+    double x[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int ch = lo; ch < hi; ++ch) {
+        const int64_t pos = (int64_t)ch * CHUNK + tpos;
+        const uint32_t xb = cv_bits<IPT>(a, j, pos);
+        double gv[IPT], wv[IPT];
+        fg_load_g<IPT>(gr, pos, gv);
+        fg_weights<IPT>(cv_bits<IPT>(a, a.p, pos), gv, wv);
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const double ev = e[pos + i];
+            const double ew = ev * wv[i];
+            const bool xi = (xb >> i) & 1u;
+            x[0] += ev;
+            x[1] += xi ? ev : 0.0;
+            x[2] += ew;
+            x[3] += xi ? ew : 0.0;
+        }
+    }
+    block_sum<4, BLOCK>(x, s_red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s_bc[c] = x[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out[c] = s_bc[c];
+    __syncthreads();
+}
+
+template <int BLOCK, int IPT, int KH>
 __global__ __launch_bounds__(BLOCK) void k_cv_sweep_fg(CvFgArgs f)
 {
     const CvArgs &a = f.a;
     constexpr int CHUNK = BLOCK * IPT;
     constexpr int NW = BLOCK / kWave;
     __shared__ double s_tot[2][NW][4];
-    __shared__ double s_red[NW * 4];
-    __shared__ double s_step[4];  // step, exp(step), the next column's totals
+    __shared__ double s_red[NW * 6];
+    // step, exp(step), the next column's totals, half 1's next carries
+    __shared__ double s_step[8];
     __shared__ int32_t s_lj[kCvList];
     __shared__ double s_ls[kCvList];
     __shared__ int s_ln;
+    __shared__ int s_abort;
+    __shared__ uint64_t s_ep0;
 
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int w = tid / kWave;
-    const int64_t r = blockIdx.x;
+    int64_t r;
+    int h;
+    if constexpr (KH == 1) {
+        r = blockIdx.x;
+        h = 0;
+    } else {
+        // the two halves of a replicate are 8 workgroups apart (same XCD)
+        const int b = (int)blockIdx.x;
+        r = (int64_t)(b / 16) * 8 + (b % 8);
+        h = (b % 16) / 8;
+        if (r >= a.reps) return;
+    }
     const int64_t off = r * a.stride;
     double *eta = a.eta + off;
     double *e = a.e + off;
-    const double *wr = f.w + off;
     const double *gr = f.g + off;
     const uint8_t *d8 = a.d8 + off;
     const int32_t *d32 = a.d32 + off;
     const int nch = (int)min(a.stride / CHUNK, (a.n + CHUNK - 1) / CHUNK);
+    const int chm = (nch * kCvSplitNum + kCvSplitDen / 2) / kCvSplitDen;
+    const int ch_lo = (KH == 2 && h == 1) ? chm : 0;
+    const int ch_hi = (KH == 2 && h == 0) ? chm : nch;
+    const bool lead = h == 0;                  // owns beta, delta, g12_out
+    const bool sums_next = KH == 2 && h == 0;  // e x_{j+1} sums for half 1
     const int64_t tpos = (int64_t)tid * IPT;
     const int64_t T = a.j_end - a.j_begin;
-    if (tid == 0) s_ln = 0;
-
-    // totals of the first coordinate
-    double tw = 0.0, twx = 0.0;
-    if (T > 0) {
-        double x[2] = {0.0, 0.0};
-        for (int ch = 0; ch < nch; ++ch) {
-            const int64_t pos = (int64_t)ch * CHUNK + tpos;
-            const uint32_t xb = cv_bits<IPT>(a, a.j_begin, pos);
-#pragma unroll
-            for (int i = 0; i < IPT; ++i) {
-                const double ew = e[pos + i] * wr[pos + i];
-                x[0] += ew;
-                x[1] += ((xb >> i) & 1u) ? ew : 0.0;
-            }
-        }
-        block_sum<2, BLOCK>(x, s_red);
-        if (tid == 0) {
-            s_step[2] = x[0];
-            s_step[3] = x[1];
-        }
+    if (tid == 0) {
+        s_ln = 0;
+        s_abort = 0;
+        s_ep0 = KH == 2 ? ld_relaxed_u64(cv_epoch(a, r)) : 0;
     }
     __syncthreads();
-    tw = s_step[2];
-    twx = s_step[3];
+    const uint64_t ep0 = s_ep0;
+
+    // totals of the first coordinate (every half over all chunks, in the
+    // same order: the same numbers), and half 1's first carries
+    double tw = 0.0, twx = 0.0;
+    double k[4] = {0.0, 0.0, 0.0, 0.0};
+    if (T > 0) {
+        double t4[4];
+        fg_sums<BLOCK, IPT>(a, e, gr, a.j_begin, 0, nch, tpos, s_red, s_step, t4);
+        tw = t4[2];
+        twx = t4[3];
+        if (KH == 2 && h == 1) fg_sums<BLOCK, IPT>(a, e, gr, a.j_begin, 0, chm, tpos, s_red, s_step, k);
+    }
 
     double s_prev = 0.0, es_prev = 1.0;
     int64_t jp = -1;
     // the next chunk's e, counts and column bits are loaded during the
-    // current one's arithmetic (x1: column j + 1, for the next totals); the
-    // weights are loaded with the chunk itself (fewer registers)
+    // current one's arithmetic (x1: column j + 1, for the next totals); G
+    // is loaded with the chunk itself (fewer registers)
     CvChunk<IPT> cur;
-    if (T > 0 && nch > 0)
-        cv_load<IPT>(a, e, d8, tpos, a.j_begin, -1, a.j_begin + 1 < a.j_end ? a.j_begin + 1 : -1,
-                     cur);
+    if (T > 0 && ch_lo < ch_hi)
+        cv_load<IPT>(a, e, d8, (int64_t)ch_lo * CHUNK + tpos, a.j_begin, -1,
+                     a.j_begin + 1 < a.j_end ? a.j_begin + 1 : -1, cur);
     int par = 0;
-    for (int64_t j = a.j_begin; j < a.j_end; ++j) {
+    for (int64_t j = a.j_begin; j < a.j_end && !s_abort; ++j) {
         double cj = 0.0, bj = 0.0, dj = 0.0;
-        if (tid == 0) {
+        if (lead && tid == 0) {
             cj = a.c[r * a.p + j];
             bj = a.beta[r * a.p + j];
             dj = a.delta[r * a.p + j];
         }
-        // carry[2], carry[3] end the pass as sum e w and sum e w x_j over the
-        // replicate (the same value in every thread)
-        double acc1 = 0.0, acc2 = 0.0, sa1 = 0.0, sd1 = 0.0;
-        double carry[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int ch = 0; ch < nch; ++ch) {
+        // carry[2], carry[3] end the pass as sum e w and sum e w x_j up to
+        // the end of this half (half 1: over the replicate)
+        double acc1 = 0.0, acc2 = 0.0, sa1 = 0.0, sd1 = 0.0, a1 = 0.0, d1 = 0.0;
+        double carry[4] = {k[0], k[1], k[2], k[3]};
+        for (int ch = ch_lo; ch < ch_hi; ++ch) {
             const int64_t pos = (int64_t)ch * CHUNK + tpos;
             if (cur.px != 0u && s_prev != 0.0) {
 #pragma unroll
@@ -910,29 +991,16 @@ __global__ __launch_bounds__(BLOCK) void k_cv_sweep_fg(CvFgArgs f)
 #pragma unroll
             for (int i = 0; i < IPT; ++i)
                 if (dv[i] == 255u) dv[i] = (uint32_t)d32[pos + i];
-            // G of the training subset at the chunk's positions; w = 1/G at
-            // competing events (the w_r of the preparation, bit for bit: the
-            // same division), 0 elsewhere and where G = 0 (no training
-            // competing event there; a held-out one has e = 0)
+            // G of the training subset at the chunk's positions and w
             double gv[IPT], wv[IPT];
-            {
-                const double2 *gs = reinterpret_cast<const double2 *>(gr + pos);
-#pragma unroll
-                for (int i = 0; i < IPT / 2; ++i) {
-                    const double2 u = gs[i];
-                    gv[2 * i] = u.x;
-                    gv[2 * i + 1] = u.y;
-                }
-                const uint32_t cb = cv_bits<IPT>(a, a.p, pos);
-#pragma unroll
-                for (int i = 0; i < IPT; ++i)
-                    wv[i] = ((cb >> i) & 1u) && gv[i] != 0.0 ? 1.0 / gv[i] : 0.0;
-            }
+            fg_load_g<IPT>(gr, pos, gv);
+            fg_weights<IPT>(cv_bits<IPT>(a, a.p, pos), gv, wv);
             CvChunk<IPT> nx;
-            const bool last = ch + 1 == nch;
+            const bool last = ch + 1 == ch_hi;
             const int64_t jn = last ? (j + 1 < a.j_end ? j + 1 : j) : j;
             const int64_t jn1 = jn + 1 < a.j_end ? jn + 1 : -1;
-            cv_load<IPT>(a, e, d8, last ? tpos : pos + CHUNK, jn, last ? j : jp, jn1, nx);
+            cv_load<IPT>(a, e, d8, last ? (int64_t)ch_lo * CHUNK + tpos : pos + CHUNK, jn,
+                         last ? j : jp, jn1, nx);
 
             double t[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -946,6 +1014,10 @@ __global__ __launch_bounds__(BLOCK) void k_cv_sweep_fg(CvFgArgs f)
                 const bool x1 = (cur.x1 >> i) & 1u;
                 sa1 += x1 ? ew : 0.0;
                 sd1 += (x1 && xi) ? ew : 0.0;
+                if (sums_next) {
+                    a1 += x1 ? cur.v[i] : 0.0;
+                    d1 += (x1 && xi) ? cur.v[i] : 0.0;
+                }
             }
             double inc[4];
 #pragma unroll
@@ -985,26 +1057,79 @@ __global__ __launch_bounds__(BLOCK) void k_cv_sweep_fg(CvFgArgs f)
             }
             cur = nx;
         }
-        double red[4] = {acc1, acc2, sa1, sd1};
-        block_sum<4, BLOCK>(red, s_red);
+        double red[6] = {acc1, acc2, sa1, sd1, a1, d1};
+        if (sums_next) block_sum<6, BLOCK>(red, s_red);
+        else block_sum<4, BLOCK>(*reinterpret_cast<double(*)[4]>(red), s_red);
         if (tid == 0) {
-            const double g1 = cj - red[0];
-            const double g2 = -red[1];
-            double step = 0.0;
-            ccd_apply(g1, g2, a.penalty, a.lambda, &bj, &dj, &step);
-            a.beta[r * a.p + j] = bj;
-            a.delta[r * a.p + j] = dj;
-            if (a.g12_out) {
-                double *o = a.g12_out + (r * a.p + j) * 3;
-                o[0] = g1;
-                o[1] = g2;
-                o[2] = step;
+            double g1, g2, step = 0.0;
+            bool ok = true;
+            double A1 = red[2], D1 = red[3];  // sum e w x_{j+1}, e w x_j x_{j+1}
+            double Aw = carry[2], Dw = carry[3];  // sum e w, e w x_j (replicate)
+            if constexpr (KH == 2) {
+                const int64_t t = j - a.j_begin + 1;
+                const uint64_t tag = ((ep0 + (uint64_t)t) << 1) | 1u;
+                const int q = (int)(t & 1);
+                double h0[15], h1[6];
+                if (h == 0) {
+                    h0[0] = red[0]; h0[1] = red[1];
+                    h0[2] = carry[0]; h0[3] = carry[1]; h0[4] = carry[2]; h0[5] = carry[3];
+                    h0[6] = red[4]; h0[7] = red[5]; h0[8] = red[2]; h0[9] = red[3];
+                    h0[10] = cj; h0[11] = bj; h0[12] = dj; h0[13] = 0.0; h0[14] = 0.0;
+                    u32x4 *sl = cv_slot(a, r, 0, q);
+#pragma unroll
+                    for (int m = 0; m < 15; ++m) st_pair(sl + m, h0[m], tag);
+                    u32x4 rr[6];
+                    ok = wait_pairs<6>(cv_slot(a, r, 1, q), tag, a.hdr, rr);
+#pragma unroll
+                    for (int m = 0; m < 6; ++m) h1[m] = pair_value(rr[m]);
+                } else {
+                    h1[0] = red[0]; h1[1] = red[1]; h1[2] = carry[2]; h1[3] = carry[3];
+                    h1[4] = red[2]; h1[5] = red[3];
+                    u32x4 *sl = cv_slot(a, r, 1, q);
+#pragma unroll
+                    for (int m = 0; m < 6; ++m) st_pair(sl + m, h1[m], tag);
+                    u32x4 rr[15];
+                    ok = wait_pairs<15>(cv_slot(a, r, 0, q), tag, a.hdr, rr);
+#pragma unroll
+                    for (int m = 0; m < 15; ++m) h0[m] = pair_value(rr[m]);
+                    cj = h0[10]; bj = h0[11]; dj = h0[12];
+                }
+                g1 = cj - (h0[0] + h1[0]);
+                g2 = -(h0[1] + h1[1]);
+                // the replicate's sums, the same numbers in both halves
+                Aw = h1[2];
+                Dw = h1[3];
+                A1 = h0[8] + h1[4];
+                D1 = h0[9] + h1[5];
+                if (ok) ccd_apply(g1, g2, a.penalty, a.lambda, &bj, &dj, &step);
+                if (h == 1) {
+                    const double em = expm1(step);
+                    s_step[4] = fma(em, h0[3], h0[2]);
+                    s_step[5] = fma(em, h0[7], h0[6]);
+                    s_step[6] = fma(em, h0[5], h0[4]);
+                    s_step[7] = fma(em, h0[9], h0[8]);
+                }
+            } else {
+                g1 = cj - red[0];
+                g2 = -red[1];
+                ccd_apply(g1, g2, a.penalty, a.lambda, &bj, &dj, &step);
+            }
+            if (!ok) s_abort = 1;
+            if (lead && ok) {
+                a.beta[r * a.p + j] = bj;
+                a.delta[r * a.p + j] = dj;
+                if (a.g12_out) {
+                    double *o = a.g12_out + (r * a.p + j) * 3;
+                    o[0] = g1;
+                    o[1] = g2;
+                    o[2] = step;
+                }
             }
             const double em = expm1(step);
             s_step[0] = step;
             s_step[1] = exp(step);
-            s_step[2] = fma(em, carry[3], carry[2]);
-            s_step[3] = fma(em, red[3], red[2]);
+            s_step[2] = fma(em, Dw, Aw);
+            s_step[3] = fma(em, D1, A1);
             if (step != 0.0) {
                 s_lj[s_ln] = (int32_t)j;
                 s_ls[s_ln] = step;
@@ -1016,16 +1141,25 @@ __global__ __launch_bounds__(BLOCK) void k_cv_sweep_fg(CvFgArgs f)
         es_prev = s_step[1];
         tw = s_step[2];
         twx = s_step[3];
+        if (KH == 2 && h == 1) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) k[c] = s_step[4 + c];
+        }
         jp = j;
         if (s_ln == kCvList) {
-            cv_apply_steps<IPT, BLOCK>(a, eta, e, a.train_s + off, s_lj, s_ls, kCvList, 0, nch, tpos,
-                                false);
+            cv_apply_steps<IPT, BLOCK>(a, eta, e, a.train_s + off, s_lj, s_ls, kCvList, ch_lo,
+                                       ch_hi, tpos, false);
             __syncthreads();
             if (tid == 0) s_ln = 0;
             __syncthreads();
         }
     }
-    cv_apply_steps<IPT, BLOCK>(a, eta, e, a.train_s + off, s_lj, s_ls, s_ln, 0, nch, tpos, true);
+    cv_apply_steps<IPT, BLOCK>(a, eta, e, a.train_s + off, s_lj, s_ls, s_ln, ch_lo, ch_hi, tpos,
+                               true);
+    // half 0 has seen half 1's last publication, made after half 1 read the
+    // epoch: the next launch's tags start after this launch's
+    if (KH == 2 && h == 0 && tid == 0 && T > 0 && !s_abort)
+        st_relaxed_u64(cv_epoch(a, r), ep0 + (uint64_t)T + 1);
 }
 
 // Fine-Gray training and held-out log pseudo-likelihoods (eq. fg_l on each
@@ -1316,21 +1450,36 @@ int32_t launch_cv_sweep(int32_t model, int32_t penalty, double lambda, int64_t n
     a.g12_out = g12_out;
     a.hdr = reinterpret_cast<WsHeader *>(ws);
     a.xch = reinterpret_cast<char *>(ws) + 256;
-    if (model == SS_FINE_GRAY) {
-        // one workgroup per replicate (no exchange, no co-residency needed)
-        CvFgArgs f;
-        f.a = a;
-        f.w = w_r;
-        f.g = g_r;
-        hipLaunchKernelGGL((k_cv_sweep_fg<kCvFgBlock, kCvFgIpt>), dim3(reps), dim3(kCvFgBlock), 0, s, f);
-        SS_LAUNCH_CHECK();
-        return SS_OK;
-    }
     // two workgroups per replicate when all of them fit on the device at
     // once (a cooperative launch checks it); one per replicate otherwise.
     // SURVSCAN_CV_HALVES=1 forces one.
     const char *env = getenv("SURVSCAN_CV_HALVES");
     const bool allow2 = !(env && env[0] == '1');
+    (void)w_r;  // the sweep derives w from G (the same division)
+    if (model == SS_FINE_GRAY) {
+        CvFgArgs f;
+        f.a = a;
+        f.g = g_r;
+        if (allow2) {
+            int dev = 0, cus = 0, coop = 0, per_cu = 0;
+            SS_HIP_CHECK(hipGetDevice(&dev));
+            SS_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            SS_HIP_CHECK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+            void *k = reinterpret_cast<void *>(k_cv_sweep_fg<kCvFgBlock, kCvFgIpt, 2>);
+            SS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kCvFgBlock, 0));
+            const int64_t G = 16 * ceil_div(reps, 8);
+            if (coop && G <= (int64_t)per_cu * cus) {
+                void *args[] = {&f};
+                SS_HIP_CHECK(hipLaunchCooperativeKernel(k, dim3((unsigned)G), dim3(kCvFgBlock),
+                                                        args, 0, s));
+                return SS_OK;
+            }
+        }
+        hipLaunchKernelGGL((k_cv_sweep_fg<kCvFgBlock, kCvFgIpt, 1>), dim3(reps), dim3(kCvFgBlock),
+                           0, s, f);
+        SS_LAUNCH_CHECK();
+        return SS_OK;
+    }
     if (allow2) {
         int dev = 0, cus = 0, coop = 0, per_cu = 0;
         SS_HIP_CHECK(hipGetDevice(&dev));

@@ -213,14 +213,15 @@ def test_cv_no_training_events():
     assert ll[1, 1] == pytest.approx(want, rel=1e-11)
 
 
+@pytest.mark.parametrize("model", ["cox", "fg"])
 @pytest.mark.parametrize("halves", HALVES)
-def test_cv_deterministic_and_set_eta(halves, monkeypatch):
+def test_cv_deterministic_and_set_eta(halves, model, monkeypatch):
     _halves(monkeypatch, halves)
-    d = cox_case(40000, 5, 11)
+    d = cox_case(40000, 5, 11) if model == "cox" else fg_case(40000, 5, 11)
     train = gen.cv_folds(12, d["n"], 5, 1)
     outs = []
     for _ in range(2):
-        prob, cvp = make_cv(d, train)
+        prob, cvp = make_cv(d, train, model)
         rng = np.random.default_rng(3)
         eta0 = rng.normal(0.0, 0.3, (cvp.reps, d["n"]))
         cvp.set_eta(eta0)
@@ -231,7 +232,7 @@ def test_cv_deterministic_and_set_eta(halves, monkeypatch):
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[0][1], outs[1][1])
     # first sweep from a non-zero eta against the oracle (replicate 2)
-    prob, cvp = make_cv(d, train)
+    prob, cvp = make_cv(d, train, model)
     cvp.set_eta(eta0)
     g12 = torch.zeros(cvp.reps * d["p"] * 3, dtype=torch.float64, device=DEV)
     cvp.sweep("l1", 0.3, g12_out=g12)
@@ -239,7 +240,7 @@ def test_cv_deterministic_and_set_eta(halves, monkeypatch):
     r = 2
     tr = train[r] == 1
     ys, sts, cp, rr, _, idx = ocv.subset(d["y"], d["status"], d["col_ptr"], d["rows"], None, tr)
-    _, _, _, hist = ocv.ccd_sweeps("cox", ys, sts, cp, rr, None, eta0[r][idx],
+    _, _, _, hist = ocv.ccd_sweeps(model, ys, sts, cp, rr, None, eta0[r][idx],
                                    occd.PENALTY_L1, 0.3, 1)
     for j in range(d["p"]):
         g1, g2, s1, s2 = hist[j]
@@ -302,17 +303,19 @@ def test_cv_many_steps_in_one_launch(halves, monkeypatch):
     check_sweeps(d, train, "none", 0.0, 2, 1e-9)
 
 
+@pytest.mark.parametrize("model", ["cox", "fg"])
 @pytest.mark.parametrize("reps", [1, 150])
-def test_cv_replicate_counts(reps, monkeypatch):
+def test_cv_replicate_counts(reps, model, monkeypatch):
     """One replicate, and more replicates than fit two workgroups each on
     the device at once (the launch then takes one workgroup per replicate
     by itself); sampled replicates against the oracle."""
     monkeypatch.delenv("SURVSCAN_CV_HALVES", raising=False)
-    d = cox_case(9000, 4, 16, density=0.1)
+    d = cox_case(9000, 4, 16, density=0.1) if model == "cox" else \
+        fg_case(9000, 4, 16, density=0.1)
     rng = np.random.default_rng(17)
     train = (rng.random((reps, d["n"])) < 0.8).astype(np.uint8)
     check_sweeps(d, train, "l1", 0.7, 2, 1e-9,
-                 reps_to_check=(0,) if reps == 1 else (0, 77, reps - 1))
+                 reps_to_check=(0,) if reps == 1 else (0, 77, reps - 1), model=model)
 
 
 def test_cv_path_matches_oracle():
@@ -365,24 +368,32 @@ def test_cv_fg_prepare_km_matches_oracle():
             assert c[r, j] == float(np.sum(x[tr] * (d["status"][tr] == 1)))
 
 
+@pytest.mark.parametrize("halves", HALVES)
 @pytest.mark.parametrize("penalty,lam", [("l1", 2.0), ("l2", 1.0), ("none", 0.0)])
-def test_cv_fg_sweeps_match_oracle(penalty, lam):
+def test_cv_fg_sweeps_match_oracle(penalty, lam, halves, monkeypatch):
+    _halves(monkeypatch, halves)
     d = fg_case(7000, 8, 23, density=0.2)
     train = gen.cv_folds(24, d["n"], 4, 2)
     check_sweeps(d, train, penalty, lam, 2, 1e-9, model="fg")
 
 
+@pytest.mark.parametrize("halves", HALVES)
+# chunks of 4096 positions: 16384 fills its stride, 16385, 40961 and 50001
+# leave chunks of pure padding; the halves split the chunks 12:13
 @pytest.mark.parametrize("n,p,ties", [(1, 2, 0), (3, 2, 0), (8193, 4, 0), (50001, 5, 40),
-                                      (16384, 3, 0), (16385, 3, 5)])
-def test_cv_fg_sizes_and_ties(n, p, ties):
+                                      (16384, 3, 0), (16385, 3, 5), (40961, 3, 30)])
+def test_cv_fg_sizes_and_ties(n, p, ties, halves, monkeypatch):
+    _halves(monkeypatch, halves)
     d = fg_case(n, p, 25, ties=ties, density=0.3 if n < 10 else 0.1)
     train = gen.cv_folds(26, n, 3, 2) if n >= 3 else np.ones((2, n), np.uint8)
     check_sweeps(d, train, "l1", 0.5, 1, 1e-10, model="fg")
 
 
-def test_cv_fg_many_steps_in_one_launch():
+@pytest.mark.parametrize("halves", HALVES)
+def test_cv_fg_many_steps_in_one_launch(halves, monkeypatch):
     """More non-zero steps than the kernel holds before eta is brought up to
     date, so the carried weighted totals cross that update too."""
+    _halves(monkeypatch, halves)
     d = fg_case(2500, 700, 27, density=0.05)
     train = gen.cv_folds(28, d["n"], 5, 1)[:2]
     check_sweeps(d, train, "none", 0.0, 2, 1e-9, model="fg")
@@ -402,9 +413,11 @@ def test_cv_fg_everyone_training_equals_single_sweep():
     assert np.array_equal(got[0], got[1])
 
 
-def test_cv_fg_ten_by_ten_design():
+@pytest.mark.parametrize("halves", HALVES)
+def test_cv_fg_ten_by_ten_design(halves, monkeypatch):
     """10 x 10 cross-validation of the Fine-Gray model at N = 1e5,
     P = 1000, one l1 sweep: replicates 0, 57 and 99 against the oracle."""
+    _halves(monkeypatch, halves)
     d = fg_case(100_000, 1000, 0, density=0.05)
     train = gen.cv_folds(0, d["n"], 10, 10)
     check_sweeps(d, train, "l1", float(np.sqrt(2.0)), 1, 1e-10, reps_to_check=(0, 57, 99),
