@@ -646,23 +646,6 @@ struct Tuple {
     }
 };
 
-// 1/x by the hardware's reciprocal estimate refined with Newton's iteration
-// r <- r + r (1 - x r) (two steps in FP64, one in FP32): within a unit or two
-// of the last place for the positive normal x of the transform.
-__device__ __forceinline__ double recip(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-__device__ __forceinline__ float recip(float x)
-{
-    const float r = __builtin_amdgcn_rcpf(x);
-    return fmaf(r, fmaf(-x, r, 1.0f), r);
-}
-
 // The fused scan -> transform -> reduce kernel (one coordinate).
 // MODEL: SS_COX (3 tuple components) or SS_FINE_GRAY (6).  PREV: apply the
 // pending step of column jprev to eta and e first (step (1) of Sec. 2.7).

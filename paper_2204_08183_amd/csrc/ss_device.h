@@ -42,6 +42,23 @@ __device__ __forceinline__ double read_lane(double x, int lane)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// 1/x by the hardware's reciprocal estimate refined with Newton's iteration
+// r <- r + r (1 - x r) (two steps in FP64, one in FP32): within a unit or two
+// of the last place for the positive normal x of the transforms.
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // Sum over the wave, returned in every lane.
 __device__ __forceinline__ double dpp_wave_sum(double x)
 {

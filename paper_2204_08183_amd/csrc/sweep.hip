@@ -45,6 +45,12 @@ using namespace dev;
 #define SW_TRACE(a, b, jj, slot) do { } while (0)
 #endif
 
+// Positions per group of the branch-free transform of k_sweep1.
+#ifndef SS_SW_GROUP
+#define SS_SW_GROUP 8
+#endif
+constexpr int kSwGroup = SS_SW_GROUP;
+
 struct SweepArgs {
     int64_t n;
     int32_t j_begin;
@@ -848,43 +854,76 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
                 for (int c = 0; c < 2; ++c) R[c] = pre[2 + c] - texcl[2 + c];
             }
             const bool has_next = j + 1 < je;
+            // Cox: S0 and S1 at a group of positions first, then the
+            // transform at all of them at once, masked by the event count:
+            // the reciprocals are independent and overlap (one wave per
+            // SIMD here, nothing else hides their latency; run by run
+            // behind a branch each one waited for the last: 8.08 -> 7.22 ms
+            // per 1000 coordinates at N = 1e6).  Fine-Gray holds too many
+            // registers already: the transform stays at the run ends, one
+            // by one (GT = 1; grouped, 12.8 -> 13.0 ms).
+            constexpr int GT = FG ? 1 : (IPT < kSwGroup ? IPT : kSwGroup);
 #pragma unroll
-            for (int i = 0; i < IPT; ++i) {
-                const bool xc = fl[i] & bcur;
-                const bool xn = has_next && (fl[i] & bnext);
-                const double ex = xc ? ev[i] : 0.0;
-                Sr[0] += ev[i];
-                Sr[1] += ex;
-                double ew = 0.0, ewx = 0.0;
-                if (FG) {
-                    ew = ev[i] * wv[i];
-                    ewx = xc ? ew : 0.0;
-                    R[0] -= ew;
-                    R[1] -= ewx;
-                }
-                const int d = dk[i];
-                if (d != 0) {
+            for (int i0 = 0; i0 < IPT; i0 += GT) {
+                double s0v[GT], s1v[GT];
+#pragma unroll
+                for (int u = 0; u < GT; ++u) {
+                    const int i = i0 + u;
+                    const bool xc = fl[i] & bcur;
+                    const bool xn = has_next && (fl[i] & bnext);
+                    const double ex = xc ? ev[i] : 0.0;
+                    Sr[0] += ev[i];
+                    Sr[1] += ex;
+                    double ew = 0.0, ewx = 0.0;
+                    if (FG) {
+                        ew = ev[i] * wv[i];
+                        ewx = xc ? ew : 0.0;
+                        R[0] -= ew;
+                        R[1] -= ewx;
+                    }
                     double S0 = Sr[0], S1 = Sr[1];
                     if (FG) {
                         const double g = s_g[i * BLOCK + tid];
                         S0 += g * R[0];
                         S1 += g * R[1];
                     }
-                    // indicator design: S2 = S1, so H = G
-                    const double Gk = S1 / S0;
-                    const double dd = (double)d;
-                    v[0] += dd * Gk;
-                    v[1] += dd * (Gk - Gk * Gk);
-                    if (a.want_log) v[2] += dd * log(S0);
+                    s0v[u] = S0;
+                    s1v[u] = S1;
+                    // A (all positions) and D (rows of column j) for j+1 on
+                    // the rows of column j+1; the sums over all positions
+                    // are the thread totals of the scan (same terms, same
+                    // order)
+                    v[4] += xn ? ev[i] : 0.0;
+                    v[4 + NT] += xn ? ex : 0.0;
+                    if (FG) {
+                        v[6] += xn ? ew : 0.0;
+                        v[6 + NT] += xn ? ewx : 0.0;
+                    }
                 }
-                // A (all positions) and D (rows of column j) for j+1 on
-                // the rows of column j+1; the sums over all positions are
-                // the thread totals of the scan (same terms, same order)
-                v[4] += xn ? ev[i] : 0.0;
-                v[4 + NT] += xn ? ex : 0.0;
-                if (FG) {
-                    v[6] += xn ? ew : 0.0;
-                    v[6 + NT] += xn ? ewx : 0.0;
+                // indicator design: S2 = S1, so H = G; S0 > 0 everywhere (it
+                // holds e of the position itself or of one before it)
+                if constexpr (FG) {
+                    const int d = dk[i0];
+                    if (d != 0) {
+                        const double Gk = s1v[0] / s0v[0];
+                        const double dd = (double)d;
+                        v[0] += dd * Gk;
+                        v[1] += dd * (Gk - Gk * Gk);
+                        if (a.want_log) v[2] += dd * log(s0v[0]);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < GT; ++u) {
+                        const double Gk = s1v[u] * recip(s0v[u]);
+                        const double dd = (double)dk[i0 + u];  // 0 off the run ends
+                        v[0] = fma(dd, Gk, v[0]);
+                        v[1] = fma(dd, Gk - Gk * Gk, v[1]);
+                    }
+                    if (a.want_log) {
+#pragma unroll
+                        for (int u = 0; u < GT; ++u)
+                            if (dk[i0 + u] != 0) v[2] += (double)dk[i0 + u] * log(s0v[u]);
+                    }
                 }
             }
             v[3] = run[0];
