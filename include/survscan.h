@@ -413,11 +413,10 @@ int32_t ss_beta_gradient(int32_t model, int64_t n, int64_t p,
  * NULL.  At the end eta holds X beta and e = exp(eta) (masked) afresh.
  * One workgroup per replicate, or two (each half of the positions, one
  * exchange per coordinate, cooperative launch) when all of them fit on
- * the device at once (Cox), one per replicate (Fine-Gray: the weighted
- * totals sum e w and sum e w x_j over the replicate are carried from one
- * coordinate to the next in closed form, a pass before the first
- * coordinate sums them); fixed summation order either way (deterministic
- * for a given device).  ws: ss_cv_workspace_bytes(R) bytes, 256-byte aligned,
+ * the device at once; Fine-Gray carries the weighted totals sum e w and
+ * sum e w x_j over the replicate from one coordinate to the next in closed
+ * form (a pass before the first coordinate sums them); fixed summation
+ * order either way (deterministic for a given device).  ws: ss_cv_workspace_bytes(R) bytes, 256-byte aligned,
  * zero-filled before first use (ss_workspace_init), kept between calls; a
  * bounded wait that gives up sets its error word (ss_workspace_error),
  * after which it must be zero-filled again.  Errors: SS_EINVAL for bad

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "lookback.h"
 #include "ss_device.h"
 
 namespace ss {
@@ -42,193 +43,6 @@ using namespace dev;
 #else
 #define SS_TRACE(ws, tile, slot) do { } while (0)
 #endif
-
-// ---------------------------------------------------------------- look-back
-// Decoupled look-back (single-pass chained scan, Sec. 2.6).  A tile's slot
-// holds its NC values as 16-byte (value, tag) pairs, tag = (epoch << 2) |
-// state with state 1 = tile aggregate and 2 = inclusive prefix; the inclusive
-// prefix overwrites the aggregate in place.  Each pair is written and read as
-// one 16-byte access, so a reader that sees all NC tags equal has a
-// consistent snapshot (mixed tags: the slot is being overwritten, not ready
-// yet), and one load brings a predecessor's state and value together: no
-// flag word, no ordering wait on either side.  While the data stream
-// saturates memory a round trip through the coherence point takes ~5 us, and
-// one round trip instead of two (flags, then payloads) took the look-back
-// from 11 to 5 us per tile at N = 2^27.
-//
-// Two levels.  Tiles form groups of kLbGroup = 64; the last tile of a full
-// group also publishes the group's aggregate (as soon as its members'
-// aggregates are visible) and later the group's inclusive prefix (its own).
-// A tile's look-back runs over the sequence: its predecessors in its own
-// group, then whole groups g-1, g-2, ...  With one level the inclusive
-// prefixes advance by at most one window of tiles per round trip, which
-// bounded the whole launch at large N; with groups one round reaches back
-// up to 64 groups.
-//
-// Wave 0 looks back over 64 elements of that sequence per round: one load
-// round trip for a round, the nearest inclusive prefix fixes which elements
-// are needed, and only the needed ones that were not ready are polled
-// again.  Every tile started earlier than its successors (workgroups start
-// in index order on each XCD) and publishes its aggregate without waiting on
-// anyone, and a group's aggregate waits only on its members, so every wait
-// ends; it is bounded all the same.
-constexpr int kLbSlot = 8;     // pairs per tile or group slot (128 bytes)
-#ifndef SS_LB_GROUP
-#define SS_LB_GROUP 64
-#endif
-constexpr int kLbGroup = SS_LB_GROUP;   // tiles per look-back group
-
-// Lanes 0 .. NC-1 of the calling wave store one pair each.
-template <int NC>
-__device__ __forceinline__ void publish_pairs(u32x4 *slot, const double (&v)[NC],
-                                              uint64_t tag)
-{
-    const int lane = lane_id();
-    // the components pass through an empty asm statement: a select chain
-    // over the array itself is folded into an indexed load, which puts the
-    // array in scratch memory
-    double x = v[0];
-#pragma unroll
-    for (int c = 1; c < NC; ++c) {
-        double y = v[c];
-        asm volatile("" : "+v"(y));
-        x = lane == c ? y : x;
-    }
-    if (lane < NC) st_pair(slot + lane, x, tag);
-}
-
-// State of a snapshot of NC pairs: all tags equal and of this launch, else 0.
-template <int NC>
-__device__ __forceinline__ uint32_t pairs_state(const u32x4 (&r)[NC], uint64_t epoch)
-{
-    const uint64_t t0 = pair_tag(r[0]);
-    bool same = (t0 >> 2) == epoch;
-#pragma unroll
-    for (int c = 1; c < NC; ++c) same = same && pair_tag(r[c]) == t0;
-    return same ? (uint32_t)(t0 & 3u) : 0u;
-}
-
-// Wave 0 only; the sum over the look-back sequence of `tile` is added to
-// excl in every lane.  The sequence: tiles tile-1 .. tile-nin (nin tiles of
-// the own group still to be summed), then groups g-1, g-2, ...; before group
-// 0 the sequence ends in an empty inclusive prefix.  Returns false if the
-// wait gave up (the error word is then set).
-template <int NC>
-__device__ bool look_back_seq(const u32x4 *lb, const u32x4 *glb, int32_t tile, int32_t nin,
-                              int32_t g, uint64_t epoch, WsHeader *hdr, double (&excl)[NC],
-                              uint64_t *lb_stats = nullptr)
-{
-    const int lane = lane_id();
-    int32_t base = 0;  // sequence index of lane 0 in this round
-    uint32_t spins = 0;
-    uint32_t rounds = 0, waits = 0;
-    for (;;) {
-        ++rounds;
-        // element base + lane: a tile of the own group, a group, or before
-        // the start (then the lane reads its own tile's slot: one request per
-        // wave, not a shared address every tile would hammer)
-        const int32_t el = base + lane;
-        const int32_t grp = g - 1 - (el - nin);
-        const bool is_tile = el < nin;
-        const bool before = !is_tile && grp < 0;
-        const u32x4 *ptr = is_tile ? lb + (int64_t)(tile - 1 - el) * kLbSlot
-                           : before ? lb + (int64_t)tile * kLbSlot
-                                    : glb + (int64_t)grp * kLbSlot;
-        double val[NC];
-        uint32_t st;
-        {
-            u32x4 r[1][NC];
-            const u32x4 *pp[1] = {ptr};
-            ld_lb<1, NC>(pp, r);
-            st = before ? (uint32_t)kStateInc : pairs_state<NC>(r[0], epoch);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) val[c] = before ? 0.0 : pair_value(r[0][c]);
-        }
-        // nearest inclusive prefix: lowest lane holding one
-        uint64_t m = __ballot(st == kStateInc);
-        int fl = m ? __ffsll((unsigned long long)m) - 1 : kWave;
-        // poll again only the needed elements that were not ready
-        for (;;) {
-            const bool pend = lane <= fl && st == 0u;
-            if (!__any(pend)) break;
-            if (pend) {
-                u32x4 r[NC];
-                ld_pairs<NC>(ptr, r);
-                st = pairs_state<NC>(r, epoch);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) val[c] = pair_value(r[c]);
-            }
-            ++waits;
-            if (++spins > kSpinLimit) {
-                if (lane == 0)
-                    __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                return false;
-            }
-            // an element polled again may now hold its inclusive prefix: the
-            // nearest one can only move closer
-            m = __ballot(st == kStateInc);
-            fl = m ? __ffsll((unsigned long long)m) - 1 : kWave;
-            __builtin_amdgcn_s_sleep(2);
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) excl[c] += wave_sum(lane <= fl ? val[c] : 0.0);
-        if (fl < kWave) break;
-        base += kWave;
-    }
-    if (lb_stats && lane == 0) *lb_stats = ((uint64_t)rounds << 32) | waits;
-    return true;
-}
-
-// Wave 0 of a group's last tile: the sum of its group's other members
-// (tiles tile-1 .. tile-nin, nin < 64) once all are visible, back to the
-// nearest one holding its inclusive prefix if any; returns true in that
-// case (sum is then the tile's whole exclusive prefix).  `ok` is cleared if
-// the wait gave up (the error word is then set).
-template <int NC>
-__device__ bool group_members(const u32x4 *lb, int32_t tile, int32_t nin, uint64_t epoch,
-                              WsHeader *hdr, double (&sum)[NC], bool &ok)
-{
-    const int lane = lane_id();
-    const bool mine = lane < nin;
-    const u32x4 *ptr = lb + (int64_t)(mine ? tile - 1 - lane : tile) * kLbSlot;
-    double val[NC];
-    uint32_t st;
-    {
-        u32x4 r[1][NC];
-        const u32x4 *pp[1] = {ptr};
-        ld_lb<1, NC>(pp, r);
-        st = mine ? pairs_state<NC>(r[0], epoch) : (uint32_t)kStateAgg;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) val[c] = mine ? pair_value(r[0][c]) : 0.0;
-    }
-    uint64_t m = __ballot(st == kStateInc);
-    int fl = m ? __ffsll((unsigned long long)m) - 1 : kWave;
-    uint32_t spins = 0;
-    for (;;) {
-        const bool pend = lane <= fl && st == 0u;
-        if (!__any(pend)) break;
-        if (pend) {
-            u32x4 r[NC];
-            ld_pairs<NC>(ptr, r);
-            st = pairs_state<NC>(r, epoch);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) val[c] = pair_value(r[c]);
-        }
-        if (++spins > kSpinLimit) {
-            if (lane == 0)
-                __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = false;
-            return false;
-        }
-        m = __ballot(st == kStateInc);
-        fl = m ? __ffsll((unsigned long long)m) - 1 : kWave;
-        __builtin_amdgcn_s_sleep(2);
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) sum[c] += wave_sum(lane <= fl ? val[c] : 0.0);
-    return fl < kWave;
-}
 
 // Polls NP pairs until all carry `tag`; false if the wait gave up (then the
 // error word is set) or another wait already did.
