@@ -404,6 +404,26 @@ __device__ __forceinline__ void ld_pairs<5>(const u32x4 *p, u32x4 (&r)[5])
 }
 
 template <>
+__device__ __forceinline__ void ld_pairs<10>(const u32x4 *p, u32x4 (&r)[10])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %10, off sc1\n\t"
+                 "global_load_dwordx4 %1, %10, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %10, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %10, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %10, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %10, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %10, off offset:96 sc1\n\t"
+                 "global_load_dwordx4 %7, %10, off offset:112 sc1\n\t"
+                 "global_load_dwordx4 %8, %10, off offset:128 sc1\n\t"
+                 "global_load_dwordx4 %9, %10, off offset:144 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]), "=&v"(r[7]), "=&v"(r[8]), "=&v"(r[9])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
 __device__ __forceinline__ void ld_pairs<11>(const u32x4 *p, u32x4 (&r)[11])
 {
     asm volatile(
@@ -495,6 +515,60 @@ __device__ __forceinline__ void ld_pairs2<15>(const u32x4 *p, u32x4 (&r0)[15],
                  "global_load_dwordx4 %29, %30, off offset:480 sc1\n\t"
                  "s_waitcnt vmcnt(0)"
                  : "=&v"(r0[0]), "=&v"(r0[1]), "=&v"(r0[2]), "=&v"(r0[3]), "=&v"(r0[4]), "=&v"(r0[5]), "=&v"(r0[6]), "=&v"(r0[7]), "=&v"(r0[8]), "=&v"(r0[9]), "=&v"(r0[10]), "=&v"(r0[11]), "=&v"(r0[12]), "=&v"(r0[13]), "=&v"(r0[14]), "=&v"(r1[0]), "=&v"(r1[1]), "=&v"(r1[2]), "=&v"(r1[3]), "=&v"(r1[4]), "=&v"(r1[5]), "=&v"(r1[6]), "=&v"(r1[7]), "=&v"(r1[8]), "=&v"(r1[9]), "=&v"(r1[10]), "=&v"(r1[11]), "=&v"(r1[12]), "=&v"(r1[13]), "=&v"(r1[14])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs2<6>(const u32x4 *p, u32x4 (&r0)[6],
+                                               u32x4 (&r1)[6])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %12, off sc1\n\t"
+                 "global_load_dwordx4 %1, %12, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %12, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %12, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %12, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %12, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %12, off offset:256 sc1\n\t"
+                 "global_load_dwordx4 %7, %12, off offset:272 sc1\n\t"
+                 "global_load_dwordx4 %8, %12, off offset:288 sc1\n\t"
+                 "global_load_dwordx4 %9, %12, off offset:304 sc1\n\t"
+                 "global_load_dwordx4 %10, %12, off offset:320 sc1\n\t"
+                 "global_load_dwordx4 %11, %12, off offset:336 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r0[0]), "=&v"(r0[1]), "=&v"(r0[2]), "=&v"(r0[3]), "=&v"(r0[4]), "=&v"(r0[5]), "=&v"(r1[0]), "=&v"(r1[1]), "=&v"(r1[2]), "=&v"(r1[3]), "=&v"(r1[4]), "=&v"(r1[5])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs2<10>(const u32x4 *p, u32x4 (&r0)[10],
+                                               u32x4 (&r1)[10])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %20, off sc1\n\t"
+                 "global_load_dwordx4 %1, %20, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %20, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %20, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %20, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %20, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %20, off offset:96 sc1\n\t"
+                 "global_load_dwordx4 %7, %20, off offset:112 sc1\n\t"
+                 "global_load_dwordx4 %8, %20, off offset:128 sc1\n\t"
+                 "global_load_dwordx4 %9, %20, off offset:144 sc1\n\t"
+                 "global_load_dwordx4 %10, %20, off offset:256 sc1\n\t"
+                 "global_load_dwordx4 %11, %20, off offset:272 sc1\n\t"
+                 "global_load_dwordx4 %12, %20, off offset:288 sc1\n\t"
+                 "global_load_dwordx4 %13, %20, off offset:304 sc1\n\t"
+                 "global_load_dwordx4 %14, %20, off offset:320 sc1\n\t"
+                 "global_load_dwordx4 %15, %20, off offset:336 sc1\n\t"
+                 "global_load_dwordx4 %16, %20, off offset:352 sc1\n\t"
+                 "global_load_dwordx4 %17, %20, off offset:368 sc1\n\t"
+                 "global_load_dwordx4 %18, %20, off offset:384 sc1\n\t"
+                 "global_load_dwordx4 %19, %20, off offset:400 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r0[0]), "=&v"(r0[1]), "=&v"(r0[2]), "=&v"(r0[3]), "=&v"(r0[4]), "=&v"(r0[5]), "=&v"(r0[6]), "=&v"(r0[7]), "=&v"(r0[8]), "=&v"(r0[9]), "=&v"(r1[0]), "=&v"(r1[1]), "=&v"(r1[2]), "=&v"(r1[3]), "=&v"(r1[4]), "=&v"(r1[5]), "=&v"(r1[6]), "=&v"(r1[7]), "=&v"(r1[8]), "=&v"(r1[9])
                  : "v"(p)
                  : "memory");
 }

@@ -520,7 +520,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a)
 // delta_j are read before publishing round j, and workgroup 0 writes beta_j
 // and delta_j only after it has read every publication of that round, so
 // no workgroup can see the updated values for the same coordinate.
-template <int BLOCK, int IPT, int MODEL>
+template <int BLOCK, int IPT, int MODEL, bool LOG>
 __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
 {
     constexpr int S = BLOCK * IPT;
@@ -529,10 +529,13 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
     // (e, e x, e w, e w x) for Fine-Gray.
     constexpr int NT = FG ? 4 : 2;
     constexpr int NW = BLOCK / kWave;
-    constexpr int NPUB = 3 + 2 * NT;  // partial sums, A, D
-    // block sums after a gather: partials (3), A and D before this segment
-    // (2 NT), and for Fine-Gray the totals of the weighted A and D (4)
-    constexpr int NSUM = 3 + 2 * NT + (FG ? 4 : 0);
+    // partial sums: sum d G, sum d (G - G^2) and, with LOG, sum d log S0
+    constexpr int P0 = LOG ? 3 : 2;
+    constexpr int NPUB = P0 + 2 * NT;  // partial sums, A, D
+    // block sums after a gather: partials (P0), A and D before this
+    // segment (2 NT), and for Fine-Gray the totals of the weighted A and D
+    // (4)
+    constexpr int NSUM = P0 + 2 * NT + (FG ? 4 : 0);
     constexpr int K = (kMaxSweepBlocks + BLOCK - 1) / BLOCK;
     static_assert(K <= 2, "at most two segments per thread in a gather");
     static_assert(S % SS_CHUNK == 0, "segment must be whole chunks");
@@ -707,15 +710,15 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
         for (int k = 0; k < K; ++k) {
             const bool before = q0 + k < b;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) t[c] += v[k][c];
+            for (int c = 0; c < P0; ++c) t[c] += v[k][c];
 #pragma unroll
-            for (int c = 0; c < 2 * NT; ++c) t[3 + c] += before ? v[k][3 + c] : 0.0;
+            for (int c = 0; c < 2 * NT; ++c) t[P0 + c] += before ? v[k][P0 + c] : 0.0;
             if (FG) {
                 // weighted components of A (indices 2, 3) and D (2, 3), all segments
-                t[3 + 2 * NT + 0] += v[k][3 + 2];
-                t[3 + 2 * NT + 1] += v[k][3 + 3];
-                t[3 + 2 * NT + 2] += v[k][3 + NT + 2];
-                t[3 + 2 * NT + 3] += v[k][3 + NT + 3];
+                t[P0 + 2 * NT + 0] += v[k][P0 + 2];
+                t[P0 + 2 * NT + 1] += v[k][P0 + 3];
+                t[P0 + 2 * NT + 2] += v[k][P0 + NT + 2];
+                t[P0 + 2 * NT + 3] += v[k][P0 + NT + 3];
             }
         }
         const int par = (int)(r & 1u);
@@ -739,11 +742,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
     auto prefix_from = [&](const double (&sm)[NSUM], double st, double (&pre)[NT]) {
         const double f = expm1(st);
 #pragma unroll
-        for (int c = 0; c < NT; ++c) pre[c] = sm[3 + c] + f * sm[3 + NT + c];
+        for (int c = 0; c < NT; ++c) pre[c] = sm[P0 + c] + f * sm[P0 + NT + c];
         if (FG) {
 #pragma unroll
             for (int c = 2; c < 4; ++c) {
-                const double tot = sm[3 + 2 * NT + (c - 2)] + f * sm[3 + 2 * NT + 2 + (c - 2)];
+                const double tot = sm[P0 + 2 * NT + (c - 2)] + f * sm[P0 + 2 * NT + 2 + (c - 2)];
                 pre[c] = tot - pre[c];
             }
         }
@@ -763,12 +766,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
         const uint8_t bj = (uint8_t)(1u << (jb % 3));
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-            v[3] += ev[i];
-            v[4] += (fl[i] & bj) ? ev[i] : 0.0;
+            v[P0] += ev[i];
+            v[P0 + 1] += (fl[i] & bj) ? ev[i] : 0.0;
             if (FG) {
                 const double ew = ev[i] * wv[i];
-                v[5] += ew;
-                v[6] += (fl[i] & bj) ? ew : 0.0;
+                v[P0 + 2] += ew;
+                v[P0 + 3] += (fl[i] & bj) ? ew : 0.0;
             }
         }
         const uint64_t tag = (ep0 << 1) | 1u;
@@ -893,11 +896,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
                     // the rows of column j+1; the sums over all positions
                     // are the thread totals of the scan (same terms, same
                     // order)
-                    v[4] += xn ? ev[i] : 0.0;
-                    v[4 + NT] += xn ? ex : 0.0;
+                    v[P0 + 1] += xn ? ev[i] : 0.0;
+                    v[P0 + 1 + NT] += xn ? ex : 0.0;
                     if (FG) {
-                        v[6] += xn ? ew : 0.0;
-                        v[6 + NT] += xn ? ewx : 0.0;
+                        v[P0 + 3] += xn ? ew : 0.0;
+                        v[P0 + 3 + NT] += xn ? ewx : 0.0;
                     }
                 }
                 // indicator design: S2 = S1, so H = G; S0 > 0 everywhere (it
@@ -909,7 +912,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
                         const double dd = (double)d;
                         v[0] += dd * Gk;
                         v[1] += dd * (Gk - Gk * Gk);
-                        if (a.want_log) v[2] += dd * log(s0v[0]);
+                        if constexpr (LOG) v[2] += dd * log(s0v[0]);
                     }
                 } else {
 #pragma unroll
@@ -919,18 +922,18 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
                         v[0] = fma(dd, Gk, v[0]);
                         v[1] = fma(dd, Gk - Gk * Gk, v[1]);
                     }
-                    if (a.want_log) {
+                    if constexpr (LOG) {
 #pragma unroll
                         for (int u = 0; u < GT; ++u)
                             if (dk[i0 + u] != 0) v[2] += (double)dk[i0 + u] * log(s0v[u]);
                     }
                 }
             }
-            v[3] = run[0];
-            v[3 + NT] = run[1];
+            v[P0] = run[0];
+            v[P0 + NT] = run[1];
             if (FG) {
-                v[5] = run[2];
-                v[5 + NT] = run[3];
+                v[P0 + 2] = run[2];
+                v[P0 + 2 + NT] = run[3];
             }
         }
         publish(v, r, tag);
@@ -953,7 +956,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
                 if (a.g12_out) {
                     a.g12_out[3 * j] = g1;
                     a.g12_out[3 * j + 1] = g2;
-                    a.g12_out[3 * j + 2] = sm[2];
+                    a.g12_out[3 * j + 2] = LOG ? sm[2] : 0.0;
                 }
             }
         }
@@ -998,30 +1001,32 @@ void *kernel_ptr()
 }
 
 template <int BLOCK, int IPT, int MODEL>
-void *kernel1_ptr()
+void *kernel1_ptr(bool log)
 {
-    return reinterpret_cast<void *>(&k_sweep1<BLOCK, IPT, MODEL>);
+    return log ? reinterpret_cast<void *>(&k_sweep1<BLOCK, IPT, MODEL, true>)
+               : reinterpret_cast<void *>(&k_sweep1<BLOCK, IPT, MODEL, false>);
 }
 
 // Indicator designs take the one-exchange kernel, valued ones the general.
+// (the one-exchange kernel publishes sum d log S0 only when it is asked for)
 template <int BLOCK, int IPT>
-void *pick_kernel(int model, bool vals)
+void *pick_kernel(int model, bool vals, bool log)
 {
     if (model == SS_FINE_GRAY)
         return vals ? kernel_ptr<BLOCK, IPT, SS_FINE_GRAY, true>()
-                    : kernel1_ptr<BLOCK, IPT, SS_FINE_GRAY>();
-    return vals ? kernel_ptr<BLOCK, IPT, SS_COX, true>() : kernel1_ptr<BLOCK, IPT, SS_COX>();
+                    : kernel1_ptr<BLOCK, IPT, SS_FINE_GRAY>(log);
+    return vals ? kernel_ptr<BLOCK, IPT, SS_COX, true>() : kernel1_ptr<BLOCK, IPT, SS_COX>(log);
 }
 
-void *kernel_for(int block, int ipt, int model, bool vals)
+void *kernel_for(int block, int ipt, int model, bool vals, bool log)
 {
-    if (block == 256 && ipt == 8) return pick_kernel<256, 8>(model, vals);
-    if (block == 256 && ipt == 16) return pick_kernel<256, 16>(model, vals);
-    if (block == 512 && ipt == 8) return pick_kernel<512, 8>(model, vals);
+    if (block == 256 && ipt == 8) return pick_kernel<256, 8>(model, vals, log);
+    if (block == 256 && ipt == 16) return pick_kernel<256, 16>(model, vals, log);
+    if (block == 512 && ipt == 8) return pick_kernel<512, 8>(model, vals, log);
     // 8192-position segments: Cox only (Fine-Gray would not fit its LDS or
     // would spill registers)
     if (block == 512 && ipt == 16 && model == SS_COX)
-        return vals ? kernel_ptr<512, 16, SS_COX, true>() : kernel1_ptr<512, 16, SS_COX>();
+        return vals ? kernel_ptr<512, 16, SS_COX, true>() : kernel1_ptr<512, 16, SS_COX>(log);
     return nullptr;
 }
 
@@ -1060,7 +1065,7 @@ int32_t launch_sweep_persistent(const SweepCall &call, const WsView &ws, hipStre
         // a few hundred segments at most: the all-to-all exchange reads G
         // aggregates per workgroup
         if (G > kMaxSweepBlocks || G > ws.max_tiles) continue;
-        void *k = kernel_for(sh.block, sh.ipt, call.model, vals);
+        void *k = kernel_for(sh.block, sh.ipt, call.model, vals, call.g12_out != nullptr);
         if (!k) continue;
         int per_cu = 0;
         SS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, sh.block, 0));

@@ -398,6 +398,14 @@ def test_sweep_deterministic_and_consistent(model, monkeypatch):
         assert prob.workspace_error() == 0
     for a_, b_ in zip(outs[0], outs[1]):
         np.testing.assert_array_equal(a_, b_)
+    # without g12_out the sweep does not form or exchange sum d log S0 (a
+    # kernel of its own): the same coefficients and e, bit for bit
+    prob = gpu_problem(model, c)
+    prob.sweep("l1", 0.5)
+    prob.sweep("l1", 0.5)
+    np.testing.assert_array_equal(prob.beta.cpu().numpy(), outs[0][1])
+    np.testing.assert_array_equal(prob.e.cpu().numpy(), outs[0][2])
+    assert prob.workspace_error() == 0
 
 
 @pytest.mark.parametrize("model", ["cox", "fg"])
