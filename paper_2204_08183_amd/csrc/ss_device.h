@@ -263,6 +263,13 @@ __device__ __forceinline__ void st_pair(u32x4 *p, double v, uint64_t tag)
                  : : "v"(p), "v"(val) : "memory");
 }
 
+// One 16-byte word, stored as st_pair stores a pair.
+__device__ __forceinline__ void st_quad(u32x4 *p, u32x4 val)
+{
+    asm volatile("global_store_dwordx4 %0, %1, off sc1\n\ts_nop 4"
+                 : : "v"(p), "v"(val) : "memory");
+}
+
 // Loads NP consecutive pairs and waits for them (one statement, so the
 // compiler cannot touch the destination registers before the wait).
 template <int NP>
@@ -341,6 +348,24 @@ __device__ __forceinline__ void ld_pairs<7>(const u32x4 *p, u32x4 (&r)[7])
                  "global_load_dwordx4 %6, %7, off offset:96 sc1\n\t"
                  "s_waitcnt vmcnt(0)"
                  : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs<8>(const u32x4 *p, u32x4 (&r)[8])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %8, off sc1\n\t"
+                 "global_load_dwordx4 %1, %8, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %8, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %8, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %8, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %8, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %8, off offset:96 sc1\n\t"
+                 "global_load_dwordx4 %7, %8, off offset:112 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]), "=&v"(r[7])
                  : "v"(p)
                  : "memory");
 }
@@ -515,6 +540,73 @@ __device__ __forceinline__ void ld_pairs2<15>(const u32x4 *p, u32x4 (&r0)[15],
                  "global_load_dwordx4 %29, %30, off offset:480 sc1\n\t"
                  "s_waitcnt vmcnt(0)"
                  : "=&v"(r0[0]), "=&v"(r0[1]), "=&v"(r0[2]), "=&v"(r0[3]), "=&v"(r0[4]), "=&v"(r0[5]), "=&v"(r0[6]), "=&v"(r0[7]), "=&v"(r0[8]), "=&v"(r0[9]), "=&v"(r0[10]), "=&v"(r0[11]), "=&v"(r0[12]), "=&v"(r0[13]), "=&v"(r0[14]), "=&v"(r1[0]), "=&v"(r1[1]), "=&v"(r1[2]), "=&v"(r1[3]), "=&v"(r1[4]), "=&v"(r1[5]), "=&v"(r1[6]), "=&v"(r1[7]), "=&v"(r1[8]), "=&v"(r1[9]), "=&v"(r1[10]), "=&v"(r1[11]), "=&v"(r1[12]), "=&v"(r1[13]), "=&v"(r1[14])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs2<4>(const u32x4 *p, u32x4 (&r0)[4],
+                                               u32x4 (&r1)[4])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %8, off sc1\n\t"
+                 "global_load_dwordx4 %1, %8, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %8, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %8, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %8, off offset:256 sc1\n\t"
+                 "global_load_dwordx4 %5, %8, off offset:272 sc1\n\t"
+                 "global_load_dwordx4 %6, %8, off offset:288 sc1\n\t"
+                 "global_load_dwordx4 %7, %8, off offset:304 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r0[0]), "=&v"(r0[1]), "=&v"(r0[2]), "=&v"(r0[3]), "=&v"(r1[0]), "=&v"(r1[1]), "=&v"(r1[2]), "=&v"(r1[3])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs2<5>(const u32x4 *p, u32x4 (&r0)[5],
+                                               u32x4 (&r1)[5])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %10, off sc1\n\t"
+                 "global_load_dwordx4 %1, %10, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %10, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %10, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %10, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %10, off offset:256 sc1\n\t"
+                 "global_load_dwordx4 %6, %10, off offset:272 sc1\n\t"
+                 "global_load_dwordx4 %7, %10, off offset:288 sc1\n\t"
+                 "global_load_dwordx4 %8, %10, off offset:304 sc1\n\t"
+                 "global_load_dwordx4 %9, %10, off offset:320 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r0[0]), "=&v"(r0[1]), "=&v"(r0[2]), "=&v"(r0[3]), "=&v"(r0[4]), "=&v"(r1[0]), "=&v"(r1[1]), "=&v"(r1[2]), "=&v"(r1[3]), "=&v"(r1[4])
+                 : "v"(p)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void ld_pairs2<8>(const u32x4 *p, u32x4 (&r0)[8],
+                                               u32x4 (&r1)[8])
+{
+    asm volatile(
+                 "global_load_dwordx4 %0, %16, off sc1\n\t"
+                 "global_load_dwordx4 %1, %16, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %16, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %16, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %16, off offset:64 sc1\n\t"
+                 "global_load_dwordx4 %5, %16, off offset:80 sc1\n\t"
+                 "global_load_dwordx4 %6, %16, off offset:96 sc1\n\t"
+                 "global_load_dwordx4 %7, %16, off offset:112 sc1\n\t"
+                 "global_load_dwordx4 %8, %16, off offset:256 sc1\n\t"
+                 "global_load_dwordx4 %9, %16, off offset:272 sc1\n\t"
+                 "global_load_dwordx4 %10, %16, off offset:288 sc1\n\t"
+                 "global_load_dwordx4 %11, %16, off offset:304 sc1\n\t"
+                 "global_load_dwordx4 %12, %16, off offset:320 sc1\n\t"
+                 "global_load_dwordx4 %13, %16, off offset:336 sc1\n\t"
+                 "global_load_dwordx4 %14, %16, off offset:352 sc1\n\t"
+                 "global_load_dwordx4 %15, %16, off offset:368 sc1\n\t"
+                 "s_waitcnt vmcnt(0)"
+                 : "=&v"(r0[0]), "=&v"(r0[1]), "=&v"(r0[2]), "=&v"(r0[3]), "=&v"(r0[4]), "=&v"(r0[5]), "=&v"(r0[6]), "=&v"(r0[7]), "=&v"(r1[0]), "=&v"(r1[1]), "=&v"(r1[2]), "=&v"(r1[3]), "=&v"(r1[4]), "=&v"(r1[5]), "=&v"(r1[6]), "=&v"(r1[7])
                  : "v"(p)
                  : "memory");
 }

@@ -51,6 +51,88 @@ using namespace dev;
 #endif
 constexpr int kSwGroup = SS_SW_GROUP;
 
+// A publication of N doubles packs three doubles into two 16-byte words,
+// each word carrying the low 32 bits of the round's tag in its last dword:
+// every word is written and read with one 16-byte access, so a reader that
+// sees the tag in all of them has a consistent snapshot, and the words per
+// publication drop from N to about 2N/3 (the gather reads every segment's
+// publication each round; its time goes with the bytes).  Tags repeat only
+// after 2^31 rounds, long after a slot was last overwritten.
+template <int N>
+constexpr int pub_words()
+{
+    return (N / 3) * 2 + (N % 3 == 0 ? 0 : (N % 3 == 1 ? 1 : 2));
+}
+
+__device__ __forceinline__ uint32_t lo32(double v)
+{
+    return (uint32_t)(unsigned long long)__double_as_longlong(v);
+}
+__device__ __forceinline__ uint32_t hi32(double v)
+{
+    return (uint32_t)((unsigned long long)__double_as_longlong(v) >> 32);
+}
+__device__ __forceinline__ double from32(uint32_t lo, uint32_t hi)
+{
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int N>
+__device__ __forceinline__ void pub_pack(const double (&v)[N], uint32_t tag,
+                                         u32x4 (&q)[pub_words<N>()])
+{
+    constexpr int G = N / 3, R = N % 3;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const double d0 = v[3 * g], d1 = v[3 * g + 1], d2 = v[3 * g + 2];
+        q[2 * g].x = lo32(d0);
+        q[2 * g].y = hi32(d0);
+        q[2 * g].z = lo32(d1);
+        q[2 * g].w = tag;
+        q[2 * g + 1].x = hi32(d1);
+        q[2 * g + 1].y = lo32(d2);
+        q[2 * g + 1].z = hi32(d2);
+        q[2 * g + 1].w = tag;
+    }
+    if constexpr (R >= 1) {
+        const double d0 = v[3 * G];
+        const double d1 = R == 2 ? v[3 * G + (R == 2 ? 1 : 0)] : 0.0;
+        q[2 * G].x = lo32(d0);
+        q[2 * G].y = hi32(d0);
+        q[2 * G].z = lo32(d1);
+        q[2 * G].w = tag;
+        if constexpr (R == 2) {
+            q[2 * G + 1].x = hi32(d1);
+            q[2 * G + 1].y = 0u;
+            q[2 * G + 1].z = 0u;
+            q[2 * G + 1].w = tag;
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void pub_unpack(const u32x4 (&q)[pub_words<N>()], double (&v)[N])
+{
+    constexpr int G = N / 3, R = N % 3;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        v[3 * g] = from32(q[2 * g].x, q[2 * g].y);
+        v[3 * g + 1] = from32(q[2 * g].z, q[2 * g + 1].x);
+        v[3 * g + 2] = from32(q[2 * g + 1].y, q[2 * g + 1].z);
+    }
+    if constexpr (R >= 1) v[3 * G] = from32(q[2 * G].x, q[2 * G].y);
+    if constexpr (R == 2) v[3 * G + 1] = from32(q[2 * G].z, q[2 * G + 1].x);
+}
+
+template <int M>
+__device__ __forceinline__ bool pub_tagged(const u32x4 (&q)[M], uint32_t tag)
+{
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < M; ++c) ok = ok && q[c].w == tag;
+    return ok;
+}
+
 struct SweepArgs {
     int64_t n;
     int32_t j_begin;
@@ -532,6 +614,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
     // partial sums: sum d G, sum d (G - G^2) and, with LOG, sum d log S0
     constexpr int P0 = LOG ? 3 : 2;
     constexpr int NPUB = P0 + 2 * NT;  // partial sums, A, D
+    constexpr int NQ = pub_words<NPUB>();  // 16-byte words of a publication
     // block sums after a gather: partials (P0), A and D before this
     // segment (2 NT), and for Fine-Gray the totals of the weighted A and D
     // (4)
@@ -646,13 +729,17 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
         __syncthreads();
         if (tid == 0) {
             u32x4 *dst = pub_slot(r, b);
+            double t[NPUB];
 #pragma unroll
             for (int c = 0; c < NPUB; ++c) {
-                double t = 0.0;
+                t[c] = 0.0;
 #pragma unroll
-                for (int q = 0; q < NW; ++q) t += s_wred[q][c];
-                st_pair(dst + c, t, tag);
+                for (int q = 0; q < NW; ++q) t[c] += s_wred[q][c];
             }
+            u32x4 wd[NQ];
+            pub_pack<NPUB>(t, (uint32_t)tag, wd);
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) st_quad(dst + c, wd[c]);
         }
     };
     // Reads every segment's publication of round r and forms the sums in a
@@ -669,15 +756,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
         bool bad = false;
         const int q0 = tid * K;  // segments q0 .. q0 + K - 1
         if (K == 2 && q0 + 1 < G) {
-            u32x4 r0[NPUB], r1[NPUB];
+            u32x4 r0[NQ], r1[NQ];
             uint32_t spins = 0;
             for (;;) {
-                ld_pairs2<NPUB>(pub_slot(r, q0), r0, r1);
-                bool ok = true;
-#pragma unroll
-                for (int c = 0; c < NPUB; ++c)
-                    ok = ok && pair_tag(r0[c]) == tag && pair_tag(r1[c]) == tag;
-                if (ok) break;
+                ld_pairs2<NQ>(pub_slot(r, q0), r0, r1);
+                if (pub_tagged<NQ>(r0, (uint32_t)tag) && pub_tagged<NQ>(r1, (uint32_t)tag))
+                    break;
                 if (((++spins & 31u) == 0 && ld_relaxed_u32(&hdr->error)) ||
                     spins > kSpinLimit) {
                     __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED,
@@ -688,19 +772,26 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
                 __builtin_amdgcn_s_sleep(1);
             }
             if (!bad) {
-#pragma unroll
-                for (int c = 0; c < NPUB; ++c) {
-                    v[0][c] = pair_value(r0[c]);
-                    v[K - 1][c] = pair_value(r1[c]);
-                }
+                pub_unpack<NPUB>(r0, v[0]);
+                pub_unpack<NPUB>(r1, v[K - 1]);
             }
         } else if (q0 < G) {
-            u32x4 rr[NPUB];
-            if (wait_pairs<NPUB>(pub_slot(r, q0), tag, hdr, rr)) {
-#pragma unroll
-                for (int c = 0; c < NPUB; ++c) v[0][c] = pair_value(rr[c]);
-            } else {
-                bad = true;
+            u32x4 rr[NQ];
+            uint32_t spins = 0;
+            for (;;) {
+                ld_pairs<NQ>(pub_slot(r, q0), rr);
+                if (pub_tagged<NQ>(rr, (uint32_t)tag)) {
+                    pub_unpack<NPUB>(rr, v[0]);
+                    break;
+                }
+                if (((++spins & 31u) == 0 && ld_relaxed_u32(&hdr->error)) ||
+                    spins > kSpinLimit) {
+                    __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    bad = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
             }
         }
         double t[NSUM];
