@@ -44,19 +44,22 @@ using namespace dev;
 #define SS_TRACE(ws, tile, slot) do { } while (0)
 #endif
 
-// Polls NP pairs until all carry `tag`; false if the wait gave up (then the
+// Polls a publication of NV packed values (publish_pairs) until all its
+// words carry `tag`, then unpacks them; false if the wait gave up (then the
 // error word is set) or another wait already did.
-template <int NP>
+template <int NV>
 __device__ __forceinline__ bool poll_pairs(const u32x4 *p, uint64_t tag, WsHeader *hdr,
-                                           u32x4 (&r)[NP])
+                                           double (&v)[NV])
 {
+    constexpr int NQ = pub_words<NV>();
     uint32_t spins = 0;
     for (;;) {
-        ld_pairs<NP>(p, r);
-        bool ok = true;
-#pragma unroll
-        for (int c = 0; c < NP; ++c) ok = ok && pair_tag(r[c]) == tag;
-        if (ok) return true;
+        u32x4 r[NQ];
+        ld_pairs<NQ>(p, r);
+        if (pub_tagged<NQ>(r, (uint32_t)tag)) {
+            pub_unpack<NV>(r, v);
+            return true;
+        }
         if (++spins > kSpinLimit || ((spins & 31u) == 0 && ld_relaxed_u32(&hdr->error))) {
             __hip_atomic_store(&hdr->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
@@ -68,7 +71,7 @@ __device__ __forceinline__ bool poll_pairs(const u32x4 *p, uint64_t tag, WsHeade
 // ------------------------------------------------------ partial sums
 // Two-level reduction of the per-tile partial sums, in a fixed order (so
 // the result does not depend on timing): every tile publishes its NR sums
-// as pairs (slots of SLOT pairs); the last tile of each group of kGroup
+// as packed words (slots of SLOT words); the last tile of each group of kGroup
 // tiles waits for its group (wave 0, one tile per lane) and publishes the
 // group's sums; the last tile of the launch waits for the groups and adds
 // them.  Only tiles with smaller indices are ever waited for.
@@ -99,10 +102,10 @@ __device__ void reduce_partials(u32x4 *part, u32x4 *gpart, int64_t tile, int64_t
 #pragma unroll
             for (int c = 0; c < NR; ++c) v[c] = 0.0;
             if (t < tile) {
-                u32x4 r[NR];
+                double r[NR];
                 if (poll_pairs<NR>(part + t * SLOT, tag, hdr, r)) {
 #pragma unroll
-                    for (int c = 0; c < NR; ++c) v[c] = pair_value(r[c]);
+                    for (int c = 0; c < NR; ++c) v[c] = r[c];
                 }
             } else if (t == tile) {
 #pragma unroll
@@ -126,10 +129,10 @@ __device__ void reduce_partials(u32x4 *part, u32x4 *gpart, int64_t tile, int64_t
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0.0;
     for (int64_t q = tid; q < ngroups - 1; q += BLOCK) {
-        u32x4 r[NR];
+        double r[NR];
         if (!poll_pairs<NR>(gpart + q * SLOT, tag, hdr, r)) break;
 #pragma unroll
-        for (int c = 0; c < NR; ++c) acc[c] += pair_value(r[c]);
+        for (int c = 0; c < NR; ++c) acc[c] += r[c];
     }
     double own[NR];
 #pragma unroll

@@ -10,13 +10,14 @@ namespace dev {
 
 // ---------------------------------------------------------------- look-back
 // Decoupled look-back (single-pass chained scan, Sec. 2.6).  A tile's slot
-// holds its NC values as 16-byte (value, tag) pairs, tag = (epoch << 2) |
-// state with state 1 = tile aggregate and 2 = inclusive prefix; the inclusive
-// prefix overwrites the aggregate in place.  Each pair is written and read as
-// one 16-byte access, so a reader that sees all NC tags equal has a
-// consistent snapshot (mixed tags: the slot is being overwritten, not ready
-// yet), and one load brings a predecessor's state and value together: no
-// flag word, no ordering wait on either side.  While the data stream
+// holds its NC values packed into 16-byte words (three doubles per two
+// words, ss_device.h), each word tagged with the low 32 bits of
+// (epoch << 2) | state, state 1 = tile aggregate and 2 = inclusive prefix;
+// the inclusive prefix overwrites the aggregate in place.  Each word is
+// written and read as one 16-byte access, so a reader that sees all tags
+// equal has a consistent snapshot (mixed tags: the slot is being
+// overwritten, not ready yet), and one load brings a predecessor's state and
+// value together: no flag word, no ordering wait on either side.  While the data stream
 // saturates memory a round trip through the coherence point takes ~5 us, and
 // one round trip instead of two (flags, then payloads) took the look-back
 // from 11 to 5 us per tile at N = 2^27.
@@ -43,34 +44,39 @@ constexpr int kLbSlot = 8;     // pairs per tile or group slot (128 bytes)
 #endif
 constexpr int kLbGroup = SS_LB_GROUP;   // tiles per look-back group
 
-// Lanes 0 .. NC-1 of the calling wave store one pair each.
+// The NC values packed into pub_words<NC>() words (ss_device.h) under the
+// low 32 bits of tag; lane q of the calling wave stores word q.
 template <int NC>
 __device__ __forceinline__ void publish_pairs(u32x4 *slot, const double (&v)[NC],
                                               uint64_t tag)
 {
+    constexpr int NQ = pub_words<NC>();
     const int lane = lane_id();
-    // the components pass through an empty asm statement: a select chain
-    // over the array itself is folded into an indexed load, which puts the
-    // array in scratch memory
-    double x = v[0];
+    u32x4 q[NQ];
+    pub_pack<NC>(v, (uint32_t)tag, q);
+    // the words pass through an empty asm statement: a select chain over
+    // the array itself is folded into an indexed load, which puts the array
+    // in scratch memory
+    u32x4 x = q[0];
 #pragma unroll
-    for (int c = 1; c < NC; ++c) {
-        double y = v[c];
+    for (int c = 1; c < NQ; ++c) {
+        u32x4 y = q[c];
         asm volatile("" : "+v"(y));
         x = lane == c ? y : x;
     }
-    if (lane < NC) st_pair(slot + lane, x, tag);
+    if (lane < NQ) st_quad(slot + lane, x);
 }
 
-// State of a snapshot of NC pairs: all tags equal and of this launch, else 0.
-template <int NC>
-__device__ __forceinline__ uint32_t pairs_state(const u32x4 (&r)[NC], uint64_t epoch)
+// State of a snapshot of NQ words: all tags equal and of this launch (the
+// low 30 bits of the epoch), else 0.
+template <int NQ>
+__device__ __forceinline__ uint32_t pairs_state(const u32x4 (&r)[NQ], uint64_t epoch)
 {
-    const uint64_t t0 = pair_tag(r[0]);
-    bool same = (t0 >> 2) == epoch;
+    const uint32_t t0 = r[0].w;
+    bool same = (t0 >> 2) == ((uint32_t)epoch & 0x3fffffffu);
 #pragma unroll
-    for (int c = 1; c < NC; ++c) same = same && pair_tag(r[c]) == t0;
-    return same ? (uint32_t)(t0 & 3u) : 0u;
+    for (int c = 1; c < NQ; ++c) same = same && r[c].w == t0;
+    return same ? (t0 & 3u) : 0u;
 }
 
 // Wave 0 only; the sum over the look-back sequence of `tile` is added to
@@ -83,6 +89,7 @@ __device__ bool look_back_seq(const u32x4 *lb, const u32x4 *glb, int32_t tile, i
                               int32_t g, uint64_t epoch, WsHeader *hdr, double (&excl)[NC],
                               uint64_t *lb_stats = nullptr)
 {
+    constexpr int NQ = pub_words<NC>();
     const int lane = lane_id();
     int32_t base = 0;  // sequence index of lane 0 in this round
     uint32_t spins = 0;
@@ -102,12 +109,13 @@ __device__ bool look_back_seq(const u32x4 *lb, const u32x4 *glb, int32_t tile, i
         double val[NC];
         uint32_t st;
         {
-            u32x4 r[1][NC];
+            u32x4 r[1][NQ];
             const u32x4 *pp[1] = {ptr};
-            ld_lb<1, NC>(pp, r);
-            st = before ? (uint32_t)kStateInc : pairs_state<NC>(r[0], epoch);
+            ld_lb<1, NQ>(pp, r);
+            st = before ? (uint32_t)kStateInc : pairs_state<NQ>(r[0], epoch);
+            pub_unpack<NC>(r[0], val);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) val[c] = before ? 0.0 : pair_value(r[0][c]);
+            for (int c = 0; c < NC; ++c) val[c] = before ? 0.0 : val[c];
         }
         // nearest inclusive prefix: lowest lane holding one
         uint64_t m = __ballot(st == kStateInc);
@@ -117,11 +125,10 @@ __device__ bool look_back_seq(const u32x4 *lb, const u32x4 *glb, int32_t tile, i
             const bool pend = lane <= fl && st == 0u;
             if (!__any(pend)) break;
             if (pend) {
-                u32x4 r[NC];
-                ld_pairs<NC>(ptr, r);
-                st = pairs_state<NC>(r, epoch);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) val[c] = pair_value(r[c]);
+                u32x4 r[NQ];
+                ld_pairs<NQ>(ptr, r);
+                st = pairs_state<NQ>(r, epoch);
+                pub_unpack<NC>(r, val);
             }
             ++waits;
             if (++spins > kSpinLimit) {
@@ -154,18 +161,20 @@ template <int NC>
 __device__ bool group_members(const u32x4 *lb, int32_t tile, int32_t nin, uint64_t epoch,
                               WsHeader *hdr, double (&sum)[NC], bool &ok)
 {
+    constexpr int NQ = pub_words<NC>();
     const int lane = lane_id();
     const bool mine = lane < nin;
     const u32x4 *ptr = lb + (int64_t)(mine ? tile - 1 - lane : tile) * kLbSlot;
     double val[NC];
     uint32_t st;
     {
-        u32x4 r[1][NC];
+        u32x4 r[1][NQ];
         const u32x4 *pp[1] = {ptr};
-        ld_lb<1, NC>(pp, r);
-        st = mine ? pairs_state<NC>(r[0], epoch) : (uint32_t)kStateAgg;
+        ld_lb<1, NQ>(pp, r);
+        st = mine ? pairs_state<NQ>(r[0], epoch) : (uint32_t)kStateAgg;
+        pub_unpack<NC>(r[0], val);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) val[c] = mine ? pair_value(r[0][c]) : 0.0;
+        for (int c = 0; c < NC; ++c) val[c] = mine ? val[c] : 0.0;
     }
     uint64_t m = __ballot(st == kStateInc);
     int fl = m ? __ffsll((unsigned long long)m) - 1 : kWave;
@@ -174,11 +183,10 @@ __device__ bool group_members(const u32x4 *lb, int32_t tile, int32_t nin, uint64
         const bool pend = lane <= fl && st == 0u;
         if (!__any(pend)) break;
         if (pend) {
-            u32x4 r[NC];
-            ld_pairs<NC>(ptr, r);
-            st = pairs_state<NC>(r, epoch);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) val[c] = pair_value(r[c]);
+            u32x4 r[NQ];
+            ld_pairs<NQ>(ptr, r);
+            st = pairs_state<NQ>(r, epoch);
+            pub_unpack<NC>(r, val);
         }
         if (++spins > kSpinLimit) {
             if (lane == 0)

@@ -51,88 +51,6 @@ using namespace dev;
 #endif
 constexpr int kSwGroup = SS_SW_GROUP;
 
-// A publication of N doubles packs three doubles into two 16-byte words,
-// each word carrying the low 32 bits of the round's tag in its last dword:
-// every word is written and read with one 16-byte access, so a reader that
-// sees the tag in all of them has a consistent snapshot, and the words per
-// publication drop from N to about 2N/3 (the gather reads every segment's
-// publication each round; its time goes with the bytes).  Tags repeat only
-// after 2^31 rounds, long after a slot was last overwritten.
-template <int N>
-constexpr int pub_words()
-{
-    return (N / 3) * 2 + (N % 3 == 0 ? 0 : (N % 3 == 1 ? 1 : 2));
-}
-
-__device__ __forceinline__ uint32_t lo32(double v)
-{
-    return (uint32_t)(unsigned long long)__double_as_longlong(v);
-}
-__device__ __forceinline__ uint32_t hi32(double v)
-{
-    return (uint32_t)((unsigned long long)__double_as_longlong(v) >> 32);
-}
-__device__ __forceinline__ double from32(uint32_t lo, uint32_t hi)
-{
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-template <int N>
-__device__ __forceinline__ void pub_pack(const double (&v)[N], uint32_t tag,
-                                         u32x4 (&q)[pub_words<N>()])
-{
-    constexpr int G = N / 3, R = N % 3;
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const double d0 = v[3 * g], d1 = v[3 * g + 1], d2 = v[3 * g + 2];
-        q[2 * g].x = lo32(d0);
-        q[2 * g].y = hi32(d0);
-        q[2 * g].z = lo32(d1);
-        q[2 * g].w = tag;
-        q[2 * g + 1].x = hi32(d1);
-        q[2 * g + 1].y = lo32(d2);
-        q[2 * g + 1].z = hi32(d2);
-        q[2 * g + 1].w = tag;
-    }
-    if constexpr (R >= 1) {
-        const double d0 = v[3 * G];
-        const double d1 = R == 2 ? v[3 * G + (R == 2 ? 1 : 0)] : 0.0;
-        q[2 * G].x = lo32(d0);
-        q[2 * G].y = hi32(d0);
-        q[2 * G].z = lo32(d1);
-        q[2 * G].w = tag;
-        if constexpr (R == 2) {
-            q[2 * G + 1].x = hi32(d1);
-            q[2 * G + 1].y = 0u;
-            q[2 * G + 1].z = 0u;
-            q[2 * G + 1].w = tag;
-        }
-    }
-}
-
-template <int N>
-__device__ __forceinline__ void pub_unpack(const u32x4 (&q)[pub_words<N>()], double (&v)[N])
-{
-    constexpr int G = N / 3, R = N % 3;
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        v[3 * g] = from32(q[2 * g].x, q[2 * g].y);
-        v[3 * g + 1] = from32(q[2 * g].z, q[2 * g + 1].x);
-        v[3 * g + 2] = from32(q[2 * g + 1].y, q[2 * g + 1].z);
-    }
-    if constexpr (R >= 1) v[3 * G] = from32(q[2 * G].x, q[2 * G].y);
-    if constexpr (R == 2) v[3 * G + 1] = from32(q[2 * G].z, q[2 * G + 1].x);
-}
-
-template <int M>
-__device__ __forceinline__ bool pub_tagged(const u32x4 (&q)[M], uint32_t tag)
-{
-    bool ok = true;
-#pragma unroll
-    for (int c = 0; c < M; ++c) ok = ok && q[c].w == tag;
-    return ok;
-}
-
 struct SweepArgs {
     int64_t n;
     int32_t j_begin;
