@@ -245,15 +245,31 @@ __device__ __forceinline__ int32_t lds_slot(int32_t r)
     return (q * C + rem % C) * BLOCK + rem / C;
 }
 
+// Clears a tile's LDS flags and (VALS) its values of column j, so that a
+// position absent from the column reads x = 0.
+template <int BLOCK, int TILE, bool VALS>
+__device__ __forceinline__ void clear_tile_lds(uint8_t *s_flag, double *s_xv)
+{
+    const int tid = threadIdx.x;
+    uint32_t *f32 = reinterpret_cast<uint32_t *>(s_flag);
+    for (int i = tid; i < TILE / 4; i += BLOCK) f32[i] = 0u;
+    if constexpr (VALS) {
+        double2 *x2 = reinterpret_cast<double2 *>(s_xv);
+        for (int i = tid; i < TILE / 2; i += BLOCK) x2[i] = make_double2(0.0, 0.0);
+    }
+}
+
 // Stages one tile (positions [t0, t0+cnt)): e (patched by the pending step
 // of column jprev, which is also written back to eta and e), the weights w
 // (Fine-Gray) and the event counts d (one byte each, element i in byte i%4
-// of word i/4) go to registers; of column j only a bit per element stays in
-// a register (returned: bit i for element i) and, with VALS, the value sits
-// in LDS at s_xv[i * BLOCK + tid] (lane-major, free of bank conflicts).  All
-// independent loads are issued together; the sparse column and the patch
-// travel through LDS flag bytes (position order).  s_flag must be zero and
-// visible on entry; ends after one workgroup barrier.
+// of word i/4) go to registers.  Column j: a 0/1 column leaves a bit per
+// element in a register (returned: bit i for element i); a valued column
+// leaves its values in LDS at s_xv[i * BLOCK + tid] (lane-major, free of
+// bank conflicts; 0 where the column has no entry, and the returned bits
+// carry nothing).  All independent loads are issued together; the sparse
+// 0/1 column and the patch travel through LDS flag bytes (position order).
+// s_flag and s_xv must be zero and visible on entry; ends after one
+// workgroup barrier.
 // NEXT: the 0/1 column jnext also goes to the flags; its bits are returned
 // in *nbits.
 template <int BLOCK, int IPT, bool WANT_W, bool VALS, bool PREV, bool WANT_D,
@@ -366,7 +382,7 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
         for (int32_t o = cj.lo + tid; o < cj.hi; o += BLOCK) {
             const int32_t r = (int32_t)(a.col.rows[cj.cb + o] - t0);
             if (VALS) s_xv[lds_slot<BLOCK, IPT>(r)] = a.col.vals[cj.cb + o];
-            lds_flag_or(s_flag, r, kFlagX);
+            else lds_flag_or(s_flag, r, kFlagX);
         }
     }
     if (NEXT) {
@@ -414,9 +430,8 @@ __device__ __forceinline__ uint32_t stage_tile(const FusedCall &a, int64_t t0, i
 template <int BLOCK, bool VALS>
 __device__ __forceinline__ double x_at(uint32_t xbits, int i, const double *s_xv)
 {
-    const bool nz = (xbits >> i) & 1u;
-    if (VALS) return nz ? s_xv[i * BLOCK + threadIdx.x] : 0.0;
-    return nz ? 1.0 : 0.0;
+    if (VALS) return s_xv[i * BLOCK + threadIdx.x];  // 0 where absent
+    return ((xbits >> i) & 1u) ? 1.0 : 0.0;
 }
 
 // The tuple of Sec. 2.7 at one position, added to running sums S.  Cox:
@@ -437,9 +452,9 @@ struct Tuple {
     __device__ static __forceinline__ void add(AT (&S)[NX], AT e, uint32_t xbits, int i,
                                                const double *s_xv, double w)
     {
-        const bool nz = (xbits >> i) & 1u;
         if constexpr (VALS) {
-            const AT x = nz ? (AT)s_xv[i * BLOCK + threadIdx.x] : (AT)0;
+            // positions absent from the column hold x = 0 in LDS
+            const AT x = (AT)s_xv[i * BLOCK + threadIdx.x];
             const AT ex = e * x;
             S[0] += e;
             S[1] += ex;
@@ -452,6 +467,7 @@ struct Tuple {
                 S[5] += exw * x;
             }
         } else {
+            const bool nz = (xbits >> i) & 1u;
             S[0] += e;
             S[1] += nz ? e : (AT)0;
             if constexpr (FG) {
@@ -492,7 +508,7 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     constexpr int NX = Tx::NX;  // distinct tuple components
 
     __shared__ __attribute__((aligned(16))) uint8_t s_flag[TILE];
-    __shared__ double s_xv[VALS ? TILE : 1];
+    __shared__ __attribute__((aligned(16))) double s_xv[VALS ? TILE : 1];
     // G(Y) of the tile (Fine-Gray) and the patched e of the pending update
     // (PREV) share one array: the patch is consumed during staging, and with
     // PREV the copy of G is only started after that
@@ -505,7 +521,6 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
     __shared__ double s_red[NW * NR + NR];
     __shared__ double s_tsum[NR];
     __shared__ double s_fgw[2];
-    __shared__ uint64_t s_epoch;
 
     const int tid = threadIdx.x;
     const int lane = lane_id();
@@ -513,19 +528,17 @@ __global__ __launch_bounds__(BLOCK) void k_fused(FusedCall a, WsView ws, int64_t
 
     // ---- 1. the tile is the workgroup index: workgroups start in index
     // order on each XCD, so every predecessor a tile waits for has started
-    // (the waits are bounded all the same); clear the LDS flags meanwhile
+    // (the waits are bounded all the same); clear the LDS flags and values
+    // meanwhile.  Each wave reads the launch's epoch itself, so no barrier
+    // waits on that load and the tile's data loads go out at once; the epoch
+    // changes only at the end of the launch's last tile, after every tile has
+    // used it.
     SS_TRACE(ws, (int64_t)blockIdx.x, 0);
-    if (tid == 0) {
-        s_epoch = ld_relaxed_u64(&ws.hdr->epoch);
-        if (a.clear_error && blockIdx.x == 0) st_relaxed_u32(&ws.hdr->error, 0u);
-    }
-    {
-        uint32_t *f32 = reinterpret_cast<uint32_t *>(s_flag);
-        for (int i = tid; i < TILE / 4; i += BLOCK) f32[i] = 0u;
-    }
+    const uint64_t epoch = ld_relaxed_u64(&ws.hdr->epoch);
+    if (tid == 0 && a.clear_error && blockIdx.x == 0) st_relaxed_u32(&ws.hdr->error, 0u);
+    clear_tile_lds<BLOCK, TILE, VALS>(s_flag, s_xv);
     __syncthreads();
     const int64_t tile = blockIdx.x;
-    const uint64_t epoch = s_epoch;
     const int64_t t0 = tile * TILE;
     const int64_t nchunk = a.col.nchunk1 - 1;
     const int64_t chunk0 = t0 / SS_CHUNK;
@@ -836,22 +849,16 @@ __global__ __launch_bounds__(BLOCK) void k_fg_totals(FusedCall a, WsView ws,
     constexpr int TILE = BLOCK * IPT;
     constexpr int NW = BLOCK / kWave;
     __shared__ __attribute__((aligned(16))) uint8_t s_flag[TILE];
-    __shared__ double s_xv[VALS ? TILE : 1];
+    __shared__ __attribute__((aligned(16))) double s_xv[VALS ? TILE : 1];
     __shared__ double s_ep[PREV ? TILE : 1];
     __shared__ double s_red[NW * 4];
     __shared__ double s_tsum[3];
-    __shared__ uint64_t s_epoch;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        s_epoch = ld_relaxed_u64(&ws.hdr->fg_epoch);
-        if (a.clear_error && blockIdx.x == 0) st_relaxed_u32(&ws.hdr->error, 0u);
-    }
-    {
-        uint32_t *f32 = reinterpret_cast<uint32_t *>(s_flag);
-        for (int i = tid; i < TILE / 4; i += BLOCK) f32[i] = 0u;
-    }
+    // every wave reads the epoch itself (see k_fused)
+    const uint64_t epoch = ld_relaxed_u64(&ws.hdr->fg_epoch);
+    if (tid == 0 && a.clear_error && blockIdx.x == 0) st_relaxed_u32(&ws.hdr->error, 0u);
+    clear_tile_lds<BLOCK, TILE, VALS>(s_flag, s_xv);
     __syncthreads();
-    const uint64_t epoch = s_epoch;
     const uint64_t tag = (epoch << 1) | 1u;
     const int64_t tile = blockIdx.x;
     const int64_t t0 = tile * TILE;
@@ -971,7 +978,7 @@ bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v)
     v->hdr = (WsHeader *)p;
     off = sizeof(WsHeader);
     v->lb = take(16 * 8 * (size_t)tiles);
-    v->glb = take(16 * 8 * (size_t)groups);
+    v->glb = take(16 * 8 * (size_t)(ceil_div(tiles, kLbGroup) + 1));
     v->part = take(16 * 8 * (size_t)tiles);
     v->fg_part = take(16 * 4 * (size_t)tiles);
     v->gpart = take(16 * 8 * (size_t)groups);

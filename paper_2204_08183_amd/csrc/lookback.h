@@ -39,10 +39,6 @@ namespace dev {
 // anyone, and a group's aggregate waits only on its members, so every wait
 // ends; it is bounded all the same.
 constexpr int kLbSlot = 8;     // pairs per tile or group slot (128 bytes)
-#ifndef SS_LB_GROUP
-#define SS_LB_GROUP 64
-#endif
-constexpr int kLbGroup = SS_LB_GROUP;   // tiles per look-back group
 
 // The NC values packed into pub_words<NC>() words (ss_device.h) under the
 // low 32 bits of tag; lane q of the calling wave stores word q.

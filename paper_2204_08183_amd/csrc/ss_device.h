@@ -128,10 +128,13 @@ __device__ __forceinline__ void block_sum(double (&x)[NC], double *s_red)
 // the integer k, so a thread takes a single logarithm at the end.  f^d is
 // formed by binary powering with the product renormalised after every
 // multiplication (d = 1, almost every event, is one multiplication); m
-// stays in [1/2, 1) between calls.
+// stays in [1/2, 1) between calls.  The exponents of add01 calls gather in
+// a 32-bit counter that renorm_all folds into k (at most 32 calls of
+// |e| <= 1100 in between).
 struct LogSum {
     double m = 1.0;
     int64_t k = 0;
+    int32_t k01 = 0;
     __device__ __forceinline__ void renorm(double &x, int64_t &kx)
     {
         kx += __builtin_amdgcn_frexp_exp(x);
@@ -167,12 +170,17 @@ struct LogSum {
         const double f = __builtin_amdgcn_frexp_mant(s);
         const int e = __builtin_amdgcn_frexp_exp(s);
         m *= d ? f : 1.0;
-        k += d ? e : 0;
+        k01 += d ? e : 0;
     }
-    __device__ __forceinline__ void renorm_all() { renorm(m, k); }
+    __device__ __forceinline__ void renorm_all()
+    {
+        k += k01;
+        k01 = 0;
+        renorm(m, k);
+    }
     __device__ __forceinline__ double value() const
     {
-        return (double)k * 0.69314718055994530942 + log(m);
+        return (double)(k + k01) * 0.69314718055994530942 + log(m);
     }
 };
 
@@ -214,14 +222,24 @@ struct ColTile {
     int32_t hi;
 };
 
+// The column index arrays do not change while a kernel runs, so they are
+// read through the constant address space: with uniform indices these are
+// scalar loads, which count on their own counter, and vector loads issued
+// around them (a tile's data) never wait for them or they for those.
+template <typename T>
+__device__ __forceinline__ T ld_const(const T *p)
+{
+    return *(const __attribute__((address_space(4))) T *)(p);
+}
+
 __device__ __forceinline__ ColTile col_tile(const Column &col, int32_t j, int64_t chunk0,
                                             int64_t chunk1)
 {
     ColTile ct;
-    ct.cb = col.col_ptr[j];
+    ct.cb = ld_const(col.col_ptr + j);
     const int32_t *cp = col.chunk_ptr + (int64_t)j * col.nchunk1;
-    ct.lo = cp[chunk0];
-    ct.hi = cp[chunk1];
+    ct.lo = ld_const(cp + chunk0);
+    ct.hi = ld_const(cp + chunk1);
     return ct;
 }
 

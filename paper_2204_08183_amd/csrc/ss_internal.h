@@ -114,6 +114,14 @@ constexpr uint64_t kStateInc = 2;
 // Tiles per group of the two-level reduction of the per-tile partial sums.
 constexpr int kGroup = 64;
 
+// Tiles per group of the two-level look-back (at most 64: a group's last
+// tile sums its other members with one lane each).
+#ifndef SS_LB_GROUP
+#define SS_LB_GROUP 64
+#endif
+constexpr int kLbGroup = SS_LB_GROUP;
+static_assert(kLbGroup >= 2 && kLbGroup <= 64, "look-back groups of 2 to 64 tiles");
+
 // Upper bound on the number of workgroups (segments) of one persistent sweep.
 constexpr int kMaxSweepBlocks = 512;
 
@@ -154,10 +162,11 @@ constexpr size_t fused_ws_bytes(int64_t n)
 {
     const int64_t tiles = ceil_div(n, SS_CHUNK) + 1;
     const int64_t groups = ceil_div(tiles, kGroup) + 1;
+    const int64_t lb_groups = ceil_div(tiles, kLbGroup) + 1;
     const int64_t npub = tiles > 2 * kMaxSweepBlocks ? tiles : 2 * kMaxSweepBlocks;
     size_t b = sizeof(WsHeader);
     b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // lb
-    b = align_up(b + 16 * 8 * (size_t)groups, 256);  // glb
+    b = align_up(b + 16 * 8 * (size_t)lb_groups, 256);  // glb
     b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // part
     b = align_up(b + 16 * 4 * (size_t)tiles, 256);   // fg_part
     b = align_up(b + 16 * 8 * (size_t)groups, 256);  // gpart
