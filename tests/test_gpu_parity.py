@@ -139,6 +139,7 @@ GH_CASES = [
     (5000, 3, 19, 0, 0.05, False, "censored", 0.0),
     (5000, 3, 20, 0, 0.05, True, "events", 0.0),
     (9000, 3, 21, 0, 1.0, False, None, 0.0),      # dense column
+    (70001, 3, 26, 30, 1.0, True, None, 0.0),     # dense valued, ragged last tile
     (9000, 3, 22, 0, 0.05, False, None, 600.0),   # large eta, FP64 range
     (100000, 3, 23, 50, 0.05, True, None, 0.0),
 ]
