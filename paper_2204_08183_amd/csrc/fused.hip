@@ -1052,7 +1052,7 @@ bool fused_ws_view(void *ws, size_t ws_bytes, int64_t n, WsView *v)
     v->sw_part = take(16 * 4 * (size_t)tiles);
     v->sw_step = take(16 * (size_t)tiles);
     v->sw_pre = take(16 * 8 * (size_t)tiles);
-    v->sw_pub = take(16 * 16 * (size_t)std::max<int64_t>(tiles, 2 * kMaxSweepBlocks));
+    v->sw_pub = take(16 * (size_t)kSwPubWords);
     v->max_tiles = tiles;
     return true;
 }

@@ -90,11 +90,12 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 // written and read with one 16-byte agent-scope access (ss_device.h).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// Layout of the workspace (every region 256-byte aligned), T = max_tiles
-// and U = ceil(T / kGroup) + 1 tile groups:
-//   WsHeader | lb[T][8] | glb[U][8] | part[T][8] | fg_part[T][4] | gpart[U][8] |
+// Layout of the workspace (every region 256-byte aligned), T = max_tiles,
+// U = ceil(T / kGroup) + 1 tile groups and V = ceil(T / kLbGroup) + 1
+// look-back groups:
+//   WsHeader | lb[T][8] | glb[V][8] | part[T][8] | fg_part[T][4] | gpart[U][8] |
 //   fg_gpart[U][4] | sw_agg[T][8] | sw_part[T][4] | sw_step[T] |
-//   sw_pre[T][8] | sw_pub[max(T, 2 kMaxSweepBlocks)][16]
+//   sw_pre[T][8] | sw_pub[kPubCopies][2][kMaxSweepBlocks][kPubSlotWords]
 struct alignas(256) WsHeader {
     uint64_t epoch;       // number of completed fused launches
     uint64_t fg_epoch;    // number of completed Fine-Gray totals passes
@@ -125,6 +126,18 @@ static_assert(kLbGroup >= 2 && kLbGroup <= 64, "look-back groups of 2 to 64 tile
 // Upper bound on the number of workgroups (segments) of one persistent sweep.
 constexpr int kMaxSweepBlocks = 512;
 
+// Publications of the one-exchange persistent sweep: up to kPubCopies
+// copies of every segment's publication, by round parity (16-byte words, at
+// most kPubSlotWords of them), each copy in an area of its own; every
+// workgroup reads one copy, so the all-to-all gather spreads over that
+// many times as many memory lines.
+#ifndef SS_PUB_COPIES
+#define SS_PUB_COPIES 8
+#endif
+constexpr int kPubCopies = SS_PUB_COPIES;
+constexpr int kPubSlotWords = 16;  // 256 bytes: ld_pairs2 reads two neighbouring slots
+constexpr int64_t kSwPubWords = 2 * (int64_t)kPubCopies * kMaxSweepBlocks * kPubSlotWords;
+
 // Upper bound on polls of one bounded wait before it gives up (each poll is
 // an uncached load plus a short sleep, so this is on the order of a second).
 constexpr uint32_t kSpinLimit = 1u << 20;
@@ -142,7 +155,7 @@ struct WsView {
     u32x4 *sw_part;   // [max_tiles][4]
     u32x4 *sw_step;   // [max_tiles]
     u32x4 *sw_pre;    // [max_tiles][8]
-    u32x4 *sw_pub;    // [max(max_tiles, 2 kMaxSweepBlocks)][16]
+    u32x4 *sw_pub;    // [kPubCopies][2][kMaxSweepBlocks][kPubSlotWords]
     int64_t max_tiles;
 };
 
@@ -151,8 +164,7 @@ struct WsView {
 // 8 slots per tile (fused kernels) or 8 x 8 per workgroup (sweeps).
 __device__ __forceinline__ uint64_t *trace_base(const WsView &ws)
 {
-    const int64_t np = ws.max_tiles > 2 * kMaxSweepBlocks ? ws.max_tiles : 2 * kMaxSweepBlocks;
-    return reinterpret_cast<uint64_t *>(ws.sw_pub + 16 * np);
+    return reinterpret_cast<uint64_t *>(ws.sw_pub + kSwPubWords);
 }
 #endif
 
@@ -163,7 +175,6 @@ constexpr size_t fused_ws_bytes(int64_t n)
     const int64_t tiles = ceil_div(n, SS_CHUNK) + 1;
     const int64_t groups = ceil_div(tiles, kGroup) + 1;
     const int64_t lb_groups = ceil_div(tiles, kLbGroup) + 1;
-    const int64_t npub = tiles > 2 * kMaxSweepBlocks ? tiles : 2 * kMaxSweepBlocks;
     size_t b = sizeof(WsHeader);
     b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // lb
     b = align_up(b + 16 * 8 * (size_t)lb_groups, 256);  // glb
@@ -175,7 +186,7 @@ constexpr size_t fused_ws_bytes(int64_t n)
     b = align_up(b + 16 * 4 * (size_t)tiles, 256);   // sw_part
     b = align_up(b + 16 * (size_t)tiles, 256);       // sw_step
     b = align_up(b + 16 * 8 * (size_t)tiles, 256);   // sw_pre
-    b = align_up(b + 16 * 16 * (size_t)npub, 256);   // sw_pub
+    b = align_up(b + 16 * (size_t)kSwPubWords, 256);   // sw_pub
 #ifdef SS_TRACE_TIMES
     b = align_up(b + sizeof(uint64_t) * 64 * (size_t)tiles, 256);
 #endif

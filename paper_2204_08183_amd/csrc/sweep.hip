@@ -533,6 +533,13 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
     constexpr int P0 = LOG ? 3 : 2;
     constexpr int NPUB = P0 + 2 * NT;  // partial sums, A, D
     constexpr int NQ = pub_words<NPUB>();  // 16-byte words of a publication
+    // Fine-Gray publications (8 words) go out in kPubCopies copies, one
+    // word per lane of wave 0; the Cox ones (4-5 words) in one copy stored
+    // by thread 0, which measured faster for them (5.88 against 5.92 ms per
+    // 1000 coordinates at N = 1e6; Fine-Gray 11.5 -> 10.4 ms with copies)
+    constexpr int NCOPY = FG ? kPubCopies : 1;
+    static_assert(NQ <= kPubSlotWords && NQ * NCOPY <= kWave,
+                  "one wave stores every copy of a publication");
     // block sums after a gather: partials (P0), A and D before this
     // segment (2 NT), and for Fine-Gray the totals of the weighted A and D
     // (4)
@@ -633,11 +640,15 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
 #pragma unroll
         for (int q = 0; q < IPT / 4; ++q) f32[q] &= keep;
     };
-    // Publication slot of segment q in round r: two sets by parity.
-    auto pub_slot = [&](uint64_t r, int64_t q) {
-        return a.ws.sw_pub + ((int64_t)(r & 1u) * kMaxSweepBlocks + q) * 16;
+    // Publication slot of segment q in round r, copy c: two sets by parity
+    // inside each copy's area.  Workgroup b reads copy b mod NCOPY.
+    auto pub_slot = [&](uint64_t r, int c, int64_t q) {
+        return a.ws.sw_pub +
+               (((int64_t)c * 2 + (r & 1u)) * kMaxSweepBlocks + q) * kPubSlotWords;
     };
-    // Block sums of NPUB values, published by thread 0 as pairs.
+    const int my_copy = (int)(b % NCOPY);
+    // Block sums of NPUB values, published by wave 0 (Fine-Gray: lane l
+    // stores word l mod NQ of copy l / NQ) or by thread 0 (Cox).
     auto publish = [&](double (&v)[NPUB], uint64_t r, uint64_t tag) {
 #pragma unroll
         for (int c = 0; c < NPUB; ++c) {
@@ -645,8 +656,22 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
             if (lane == 0) s_wred[w][c] = t;
         }
         __syncthreads();
-        if (tid == 0) {
-            u32x4 *dst = pub_slot(r, b);
+        if constexpr (!FG) {
+            if (tid == 0) {
+                u32x4 *dst = pub_slot(r, 0, b);
+                double t[NPUB];
+#pragma unroll
+                for (int c = 0; c < NPUB; ++c) {
+                    t[c] = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) t[c] += s_wred[q][c];
+                }
+                u32x4 wd[NQ];
+                pub_pack<NPUB>(t, (uint32_t)tag, wd);
+#pragma unroll
+                for (int c = 0; c < NQ; ++c) st_quad(dst + c, wd[c]);
+            }
+        } else if (w == 0) {
             double t[NPUB];
 #pragma unroll
             for (int c = 0; c < NPUB; ++c) {
@@ -656,8 +681,17 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
             }
             u32x4 wd[NQ];
             pub_pack<NPUB>(t, (uint32_t)tag, wd);
+            const int word = lane % NQ;
+            // (an empty asm statement per word: a select chain over the
+            // array itself is folded into an indexed load from scratch)
+            u32x4 x = wd[0];
 #pragma unroll
-            for (int c = 0; c < NQ; ++c) st_quad(dst + c, wd[c]);
+            for (int c = 1; c < NQ; ++c) {
+                u32x4 y = wd[c];
+                asm volatile("" : "+v"(y));
+                x = word == c ? y : x;
+            }
+            if (lane < NQ * NCOPY) st_quad(pub_slot(r, lane / NQ, b) + word, x);
         }
     };
     // Reads every segment's publication of round r and forms the sums in a
@@ -677,7 +711,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
             u32x4 r0[NQ], r1[NQ];
             uint32_t spins = 0;
             for (;;) {
-                ld_pairs2<NQ>(pub_slot(r, q0), r0, r1);
+                ld_pairs2<NQ>(pub_slot(r, my_copy, q0), r0, r1);
                 if (pub_tagged<NQ>(r0, (uint32_t)tag) && pub_tagged<NQ>(r1, (uint32_t)tag))
                     break;
                 if (((++spins & 31u) == 0 && ld_relaxed_u32(&hdr->error)) ||
@@ -697,7 +731,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
             u32x4 rr[NQ];
             uint32_t spins = 0;
             for (;;) {
-                ld_pairs<NQ>(pub_slot(r, q0), rr);
+                ld_pairs<NQ>(pub_slot(r, my_copy, q0), rr);
                 if (pub_tagged<NQ>(rr, (uint32_t)tag)) {
                     pub_unpack<NPUB>(rr, v[0]);
                     break;
