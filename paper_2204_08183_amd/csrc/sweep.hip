@@ -50,6 +50,10 @@ using namespace dev;
 #define SS_SW_GROUP 8
 #endif
 constexpr int kSwGroup = SS_SW_GROUP;
+#ifndef SS_SW_FG_GROUP
+#define SS_SW_FG_GROUP 4
+#endif
+constexpr int kSwFgGroup = SS_SW_FG_GROUP;  // the same for Fine-Gray
 
 struct SweepArgs {
     int64_t n;
@@ -900,15 +904,16 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
                 for (int c = 0; c < 2; ++c) R[c] = pre[2 + c] - texcl[2 + c];
             }
             const bool has_next = j + 1 < je;
-            // Cox: S0 and S1 at a group of positions first, then the
-            // transform at all of them at once, masked by the event count:
-            // the reciprocals are independent and overlap (one wave per
-            // SIMD here, nothing else hides their latency; run by run
-            // behind a branch each one waited for the last: 8.08 -> 7.22 ms
-            // per 1000 coordinates at N = 1e6).  Fine-Gray holds too many
-            // registers already: the transform stays at the run ends, one
-            // by one (GT = 1; grouped, 12.8 -> 13.0 ms).
-            constexpr int GT = FG ? 1 : (IPT < kSwGroup ? IPT : kSwGroup);
+            // S0 and S1 at a group of positions first, then the transform
+            // at all of them at once, masked by the event count: the
+            // reciprocals are independent and overlap (one wave per SIMD
+            // here, nothing else hides their latency; run by run behind a
+            // branch each one waited for the last: Cox 8.08 -> 7.22 ms per
+            // 1000 coordinates at N = 1e6).  Fine-Gray, which holds far more
+            // registers, groups kSwFgGroup positions (10.32 -> 10.20 ms at
+            // 4; with an IEEE division instead of the reciprocal, grouping
+            // 8 had measured 12.8 -> 13.0 ms).
+            constexpr int GT = FG ? kSwFgGroup : (IPT < kSwGroup ? IPT : kSwGroup);
 #pragma unroll
             for (int i0 = 0; i0 < IPT; i0 += GT) {
                 double s0v[GT], s1v[GT];
@@ -948,7 +953,20 @@ __global__ __launch_bounds__(BLOCK) void k_sweep1(SweepArgs a)
                 }
                 // indicator design: S2 = S1, so H = G; S0 > 0 everywhere (it
                 // holds e of the position itself or of one before it)
-                if constexpr (FG) {
+                if constexpr (FG && GT > 1) {
+#pragma unroll
+                    for (int u = 0; u < GT; ++u) {
+                        const double Gk = s1v[u] * recip(s0v[u]);
+                        const double dd = (double)dk[i0 + u];  // 0 off the run ends
+                        v[0] = fma(dd, Gk, v[0]);
+                        v[1] = fma(dd, Gk - Gk * Gk, v[1]);
+                    }
+                    if constexpr (LOG) {
+#pragma unroll
+                        for (int u = 0; u < GT; ++u)
+                            if (dk[i0 + u] != 0) v[2] += (double)dk[i0 + u] * log(s0v[u]);
+                    }
+                } else if constexpr (FG) {
                     const int d = dk[i0];
                     if (d != 0) {
                         // hardware estimate and Newton steps, as Cox (an
